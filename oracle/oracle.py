@@ -1,0 +1,148 @@
+"""ctypes binding of the C oracle (test infrastructure only).
+
+The oracle owns nothing: the caller passes numpy byte arrays for each VM's
+arena and for the host pool, and the oracle reads and writes them in place.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CODES = {
+    "OK": 0, "NOT_PRESENT": 1, "RESERVED": 2, "PROT_USER": 3, "PROT_WRITE": 4,
+    "NO_MEMSLOT": 5, "NONCANONICAL": 6, "INVALID": 7,
+}
+RESULT_DTYPE = np.dtype([("bytes_done", "<u8"), ("fault_gva", "<u8"), ("code", "<u4"), ("level", "<u2"),
+                         ("pad", "<u2")])
+FAULT_DTYPE = np.dtype([("req_index", "<u8"), ("fault_gva", "<u8"), ("code", "<u4"), ("level", "<u2"),
+                        ("pad", "<u2")])
+XLAT_DTYPE = np.dtype([("gpa", "<u8"), ("hpa", "<u8"), ("code", "<u4"), ("level", "u1"), ("page_shift", "u1"),
+                       ("vm", "<u2")])
+SLOT_DTYPE = np.dtype([("gpa", "<u8"), ("bytes", "<u8"), ("arena_off", "<u8")])
+XLAT_WRITE = 1
+XLAT_SET_AD = 2
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_libs = {}
+
+
+def _load(path: str | None = None):
+    """Load the oracle library (``path`` lets a test load a deliberately broken build)."""
+    key = path or _LIB
+    if key not in _libs:
+        if path is None and not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(key)
+        vp, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        lib.orc_new.argtypes = [u32, u32]
+        lib.orc_new.restype = vp
+        lib.orc_free.argtypes = [vp]
+        lib.orc_set_vm.argtypes = [vp, u32, vp, u64, vp, u32]
+        lib.orc_set_proc.argtypes = [vp, u32, u32, u64, u32]
+        lib.orc_set_pool.argtypes = [vp, vp, u64]
+        lib.orc_ad_sets.argtypes = [vp]
+        lib.orc_ad_sets.restype = u64
+        lib.orc_translate.argtypes = [vp, u32, vp, u64, u32, vp]
+        lib.orc_copy.argtypes = [vp, vp, vp]
+        lib.orc_copy.restype = ctypes.c_int
+        lib.orc_batch.argtypes = [vp, vp, u64, vp, vp]
+        lib.orc_batch.restype = ctypes.c_int64
+        lib.orc_check_conflicts.argtypes = [vp, vp, u64, vp, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        lib.orc_check_conflicts.restype = ctypes.c_int
+        _libs[key] = lib
+    return _libs[key]
+
+
+class Oracle:
+    """State = arenas (one uint8 array per VM), memslots, processes and a pool.
+
+    ``asid`` values are positions in the process list given at construction.
+    """
+
+    def __init__(self, arenas, slots, procs, pool, lib_path: str | None = None):
+        """arenas: list of uint8 arrays; slots: list of SLOT_DTYPE arrays;
+        procs: list of (vm, cr3, levels); pool: uint8 array."""
+        lib = _load(lib_path)
+        self._lib = lib
+        self.arenas = [np.ascontiguousarray(a) for a in arenas]
+        for a, b in zip(arenas, self.arenas):
+            assert a is b, "arenas must be C-contiguous uint8 arrays (the oracle writes them in place)"
+        self.slots = [np.ascontiguousarray(np.asarray(s, dtype=SLOT_DTYPE)) for s in slots]
+        self.procs = list(procs)
+        self.pool = pool
+        assert pool.dtype == np.uint8 and pool.flags.c_contiguous
+        self._h = lib.orc_new(len(arenas), len(procs))
+        for i, (a, s) in enumerate(zip(self.arenas, self.slots)):
+            assert a.dtype == np.uint8
+            lib.orc_set_vm(self._h, i, a.ctypes.data, a.size, s.ctypes.data, len(s))
+        for i, (vm, cr3, levels) in enumerate(self.procs):
+            lib.orc_set_proc(self._h, i, vm, cr3, levels)
+        lib.orc_set_pool(self._h, pool.ctypes.data, pool.size)
+
+    @classmethod
+    def from_workload(cls, wl, arenas=None, pool=None, lib_path: str | None = None):
+        if arenas is None:
+            arenas = [wl.arena_image(v) for v in range(len(wl.vms))]
+        if pool is None:
+            pool = wl.pool_image()
+        return cls(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], pool,
+                   lib_path=lib_path)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self._lib.orc_free(self._h)
+            self._h = None
+
+    @property
+    def ad_sets(self) -> int:
+        return int(self._lib.orc_ad_sets(self._h))
+
+    def translate(self, asid: int, gvas, flags: int = 0) -> np.ndarray:
+        g = np.ascontiguousarray(np.asarray(gvas, dtype=np.uint64).reshape(-1))
+        out = np.zeros(len(g), XLAT_DTYPE)
+        self._lib.orc_translate(self._h, asid, g.ctypes.data, len(g), flags, out.ctypes.data)
+        return out
+
+    def copy(self, req) -> np.ndarray:
+        r = np.ascontiguousarray(np.asarray(req).reshape(1))
+        res = np.zeros(1, RESULT_DTYPE)
+        rc = self._lib.orc_copy(self._h, r.ctypes.data, res.ctypes.data)
+        if rc != 0:
+            raise ValueError("request names pool bytes outside the pool")
+        return res[0]
+
+    def batch(self, reqs):
+        r = np.ascontiguousarray(reqs)
+        n = len(r)
+        res = np.zeros(n, RESULT_DTYPE)
+        faults = np.zeros(n, FAULT_DTYPE)
+        nf = self._lib.orc_batch(self._h, r.ctypes.data, n, res.ctypes.data, faults.ctypes.data)
+        if nf < 0:
+            raise ValueError("request names pool bytes outside the pool")
+        return res, faults[:nf].copy()
+
+    def check_conflicts(self, reqs, epoch_end=None):
+        """Return None if every epoch is conflict-free, else the offending (i, j)."""
+        r = np.ascontiguousarray(reqs)
+        e = np.ascontiguousarray(np.asarray(epoch_end if epoch_end is not None else [len(r)], np.uint64))
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        rc = self._lib.orc_check_conflicts(self._h, r.ctypes.data, len(r), e.ctypes.data, len(e),
+                                           ctypes.byref(a), ctypes.byref(b))
+        if rc < 0:
+            raise MemoryError
+        return None if rc == 0 else (int(a.value), int(b.value))

@@ -1,0 +1,489 @@
+"""Checks that pin the CPU oracle to facts other than itself.
+
+Each ``check_*`` function returns a list of failure strings (empty = pass) and
+takes an optional ``lib_path`` so the mutation test can run the same checks
+against deliberately broken builds of the oracle and show they fail.
+
+Pins used (none re-types the oracle's own code):
+  * hand-derived x86-64 walks, A/D updates and copies (tests/golden);
+  * encode -> decode: the generator encodes tables from an explicit leaf map
+    and the oracle's walk must reproduce that map for every leaf, and report
+    unmapped addresses at the level where the encoded path ends;
+  * per-byte brute force: every byte of a request translated on its own must
+    give the chunked copy's bytes, bytes_done and fault;
+  * a textbook special case: identity tables with one memslot at arena
+    offset 0 make every successful copy equal to plain memcpy;
+  * invariants: round trips, untouched bytes outside requests, A/D equal to
+    a closed form computed from the encoded map without walking.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+from oracle import CODES, RESULT_DTYPE, Oracle
+from oracle.oracle import SLOT_DTYPE, XLAT_SET_AD, XLAT_WRITE
+from workload import REQ_DTYPE, gen
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "walk_x86_64.json")
+H = lambda s: int(s, 16)  # noqa: E731
+
+
+# ----------------------------------------------------------------- golden --
+def golden_worlds():
+    with open(GOLDEN) as f:
+        return json.load(f)["worlds"]
+
+
+def build_golden(world, lib_path=None, pool_bytes=0x4000):
+    arena = np.zeros(H(world["arena_bytes"]), np.uint8)
+    gen.fill_bytes(arena, 77, 3)
+    for t in world["table_frames_arena_off"]:
+        arena[H(t):H(t) + 4096] = 0
+    for e in world["entries"]:
+        arena[H(e["arena_off"]):H(e["arena_off"]) + 8] = np.frombuffer(
+            H(e["value"]).to_bytes(8, "little"), np.uint8)
+    slots = np.zeros(len(world["slots"]), SLOT_DTYPE)
+    for i, s in enumerate(world["slots"]):
+        slots[i] = (H(s["gpa"]), H(s["bytes"]), H(s["arena_off"]))
+    pool = np.zeros(pool_bytes, np.uint8)
+    gen.fill_bytes(pool, 78, 4)
+    o = Oracle([arena], [slots], [(0, H(world["cr3"]), world["levels"])], pool, lib_path=lib_path)
+    return o, arena, pool
+
+
+def _u64(arena, off):
+    return int.from_bytes(arena[off:off + 8].tobytes(), "little")
+
+
+def check_golden(lib_path=None):
+    fails = []
+    for w in golden_worlds():
+        o, arena, pool = build_golden(w, lib_path)
+        for q in w["queries"]:
+            x = o.translate(0, [H(q["gva"])], XLAT_WRITE if q["write"] else 0)[0]
+            got = (int(x["code"]), int(x["level"]), int(x["gpa"]), int(x["hpa"]), int(x["page_shift"]))
+            exp = (q["code"], q["level"], H(q["gpa"]), H(q["hpa"]), q["shift"])
+            if got != exp:
+                fails.append(f"{w['name']} walk {q['gva']} w={q['write']}: got {got} expected {exp} ({q['why']})")
+        # an invalid process id
+        x = o.translate(5, [0x1000])[0]
+        if int(x["code"]) != CODES["INVALID"]:
+            fails.append(f"{w['name']} invalid asid gave code {int(x['code'])}")
+        if "ad_after_set_ad_write" in w:
+            ad = w["ad_after_set_ad_write"]
+            o, arena, pool = build_golden(w, lib_path)
+            o.translate(0, [H(ad["gva"])], XLAT_WRITE | XLAT_SET_AD)
+            for e in ad["expect"]:
+                if _u64(arena, H(e["arena_off"])) != H(e["value"]):
+                    fails.append(f"{w['name']} A/D at {e['arena_off']}: {hex(_u64(arena, H(e['arena_off'])))}"
+                                 f" expected {e['value']}")
+        for c in w["copies"]:
+            o, arena, pool = build_golden(w, lib_path)
+            a0, p0 = arena.copy(), pool.copy()
+            req = np.zeros(1, REQ_DTYPE)
+            req[0] = (H(c["gva"]), 0, H(c["len"]), 0, c["dir"], (0, 0, 0), 0)
+            r = o.copy(req[0])
+            got = (int(r["code"]), int(r["level"]), int(r["bytes_done"]), int(r["fault_gva"]))
+            exp = (c["code"], c["level"], H(c["bytes_done"]), H(c["fault_gva"]))
+            if got != exp:
+                fails.append(f"{w['name']} copy {c['gva']}+{c['len']} dir {c['dir']}: got {got} expected {exp}")
+            a_exp, p_exp = a0.copy(), p0.copy()
+            for pc in c["pieces"]:
+                ao, po, n = H(pc["arena_off"]), H(pc["pool_off"]), H(pc["len"])
+                if c["dir"] == 0:
+                    p_exp[po:po + n] = a0[ao:ao + n]
+                else:
+                    a_exp[ao:ao + n] = p0[po:po + n]
+            for e in c["ad"]:
+                a_exp[H(e["arena_off"]):H(e["arena_off"]) + 8] = np.frombuffer(
+                    H(e["value"]).to_bytes(8, "little"), np.uint8)
+            if not np.array_equal(arena, a_exp):
+                bad = np.nonzero(arena != a_exp)[0]
+                fails.append(f"{w['name']} copy {c['gva']} dir {c['dir']}: {len(bad)} arena bytes differ, first {hex(bad[0])}")
+            if not np.array_equal(pool, p_exp):
+                bad = np.nonzero(pool != p_exp)[0]
+                fails.append(f"{w['name']} copy {c['gva']} dir {c['dir']}: {len(bad)} pool bytes differ, first {hex(bad[0])}")
+    return fails
+
+
+# ------------------------------------------------------- encode -> decode --
+def _leaf_lookup(p):
+    """Map page-granular keys to leaf indices using the encoder's own map."""
+    tabs = {}
+    for L in (1, 2, 3):
+        m = np.nonzero(p.leaf_level == L)[0]
+        keys = p.leaf_va[m] >> np.uint64(12 + 9 * (L - 1))
+        order = np.argsort(keys)
+        tabs[L] = (keys[order], m[order])
+    return tabs
+
+
+def find_leaf(p, tabs, va):
+    """Index of the leaf covering each va, -1 if none (from the encoded map)."""
+    va = np.asarray(va, np.uint64)
+    out = np.full(len(va), -1, np.int64)
+    for L in (1, 2, 3):
+        keys, idx = tabs[L]
+        if len(keys) == 0:
+            continue
+        k = va >> np.uint64(12 + 9 * (L - 1))
+        pos = np.minimum(np.searchsorted(keys, k), len(keys) - 1)
+        hit = keys[pos] == k
+        out = np.where(hit & (out < 0), idx[pos], out)
+    return out
+
+
+def expected_unmapped_level(p, va):
+    """Level of the deepest encoded table on the path of an unmapped address."""
+    va = np.asarray(va, np.uint64)
+    lvl = np.full(len(va), p.levels, np.int64)
+    for L in range(p.levels - 1, 0, -1):
+        ids = p.tables[L][0]
+        k = va >> np.uint64(12 + 9 * L)
+        pos = np.minimum(np.searchsorted(ids, k), max(len(ids) - 1, 0))
+        has = (ids[pos] == k) if len(ids) else np.zeros(len(va), bool)
+        lvl = np.where(has, L, lvl)
+    return lvl
+
+
+def check_roundtrip(wl, lib_path=None, per_proc=20000, seed=5):
+    fails = []
+    o = Oracle.from_workload(wl, lib_path=lib_path)
+    rng = np.random.default_rng(seed)
+    for p in wl.procs:
+        n = len(p.leaf_va)
+        sel = rng.choice(n, min(n, per_proc), replace=False) if n > per_proc else np.arange(n)
+        size = np.uint64(1) << (np.uint64(12) + np.uint64(9) * (p.leaf_level[sel].astype(np.uint64) - np.uint64(1)))
+        off = (rng.integers(0, 2**62, len(sel), dtype=np.uint64) % size)
+        va = p.leaf_va[sel] + off
+        x = o.translate(p.asid, va)
+        pres = p.leaf_present[sel]
+        exp_gpa = p.leaf_frame[sel] + off
+        ok_codes = x["code"][pres]
+        if np.any(ok_codes != 0):
+            i = np.nonzero(ok_codes != 0)[0][0]
+            fails.append(f"asid {p.asid}: mapped va {hex(int(va[pres][i]))} gave code {int(ok_codes[i])}")
+            continue
+        if np.any(x["gpa"][pres] != exp_gpa[pres]):
+            i = np.nonzero(x["gpa"][pres] != exp_gpa[pres])[0][0]
+            fails.append(f"asid {p.asid}: va {hex(int(va[pres][i]))} gpa {hex(int(x['gpa'][pres][i]))} "
+                         f"expected {hex(int(exp_gpa[pres][i]))}")
+            continue
+        exp_hpa = gen.gpa_to_arena(wl.vms[p.vm].slots, exp_gpa[pres])
+        if np.any(x["hpa"][pres].astype(np.int64) != exp_hpa):
+            fails.append(f"asid {p.asid}: hpa differs from the memslot layout")
+        if np.any(x["page_shift"][pres] != (12 + 9 * (p.leaf_level[sel][pres].astype(np.int64) - 1))):
+            fails.append(f"asid {p.asid}: page_shift differs from the encoded leaf size")
+        npres = ~pres
+        if np.any(x["code"][npres] != CODES["NOT_PRESENT"]) or \
+                np.any(x["level"][npres] != p.leaf_level[sel][npres]):
+            fails.append(f"asid {p.asid}: not-present leaves not reported at their own level")
+        # unmapped addresses: random user addresses that no leaf covers
+        lim = 1 << (47 if p.levels == 4 else 56)
+        cand = rng.integers(0, lim, 4000, dtype=np.uint64)
+        # plus addresses just past each VMA (share upper tables with mapped ones)
+        cand = np.concatenate([cand, p.vmas[:, 0] + p.vmas[:, 1], p.vmas[:, 0] - np.uint64(4096)])
+        cand = cand[find_leaf(p, _leaf_lookup(p), cand) < 0]
+        xu = o.translate(p.asid, cand)
+        if np.any(xu["code"] != CODES["NOT_PRESENT"]):
+            fails.append(f"asid {p.asid}: an unmapped address did not fault NOT_PRESENT")
+        elif np.any(xu["level"].astype(np.int64) != expected_unmapped_level(p, cand)):
+            fails.append(f"asid {p.asid}: unmapped address fault level differs from the encoded path")
+    return fails
+
+
+# ---------------------------------------------------------- brute force --
+def check_bruteforce(wl, lib_path=None, max_requests=None):
+    """Per-byte translation vs the chunked copy, on a fresh oracle state."""
+    fails = []
+    o = Oracle.from_workload(wl, lib_path=lib_path)
+    a0 = [a.copy() for a in o.arenas]
+    p0 = o.pool.copy()
+    reqs = wl.requests if max_requests is None else wl.requests[:max_requests]
+    res, _ = o.batch(reqs)
+    # expected, request by request in order on a second state
+    o2 = Oracle([a.copy() for a in a0], [v.slots for v in wl.vms],
+                [(p.vm, p.cr3, p.levels) for p in wl.procs], p0.copy(), lib_path=lib_path)
+    for i, r in enumerate(reqs):
+        n = int(r["len"])
+        gva = int(r["gva"])
+        to_guest = int(r["dir"]) == 1
+        if n == 0:
+            continue
+        b = np.arange(n, dtype=np.uint64) + np.uint64(gva)
+        x = o2.translate(int(r["asid"]), b, XLAT_WRITE if to_guest else 0)
+        bad = np.nonzero(x["code"] != 0)[0]
+        done = int(bad[0]) if len(bad) else n
+        exp = (done, gva + done if len(bad) else 0, int(x["code"][done]) if len(bad) else 0,
+               int(x["level"][done]) if len(bad) else 0)
+        got = (int(res[i]["bytes_done"]), int(res[i]["fault_gva"]), int(res[i]["code"]), int(res[i]["level"]))
+        if got != exp:
+            fails.append(f"request {i}: chunked {got} vs per-byte {exp}")
+            continue
+        ar = o2.arenas[wl.procs[int(r["asid"])].vm]
+        hp = x["hpa"][:done].astype(np.int64)
+        host = int(r["host"])
+        if to_guest:
+            ar[hp] = o2.pool[host:host + done]
+        else:
+            o2.pool[host:host + done] = ar[hp]
+        # A/D: set through a walk of the first copied byte of every copied page
+        if done:
+            pg = np.unique(b[:done] >> np.uint64(12))
+            firsts = np.maximum(pg << np.uint64(12), np.uint64(gva))
+            o2.translate(int(r["asid"]), firsts, (XLAT_WRITE if to_guest else 0) | XLAT_SET_AD)
+    for v in range(len(wl.vms)):
+        if not np.array_equal(o.arenas[v], o2.arenas[v]):
+            fails.append(f"vm {v}: arena bytes differ between chunked and per-byte application")
+    if not np.array_equal(o.pool, o2.pool):
+        fails.append("pool bytes differ between chunked and per-byte application")
+    return fails
+
+
+# ------------------------------------------------------- identity tables --
+def identity_world(n_pages=96, levels=4, seed=9):
+    """Identity-mapped user pages [base, base + n_pages*4K) with one memslot at
+    arena offset 0, built by a tiny recursive encoder independent of the
+    generator (tables allocated top-down from the end of guest memory)."""
+    rng = np.random.default_rng(seed)
+    base = 0x40_0000  # 4 MiB
+    mem = 16 << 20
+    arena = np.zeros(mem, np.uint8)
+    gen.fill_bytes(arena, seed, 1)
+    next_frame = [mem - 4096]
+    tables = {}
+
+    def alloc():
+        f = next_frame[0]
+        next_frame[0] -= 4096
+        arena[f:f + 4096] = 0
+        return f
+
+    root = alloc()
+
+    def put(table, idx, val):
+        arena[table + 8 * idx: table + 8 * idx + 8] = np.frombuffer(int(val).to_bytes(8, "little"), np.uint8)
+
+    def get(table, idx):
+        return int.from_bytes(arena[table + 8 * idx: table + 8 * idx + 8].tobytes(), "little")
+
+    present = rng.random(n_pages) > 0.1
+    for k in range(n_pages):
+        va = base + 4096 * k
+        table = root
+        for lvl in range(levels, 1, -1):
+            idx = (va >> (12 + 9 * (lvl - 1))) & 511
+            e = get(table, idx)
+            if e & 1:
+                table = e & 0x000FFFFFFFFFF000
+            else:
+                t = alloc()
+                put(table, idx, t | 0x7)
+                table = t
+        put(table, (va >> 12) & 511, (va | 0x7) if present[k] else 0)
+    slots = np.zeros(1, SLOT_DTYPE)
+    slots[0] = (0, mem, 0)
+    return arena, slots, root, base, present
+
+
+def check_identity(lib_path=None, seed=9):
+    fails = []
+    for levels in (4, 5):
+        arena, slots, root, base, present = identity_world(levels=levels, seed=seed)
+        pool = np.zeros(1 << 20, np.uint8)
+        gen.fill_bytes(pool, seed, 2)
+        o = Oracle([arena], [slots], [(0, root, levels)], pool, lib_path=lib_path)
+        rng = np.random.default_rng(seed + levels)
+        hostpos = 0
+        for _ in range(60):
+            gva = base + int(rng.integers(0, 96 * 4096 - 1))
+            n = int(rng.integers(1, min(20000, base + 96 * 4096 - gva) + 1))
+            d = int(rng.integers(0, 2))
+            req = np.zeros(1, REQ_DTYPE)
+            req[0] = (gva, hostpos, n, 0, d, (0, 0, 0), 0)
+            pre_a, pre_p = arena.copy(), pool.copy()
+            r = o.copy(req[0])
+            pages = [(gva + i) >> 12 for i in range(0, n)]
+            first_bad = next((i for i in range(n) if not present[((gva + i) >> 12) - (base >> 12)]), n)
+            if int(r["bytes_done"]) != first_bad:
+                fails.append(f"identity L{levels}: bytes_done {int(r['bytes_done'])} expected {first_bad}")
+                break
+            k = first_bad
+            if d == 0:
+                exp_p = pre_p.copy()
+                exp_p[hostpos:hostpos + k] = pre_a[gva:gva + k]   # memcpy(pool+host, arena+gva, k)
+                if not np.array_equal(pool, exp_p):
+                    fails.append(f"identity L{levels}: guest->host differs from memcpy")
+                    break
+            else:
+                data = arena[gva:gva + k]
+                if not np.array_equal(data, pre_p[hostpos:hostpos + k]):
+                    fails.append(f"identity L{levels}: host->guest differs from memcpy")
+                    break
+            del pages
+            hostpos = (hostpos + n + 64) % ((1 << 20) - 20100)
+    return fails
+
+
+# -------------------------------------------------------------- A/D form --
+def expected_ad(wl, reqs, res):
+    """Final page-table bytes from the encoded map and the copied pages only."""
+    exp = {}
+    for v in wl.vms:
+        exp[v.vm] = v.pt_data.copy()
+    pos = {}
+    for v in wl.vms:
+        order = np.argsort(v.pt_gfn)
+        pos[v.vm] = (v.pt_gfn[order], order)
+    tabs = {p.asid: _leaf_lookup(p) for p in wl.procs}
+    A, D = np.uint64(0x20), np.uint64(0x40)
+    for i, r in enumerate(reqs):
+        done = int(res[i]["bytes_done"])
+        if done == 0:
+            continue
+        p = wl.procs[int(r["asid"])]
+        gva = int(r["gva"])
+        pages = np.arange(gva >> 12, ((gva + done - 1) >> 12) + 1, dtype=np.uint64) << np.uint64(12)
+        li = find_leaf(p, tabs[p.asid], pages)
+        assert np.all(li >= 0)
+        gfns, order = pos[p.vm]
+        tgt = exp[p.vm]
+
+        def orbits(gfn, idx, bits):
+            k = order[np.searchsorted(gfns, gfn)]
+            np.bitwise_or.at(tgt, (k, idx.astype(np.int64)), bits)
+
+        lv = p.leaf_level[li]
+        orbits(p.leaf_table_gfn[li], p.leaf_index[li], A | (D if int(r["dir"]) == 1 else np.uint64(0)))
+        for L in range(2, p.levels + 1):
+            m = lv < L
+            if not m.any():
+                continue
+            ids, tg = p.tables[L]
+            va = pages[m]
+            t = tg[np.searchsorted(ids, va >> np.uint64(12 + 9 * L))]
+            idx = (va >> np.uint64(12 + 9 * (L - 1))) & np.uint64(511)
+            orbits(t, idx, A)
+    return exp
+
+
+def check_ad_closed_form(wl, lib_path=None):
+    fails = []
+    o = Oracle.from_workload(wl, lib_path=lib_path)
+    res, _ = o.batch(wl.requests)
+    exp = expected_ad(wl, wl.requests, res)
+    for v in wl.vms:
+        hpa = gen.gpa_to_arena(v.slots, v.pt_gfn << np.uint64(12))
+        got = o.arenas[v.vm].reshape(-1, 4096)[(hpa >> 12)].view(np.uint64)
+        if not np.array_equal(got, exp[v.vm]):
+            nbad = int(np.sum(got != exp[v.vm]))
+            fails.append(f"vm {v.vm}: {nbad} page-table entries differ from the A/D closed form")
+    return fails
+
+
+# ------------------------------------------------------------ invariants --
+def check_invariants(wl, lib_path=None):
+    """Round trips and untouched bytes."""
+    fails = []
+    o = Oracle.from_workload(wl, lib_path=lib_path)
+    a0 = [a.copy() for a in o.arenas]
+    p0 = o.pool.copy()
+    reqs = wl.requests
+    res, faults = o.batch(reqs)
+    # fault list: one record per faulting request, ascending
+    fidx = np.nonzero(res["code"] != 0)[0]
+    if not np.array_equal(faults["req_index"], fidx.astype(np.uint64)):
+        fails.append("fault list is not the ascending list of faulting requests")
+    # bytes outside requests unchanged: pool changes only inside FROM_GUEST prefixes
+    allowed = np.zeros(o.pool.size, bool)
+    for i in np.nonzero(reqs["dir"] == 0)[0]:
+        h, d = int(reqs[i]["host"]), int(res[i]["bytes_done"])
+        allowed[h:h + d] = True
+    if np.any((o.pool != p0) & ~allowed):
+        fails.append("pool bytes changed outside guest->host request prefixes")
+    # arena changes only in page-table frames (A/D) and TO_GUEST prefixes
+    for v in wl.vms:
+        allowed = np.zeros(o.arenas[v.vm].size, bool)
+        hpa = gen.gpa_to_arena(v.slots, v.pt_gfn << np.uint64(12))
+        for h in hpa:
+            allowed[h:h + 4096] = True
+        for i in np.nonzero((reqs["dir"] == 1))[0]:
+            p = wl.procs[int(reqs[i]["asid"])]
+            if p.vm != v.vm or res[i]["bytes_done"] == 0:
+                continue
+            g = int(reqs[i]["gva"])
+            x = o.translate(int(reqs[i]["asid"]), np.arange(g, g + int(res[i]["bytes_done"]), dtype=np.uint64))
+            allowed[x["hpa"].astype(np.int64)] = True
+        if np.any((o.arenas[v.vm] != a0[v.vm]) & ~allowed):
+            fails.append(f"vm {v.vm}: arena bytes changed outside page tables and host->guest prefixes")
+    # round trips, epoch by epoch (requests of one epoch never overlap; across
+    # epochs they may reuse guest and pool bytes)
+    o2 = Oracle([a.copy() for a in a0], [v.slots for v in wl.vms],
+                [(p.vm, p.cr3, p.levels) for p in wl.procs], p0.copy(), lib_path=lib_path)
+    pt_mask = []
+    for v in range(len(wl.vms)):
+        hpa = gen.gpa_to_arena(wl.vms[v].slots, wl.vms[v].pt_gfn << np.uint64(12))
+        m = np.zeros(o2.arenas[v].size, bool)
+        for h in hpa:
+            m[h:h + 4096] = True
+        pt_mask.append(m)
+    for e0, e1 in wl.epochs():
+        ep = reqs[e0:e1]
+        # guest -> host -> guest leaves guest data bytes as they were
+        fwd = ep.copy()
+        fwd["dir"] = 0
+        snap = [a.copy() for a in o2.arenas]
+        r1, _ = o2.batch(fwd)
+        back = fwd.copy()
+        back["dir"] = 1
+        r2, _ = o2.batch(back)
+        if not np.array_equal(r1["bytes_done"], r2["bytes_done"]):
+            fails.append(f"epoch [{e0},{e1}) guest->host->guest: bytes_done differ")
+        for v in range(len(wl.vms)):
+            if np.any((o2.arenas[v] != snap[v]) & ~pt_mask[v]):
+                fails.append(f"epoch [{e0},{e1}) guest->host->guest changed guest data bytes in vm {v}")
+        # host -> guest -> host brings the pool prefix back
+        before = o2.pool.copy()
+        r3, _ = o2.batch(back)
+        o2.pool[:] = 0
+        r4, _ = o2.batch(fwd)
+        for i in range(len(ep)):
+            h, d = int(ep[i]["host"]), int(r3[i]["bytes_done"])
+            if int(r4[i]["bytes_done"]) < d or not np.array_equal(o2.pool[h:h + d], before[h:h + d]):
+                fails.append(f"host->guest->host: request {e0 + i} did not come back")
+                break
+        if fails:
+            break
+    # every byte of a not-present page faults: requests wholly inside one not-present leaf
+    for p in wl.procs[:4]:
+        np_idx = np.nonzero(~p.leaf_present)[0][:50]
+        for li in np_idx:
+            va = int(p.leaf_va[li]) + 5
+            q = np.zeros(1, REQ_DTYPE)
+            q[0] = (va, 0, 16, p.asid, 0, (0, 0, 0), 0)
+            r = o2.copy(q[0])
+            if int(r["code"]) != CODES["NOT_PRESENT"] or int(r["bytes_done"]) != 0:
+                fails.append(f"asid {p.asid}: read of a not-present page at {hex(va)} did not fault")
+                break
+    return fails
+
+
+def small_specs():
+    """Reduced configurations with the named ones' structure, sized for seconds on the CPU."""
+    KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
+    return {
+        "tiny4k": gen.spec("C1", mem_bytes=512 * KiB, n_requests=64, n_slots=2, p_np=0.2, len_hi=12000, seed=11),
+        "c1": gen.spec("C1"),
+        "mix2m": gen.spec("C2", mem_bytes=64 * MiB, n_requests=400, n_slots=6, len_hi=40000, seed=12),
+        "multi_vm": gen.spec("C3", n_vms=3, procs_per_vm=2, mem_bytes=32 * MiB, n_requests=500, len_hi=300000,
+                             seed=13),
+        "lvl5": gen.spec("C5", n_vms=2, mem_bytes=32 * MiB, mix=(0.6, 0.4, 0.0), n_requests=300, len_hi=100000,
+                         seed=14),
+        "lvl5_1g": gen.spec("C5", n_vms=1, mem_bytes=3 * GiB // 2, mapped_frac=0.7, mix=(0.02, 0.02, 0.96),
+                            n_requests=200, len_hi=100000, seed=15),
+        "prot": gen.spec("C2", mem_bytes=16 * MiB, n_requests=300, p_readonly=0.1, p_supervisor=0.05,
+                         p_upper_np=0.05, len_hi=20000, seed=16),
+    }

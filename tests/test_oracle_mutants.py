@@ -1,0 +1,84 @@
+"""The pins catch plausible mistakes.
+
+Each case copies the oracle source, plants one mistake (a dropped term, a
+wrong bit, a swapped operand, an off-by-one), builds it on the CPU and runs
+the pin checks against it: at least one pin must fail.  The real oracle is
+never modified.
+"""
+import os
+import subprocess
+
+import pytest
+
+import pins
+from workload import gen
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "oracle.c")
+
+MUTANTS = {
+    "index_mask_8bit": ("uint64_t idx = (gva >> shift) & 511;", "uint64_t idx = (gva >> shift) & 255;"),
+    "index_shift_off_by_one_level": ("uint32_t shift = 12 + 9 * (uint32_t)(lvl - 1);",
+                                     "uint32_t shift = 12 + 9 * (uint32_t)(lvl - 1) + (lvl == 2);"),
+    "user_bit_not_accumulated": ("user_ok &= (int)((e >> 2) & 1);", "user_ok &= 1;"),
+    "write_bit_not_accumulated": ("write_ok &= (int)((e >> 1) & 1);", "write_ok &= (int)((e >> 1) & 1) | (lvl > 1);"),
+    "dirty_on_reads": ("if (write && i + 1 == w->npath) want |= (uint8_t)ORC_D;",
+                       "if (i + 1 == w->npath) want |= (uint8_t)ORC_D;"),
+    "accessed_only_on_leaf": ("uint8_t want = (uint8_t)ORC_A;",
+                              "uint8_t want = (i + 1 == w->npath) ? (uint8_t)ORC_A : 0;"),
+    "pat_bit_reserved": ("uint64_t rsvd = (size - 1) & ~((1ull << 13) - 1);",
+                         "uint64_t rsvd = (size - 1) & ~((1ull << 12) - 1);"),
+    "large_frame_keeps_low_bits": ("frame = e & ORC_ADDR_MASK & ~(size - 1);", "frame = e & ORC_ADDR_MASK;"),
+    "ps_at_level4_allowed": ("if (lvl >= 4 && (e & ORC_PS)) {", "if (lvl >= 5 && (e & ORC_PS)) {"),
+    "user_write_order_swapped": ("    if (!user_ok) {\n        w->code = ORC_PROT_USER;",
+                                 "    if (!user_ok && !(write && !write_ok)) {\n        w->code = ORC_PROT_USER;"),
+    "fault_gva_page_base": ("res->fault_gva = lo;", "res->fault_gva = page;"),
+    "bytes_done_counts_fault_page": ("res->bytes_done = lo - req->gva;", "res->bytes_done = hi - req->gva;"),
+    "slot_end_inclusive": ("if (gpa >= sl->gpa && gpa - sl->gpa < sl->bytes) {",
+                           "if (gpa >= sl->gpa && gpa - sl->gpa <= sl->bytes) {"),
+    "slot_offset_dropped": ("*hpa = sl->arena_off + (gpa - sl->gpa);", "*hpa = sl->arena_off + gpa;"),
+    "canonical_limit_48": ("return levels == 5 ? (1ull << 56) : (1ull << 47);",
+                           "return levels == 5 ? (1ull << 56) : (1ull << 48);"),
+    "copy_direction_swapped": ("        if (to_guest)\n            memcpy(g, h, hi - lo);",
+                               "        if (!to_guest)\n            memcpy(g, h, hi - lo);"),
+    "ad_before_fault_check": ("        if (w.code != ORC_OK) {\n            res->bytes_done",
+                              "        if (w.npath) set_ad(s, p, &w, to_guest);\n"
+                              "        if (w.code != ORC_OK) {\n            res->bytes_done"),
+    "cr3_low_bits_used": ("uint64_t table = p->cr3 & ORC_ADDR_MASK;", "uint64_t table = p->cr3 & ~0x7ull;"),
+    "copy_whole_page": ("            memcpy(h, g, hi - lo);", "            memcpy(h, g, hi - lo + (hi - lo < 4096));"),
+}
+
+_SMALL = {}
+
+
+def _small(name):
+    if name not in _SMALL:
+        _SMALL[name] = gen.make_workload(pins.small_specs()[name])
+    return _SMALL[name]
+
+
+def _build(tmp_path, name):
+    src = open(SRC).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / f"lib{name}.so"
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", str(path), "-o", str(lib)])
+    return str(lib)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(tmp_path, name):
+    lib = _build(tmp_path, name)
+    checks = [
+        lambda: pins.check_golden(lib),
+        lambda: pins.check_identity(lib),
+        lambda: pins.check_roundtrip(_small("mix2m"), lib, per_proc=3000),
+        lambda: pins.check_roundtrip(_small("lvl5_1g"), lib, per_proc=3000),
+        lambda: pins.check_bruteforce(_small("prot"), lib, max_requests=60),
+        lambda: pins.check_ad_closed_form(_small("c1"), lib),
+    ]
+    for c in checks:
+        if c():
+            return
+    pytest.fail(f"no pin caught mutant {name}")

@@ -1,0 +1,72 @@
+"""The CPU oracle against facts other than itself (hand-derived walks,
+the generator's encoded map, per-byte brute force, memcpy, invariants)."""
+import pytest
+
+import pins
+from workload import gen
+
+SPECS = pins.small_specs()
+_WL = {}
+
+
+def wl(name):
+    if name not in _WL:
+        _WL[name] = gen.make_workload(SPECS[name])
+    return _WL[name]
+
+
+def test_golden_walks_ad_and_copies():
+    assert pins.check_golden() == []
+
+
+@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g"])
+def test_encode_decode_roundtrip(name):
+    assert pins.check_roundtrip(wl(name)) == []
+
+
+@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "prot"])
+def test_per_byte_bruteforce(name):
+    assert pins.check_bruteforce(wl(name), max_requests=120) == []
+
+
+def test_identity_tables_equal_memcpy():
+    assert pins.check_identity() == []
+
+
+@pytest.mark.parametrize("name", ["c1", "mix2m", "multi_vm", "lvl5", "prot"])
+def test_ad_closed_form(name):
+    assert pins.check_ad_closed_form(wl(name)) == []
+
+
+@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5"])
+def test_invariants(name):
+    assert pins.check_invariants(wl(name)) == []
+
+
+@pytest.mark.parametrize("name", ["c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g"])
+def test_generated_batches_are_conflict_free(name):
+    from oracle import Oracle
+    w = wl(name)
+    o = Oracle.from_workload(w)
+    assert o.check_conflicts(w.requests, w.epoch_end) is None
+
+
+def test_conflict_checker_finds_planted_overlap():
+    from oracle import Oracle
+    w = wl("c1")
+    o = Oracle.from_workload(w)
+    r = w.requests.copy()
+    # make request 1 write the same pool bytes request 0 writes (both guest->host)
+    r["dir"][:2] = 0
+    r["host"][1] = r["host"][0]
+    assert o.check_conflicts(r, [len(r)]) is not None
+    # a guest-side write overlapping another request's read of the same guest bytes
+    r = w.requests.copy()
+    r["asid"][1] = r["asid"][0]
+    r["gva"][1] = r["gva"][0]
+    r["dir"][0], r["dir"][1] = 0, 1
+    r["len"][:2] = 64
+    res, _ = o.batch(w.requests[:0])
+    x = o.translate(int(r["asid"][0]), [int(r["gva"][0])])[0]
+    if x["code"] == 0:
+        assert o.check_conflicts(r, [len(r)]) is not None
