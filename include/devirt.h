@@ -1,0 +1,293 @@
+/*
+ * devirt.h -- C ABI of the MI355X (gfx950) guest-memory translate-and-copy
+ * library.
+ *
+ * The library implements the data path of the software hybrid address space
+ * (section 4.2 of "Making I/O Virtualization Easy with Device Files"): a host
+ * driver that serves a guest's file operation reads or writes the guest's
+ * user buffer at a guest virtual address.  Each page of the buffer is
+ * translated separately, because guest-contiguous pages need not be
+ * host-contiguous (section 4.2): first by a software walk of the guest's own
+ * page tables (guest virtual -> guest physical), then through the VM's
+ * memslots (guest physical -> host address, as KVM does; section 4.2).  The
+ * bytes are then copied between the guest memory image and host buffers.
+ *
+ * Platform: x86-64 guest paging, 4-level (48-bit) or 5-level (57-bit), with
+ * 4 KiB, 2 MiB and 1 GiB pages.  Guest memory ("arena") and host buffers
+ * live in HBM of one GPU.  The paper's own platform was 32-bit PAE on KVM
+ * (section 6.2); the interface below keeps its roles: a process is named by
+ * its page-table root captured when it first issues an operation
+ * (section 6.3), an operation carries a handful of scalar arguments
+ * (section 6.1), results come back in a per-operation record (section 5), and
+ * a failed operation leaves a defined, re-executable state (section 6.6).
+ *
+ * Conventions for every call:
+ *   - Return value: 0 on success, a negative errno on misuse or a HIP failure
+ *     (-EINVAL, -ENOMEM, -EEXIST, -EBUSY, -EIO, -ENOENT).  Calls never abort
+ *     and never print; devirt_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   - Guest faults are NOT errors: they are reported per operation in
+ *     devirt_result / devirt_xlat / devirt_fault records.
+ *   - Pointers named *_dev are device pointers (HBM of the context's GPU);
+ *     *_host are host pointers.  The caller owns every buffer it passes and
+ *     keeps it alive until the stream has passed the call.
+ *   - Data-path calls (translate, copy, submit_batch) are asynchronous and
+ *     ordered on the given HIP stream (NULL = the null stream).  Control
+ *     calls (vm/memslot/process) synchronise the device first.
+ *   - A context is externally synchronised: one thread at a time.
+ */
+#ifndef DEVIRT_H
+#define DEVIRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct devirt_ctx devirt_ctx;
+typedef struct devirt_server devirt_server;
+
+/* ---------------------------------------------------------------- records */
+
+/* Direction of a copy (section 4.2: "read from and write to a user buffer"). */
+#define DEVIRT_FROM_GUEST 0u /* guest memory -> host buffer (e.g. a guest write()) */
+#define DEVIRT_TO_GUEST 1u   /* host buffer -> guest memory (e.g. a guest read())  */
+
+/* One operation's argument buffer: 32 bytes, little endian, device memory.
+ * Mirrors the few scalar arguments a forwarded file operation carries
+ * (section 6.1). */
+typedef struct {
+    uint64_t gva;     /* guest virtual address of the buffer                */
+    uint64_t host;    /* device pointer to the host-side buffer             */
+    uint32_t len;     /* bytes                                              */
+    uint32_t asid;    /* process id from devirt_process_create              */
+    uint8_t dir;      /* DEVIRT_FROM_GUEST or DEVIRT_TO_GUEST               */
+    uint8_t rsvd[3];  /* must be 0                                          */
+    uint32_t tag;     /* caller's tag; the serving loop reads it as the
+                         guest thread id (one operation in flight per id)  */
+} devirt_request;
+
+/* Fault codes (devirt_result.code, devirt_fault.code, devirt_xlat.code). */
+#define DEVIRT_OK 0u
+#define DEVIRT_NOT_PRESENT 1u  /* P = 0 in the entry at `level`                   */
+#define DEVIRT_RESERVED 2u     /* PS in a level-4/5 entry, or a large leaf with
+                                  bits [shift-1:13] set                           */
+#define DEVIRT_PROT_USER 3u    /* U/S = 0 somewhere on the path (user access)     */
+#define DEVIRT_PROT_WRITE 4u   /* R/W = 0 somewhere on the path, writing guest    */
+#define DEVIRT_NO_MEMSLOT 5u   /* a table (level >= 1) or the data page (level 0)
+                                  has no memslot                                  */
+#define DEVIRT_NONCANONICAL 6u /* range not inside user canonical space, or wraps */
+#define DEVIRT_INVALID 7u      /* unknown asid                                    */
+
+/* Per-operation result (24 bytes), the analogue of the per-guest-thread
+ * result page (section 5).  Copies have prefix semantics: every byte before
+ * the first faulting byte is copied, nothing after it; bytes_done is that
+ * byte's offset.  fault_gva is the first byte not copied (0 if none). */
+typedef struct {
+    uint64_t bytes_done;
+    uint64_t fault_gva;
+    uint32_t code;
+    uint16_t level;
+    uint16_t pad;
+} devirt_result;
+
+/* Fault-list record (24 bytes): one per operation whose code is not OK,
+ * ascending by request index. */
+typedef struct {
+    uint64_t req_index;
+    uint64_t fault_gva;
+    uint32_t code;
+    uint16_t level;
+    uint16_t pad;
+} devirt_fault;
+
+/* Translation of one address (24 bytes).  gpa and page_shift are set once a
+ * leaf was reached (code OK, PROT_*, or NO_MEMSLOT at level 0); hpa (byte
+ * offset in the VM's arena) only when code is OK; vm is 0xFFFF for an
+ * unknown asid. */
+typedef struct {
+    uint64_t gpa;
+    uint64_t hpa;
+    uint32_t code;
+    uint8_t level;
+    uint8_t page_shift;
+    uint16_t vm;
+} devirt_xlat;
+
+/* devirt_translate flags */
+#define DEVIRT_XLAT_WRITE 1u  /* check write permission                          */
+#define DEVIRT_XLAT_SET_AD 2u /* on success, OR A into every walked entry and,
+                                 with WRITE, D into the leaf                     */
+
+/* ---------------------------------------------------------------- context */
+
+/* Open a context on HIP device `hip_device`. */
+int devirt_open(int hip_device, devirt_ctx **out);
+/* Release everything the context owns (arenas, tables, workspaces). */
+int devirt_close(devirt_ctx *ctx);
+/* Message for the calling thread's last failed call ("" if none). */
+const char *devirt_last_error(void);
+
+/* ------------------------------------------------- guest memory and tables */
+
+/* Allocate a VM's guest-memory arena of `arena_bytes` (multiple of 4 KiB) in
+ * HBM; returns its id in *vm.  The arena starts zeroed. */
+int devirt_vm_create(devirt_ctx *ctx, uint64_t arena_bytes, uint32_t *vm);
+/* Borrow the arena's device pointer and size (valid until devirt_close). */
+int devirt_vm_arena(devirt_ctx *ctx, uint32_t vm, void **dev_ptr, uint64_t *bytes);
+/* Synchronous copies into / out of an arena; src/dst may be host or device
+ * pointers.  -EINVAL if [off, off+bytes) leaves the arena. */
+int devirt_vm_write(devirt_ctx *ctx, uint32_t vm, uint64_t off, const void *src, uint64_t bytes);
+int devirt_vm_read(devirt_ctx *ctx, uint32_t vm, uint64_t off, void *dst, uint64_t bytes);
+
+/* Define memslot `slot` (0..63) of a VM: guest-physical [gpa, gpa+bytes) is
+ * backed by arena bytes [arena_off, arena_off+bytes) (KVM's GPA -> host map,
+ * section 4.2).  All three values 4 KiB aligned, gpa+bytes <= 2^52.
+ * bytes == 0 deletes the slot.  -EEXIST if the GPA range overlaps another
+ * slot of the VM, -EINVAL if unaligned or outside the arena. */
+int devirt_memslot_set(devirt_ctx *ctx, uint32_t vm, uint32_t slot, uint64_t gpa, uint64_t bytes,
+                       uint64_t arena_off);
+
+/* Register a guest process by its page-table root (CR3; low 12 bits
+ * ignored) and paging depth (4 or 5), captured once as the backend does when
+ * a thread first makes a call (section 6.3).  Returns ids 0, 1, 2, ... */
+int devirt_process_create(devirt_ctx *ctx, uint32_t vm, uint64_t cr3_gpa, uint32_t levels, uint32_t *asid);
+
+/* ---------------------------------------------------------------- data path */
+
+/* Translate n guest virtual addresses of process `asid` (section 4.2: walk
+ * the guest page tables, then the memslots).  gva_dev: n x uint64_t;
+ * out_dev: n x devirt_xlat. */
+int devirt_translate(devirt_ctx *ctx, uint32_t asid, const uint64_t *gva_dev, uint64_t n, uint32_t flags,
+                     devirt_xlat *out_dev, void *hip_stream);
+
+/* One operation, one launch (the plain per-request method): copy len bytes
+ * from guest memory at gva into dst_dev / from src_dev into guest memory at
+ * gva, page by page (section 4.2), with prefix semantics on a fault and A/D
+ * bits set for every page copied.  len < 2^32.  res_dev: 1 devirt_result. */
+int devirt_copy_from_guest(devirt_ctx *ctx, uint32_t asid, uint64_t gva, void *dst_dev, uint64_t len,
+                           devirt_result *res_dev, void *hip_stream);
+int devirt_copy_to_guest(devirt_ctx *ctx, uint32_t asid, uint64_t gva, const void *src_dev, uint64_t len,
+                         devirt_result *res_dev, void *hip_stream);
+
+/* Many operations from many guests in one submission.  Results equal
+ * applying the requests one after another in index order, provided that
+ * inside each epoch no two requests touch overlapping guest bytes of one VM
+ * or overlapping host bytes where one of them writes, and none writes a page
+ * table; epochs run in order.  epoch_end_host: n_epochs ascending exclusive
+ * end indices, the last == n (NULL: one epoch).  res_dev: n devirt_result;
+ * faults_dev: room for n devirt_fault (may be NULL together with
+ * n_faults_dev); n_faults_dev: one uint64_t; t_done_dev: NULL or n uint64_t
+ * receiving each request's completion time in ns after the submission
+ * started on the device. */
+int devirt_submit_batch(devirt_ctx *ctx, const devirt_request *reqs_dev, uint64_t n,
+                        const uint64_t *epoch_end_host, uint32_t n_epochs, devirt_result *res_dev,
+                        devirt_fault *faults_dev, uint64_t *n_faults_dev, uint64_t *t_done_dev, void *hip_stream);
+
+/* Wait for everything the context enqueued on hip_stream. */
+int devirt_sync(devirt_ctx *ctx, void *hip_stream);
+
+/* ---------------------------------------------------------------- tuning */
+
+/* Launch and schedule knobs of the batched path.  None changes results. */
+typedef struct {
+    uint32_t group;           /* requests one translating wavefront owns: 1..64     */
+    uint32_t seg_chunks;      /* max 4 KiB pages merged into one copy segment: 1..64 */
+    uint32_t xlat_wg;         /* translate workgroup size (multiple of 64, <= 256)  */
+    uint32_t xlat_wgs_per_cu; /* translate grid = CUs x this                        */
+    uint32_t copy_wg;         /* copy workgroup size (multiple of 64, <= 1024)      */
+    uint32_t copy_wgs_per_cu; /* copy grid = CUs x this                             */
+    uint32_t nontemporal;     /* 1: streaming (non-temporal) stores when copying     */
+    uint32_t inline_bytes;    /* segments up to this size (<= 256) are copied by the
+                                 translating lane itself                            */
+    uint32_t use_graph;       /* 1: capture each distinct batch shape as a HIP graph
+                                 and replay it                                     */
+    uint32_t fused;           /* 1: run all epochs of a batch in one persistent
+                                 launch with device-side epoch barriers             */
+} devirt_config;
+
+int devirt_get_config(devirt_ctx *ctx, devirt_config *cfg);
+/* -EINVAL if a field is out of range; the previous config is kept. */
+int devirt_set_config(devirt_ctx *ctx, const devirt_config *cfg);
+
+/* Time candidate configs on a real batch and keep the fastest.  The batch
+ * is executed once per candidate and repetition, with the usual effects on
+ * guest memory, host buffers, A/D bits and result buffers; the final state
+ * is that of the last execution.  The winner is stored in the context and
+ * returned in *best (and its median time in *best_ms).  Synchronous. */
+int devirt_autotune(devirt_ctx *ctx, const devirt_request *reqs_dev, uint64_t n, const uint64_t *epoch_end_host,
+                    uint32_t n_epochs, devirt_result *res_dev, devirt_fault *faults_dev, uint64_t *n_faults_dev,
+                    void *hip_stream, uint32_t reps, devirt_config *best, double *best_ms);
+
+/* ---------------------------------------------------------------- metrics */
+
+typedef struct {
+    uint64_t batches;        /* devirt_submit_batch calls                          */
+    uint64_t epochs;         /* epochs launched                                    */
+    uint64_t plain_calls;    /* devirt_copy_* calls                                */
+    uint64_t graph_replays;  /* batches served by replaying a captured graph       */
+    /* the following are filled only while profiling is on */
+    uint64_t copy_launches;  /* copy-kernel launches timed                         */
+    double copy_ms;          /* summed copy-kernel time (HIP events)               */
+    uint64_t xlat_launches;  /* translate-kernel launches timed                    */
+    double xlat_ms;          /* summed translate-kernel time                       */
+    uint64_t pages_walked;   /* 4 KiB pages translated by the batched path         */
+    uint64_t cache_hits;     /* per-wavefront walk-cache hits (1 GiB regions)      */
+    uint64_t cache_misses;
+    uint64_t segments;       /* copy segments queued                               */
+    uint64_t inline_segments;/* segments copied by the translating wavefront       */
+    uint64_t ad_atomics;     /* A/D atomic ORs issued                              */
+} devirt_stats;
+
+/* With profiling on, data-path calls run without graphs, each kernel launch
+ * is bracketed by HIP events on the call's stream, and device counters are
+ * gathered; devirt_get_stats synchronises to read them. */
+int devirt_set_profiling(devirt_ctx *ctx, int on);
+int devirt_get_stats(devirt_ctx *ctx, devirt_stats *out);
+int devirt_reset_stats(devirt_ctx *ctx);
+
+/* ---------------------------------------------------------------- serving */
+
+/* Serving loop: operations arrive one by one and are admitted when (a) their
+ * guest thread (devirt_request.tag, per asid) has no operation in flight --
+ * the guest thread sleeps until its operation completes (section 5) -- (b) a
+ * descriptor slot is free and (c) the bytes of all operations in flight stay
+ * within pool_bytes.  Admitted operations are batched continuously: while
+ * earlier batches run on the GPU, newly admitted ones are launched on further
+ * streams, and completions are polled (section 7.4 finds polling faster than
+ * interrupts).  Page tables stay resident in the context. */
+typedef struct {
+    uint32_t max_inflight; /* descriptor slots (operations admitted, not yet done)  */
+    uint64_t pool_bytes;   /* byte budget of operations in flight                   */
+    uint32_t max_batch;    /* operations per launch (0: max_inflight)               */
+    uint32_t streams;      /* launches in flight at once, 1..8                      */
+    uint32_t flags;        /* reserved, 0                                           */
+} devirt_server_cfg;
+
+typedef struct {
+    uint64_t ticket;       /* submission order, from 0                              */
+    devirt_result res;
+    uint64_t t_submit_ns;  /* host steady clock: submitted                          */
+    uint64_t t_admit_ns;   /* admitted into a launch                                */
+    uint64_t t_done_ns;    /* completion observed by the server                     */
+} devirt_completion;
+
+/* Start a server thread on the context.  While it runs, the context may
+ * only be used through the server (and read-only queries). */
+int devirt_server_start(devirt_ctx *ctx, const devirt_server_cfg *cfg, devirt_server **out);
+/* Queue n operations (host copies of the descriptors; their host buffers are
+ * device memory the caller keeps alive until completion).  Returns the
+ * number queued in *n_queued; -EBUSY if the queue is full. */
+int devirt_server_submit(devirt_server *srv, const devirt_request *reqs_host, uint32_t n, uint32_t *n_queued);
+/* Take up to max completions (any order); *n_out receives the count. */
+int devirt_server_poll(devirt_server *srv, devirt_completion *out, uint32_t max, uint32_t *n_out);
+/* Drain: wait until everything submitted has completed. */
+int devirt_server_drain(devirt_server *srv);
+/* Stop the thread (after draining) and free the server. */
+int devirt_server_stop(devirt_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEVIRT_H */

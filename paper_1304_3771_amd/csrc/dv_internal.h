@@ -1,0 +1,112 @@
+// Internal layouts shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+#include "../../include/devirt.h"
+
+namespace dv {
+
+// x86-64 entry bits (section 4.2 walks the guest's own tables).
+constexpr uint64_t kAddrMask = 0x000FFFFFFFFFF000ull;  // address bits 51:12
+constexpr uint64_t kP = 1ull, kRW = 2ull, kUS = 4ull, kA = 0x20ull, kD = 0x40ull, kPS = 0x80ull;
+
+// A memslot as the device sees it: sorted by gpa, end = gpa + bytes.
+struct DSlot {
+    uint64_t gpa;
+    uint64_t end;
+    uint64_t arena_off;
+};
+
+// Per-VM device view.  `index` holds one word per 2 MiB of guest-physical
+// space below index_len * 2 MiB:
+//   0                 no slot overlaps the block
+//   delta | 2         one slot covers the whole block; hpa = gpa + delta
+//                     (delta = arena_off - slot gpa, 4 KiB aligned, mod 2^64)
+//   1                 the block is split between slots / holes: search slots
+// When index_complete is set, no slot lies at or above index_len * 2 MiB.
+struct DVm {
+    uint8_t *arena;
+    uint64_t arena_bytes;
+    const uint64_t *index;
+    const DSlot *slots;
+    uint32_t index_len;
+    uint32_t nslots;
+    uint32_t index_complete;
+    uint32_t pad;
+};
+
+struct DProc {
+    uint64_t cr3;
+    uint32_t vm;
+    uint32_t levels;
+};
+
+struct DView {
+    const DVm *vms;
+    const DProc *procs;
+    uint32_t nvm;
+    uint32_t nproc;
+};
+
+// One queued copy segment (32 B): a run of pages of one request whose guest
+// side is contiguous in the arena.
+struct DSeg {
+    uint64_t src;
+    uint64_t dst;
+    uint32_t len;
+    uint32_t req;
+    uint64_t pad;
+};
+
+// Per-epoch device counters (16 B each).
+struct DEpochCtr {
+    uint32_t group_cursor;  // next request group to translate
+    uint32_t nseg;          // segments queued (may exceed capacity: overflow copied inline)
+    uint32_t pad0, pad1;
+};
+
+// Device counters gathered while profiling.
+struct DCounters {
+    unsigned long long pages_walked;
+    unsigned long long cache_hits;
+    unsigned long long cache_misses;
+    unsigned long long segments;
+    unsigned long long inline_segments;
+    unsigned long long ad_atomics;
+};
+
+// Everything one batch launch needs besides the view.
+struct DBatch {
+    const devirt_request *reqs;
+    devirt_result *res;
+    uint64_t *t_done;         // may be null
+    uint32_t *pending;        // per request, queued segments not yet copied (t_done only)
+    DSeg *segs;
+    uint64_t seg_cap;
+    DEpochCtr *ctr;           // per epoch
+    DCounters *counters;      // null unless profiling
+    uint64_t *t0;             // device wall clock at batch start
+    uint64_t ns_num;          // ns = ticks * ns_num / ns_den
+    uint64_t ns_den;
+    uint32_t group;
+    uint32_t seg_chunks;
+    uint32_t inline_bytes;
+    uint32_t nontemporal;
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+hipError_t launch_reset(hipStream_t s, DBatch b, uint32_t n_epochs);
+hipError_t launch_translate_groups(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0,
+                                   uint64_t r1, uint32_t epoch);
+hipError_t launch_copy(hipStream_t s, int grid, int block, DBatch b, uint32_t epoch);
+hipError_t launch_plain(hipStream_t s, DView v, DBatch b, devirt_request req, int inline_copy);
+hipError_t launch_xlat(hipStream_t s, int grid, int block, DView v, uint32_t asid, const uint64_t *gva,
+                       uint64_t n, uint32_t flags, devirt_xlat *out, DCounters *counters);
+hipError_t launch_fault_count(hipStream_t s, const devirt_result *res, uint64_t n, uint32_t *tile_cnt);
+hipError_t launch_fault_scan(hipStream_t s, uint32_t *tile_cnt, uint64_t ntiles, uint64_t *n_faults);
+hipError_t launch_fault_scatter(hipStream_t s, const devirt_result *res, uint64_t n, const uint32_t *tile_off,
+                                devirt_fault *faults);
+constexpr int kFaultTile = 1024;
+
+}  // namespace dv

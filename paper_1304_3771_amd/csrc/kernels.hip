@@ -1,0 +1,1120 @@
+// gfx950 kernels of the guest-memory translate-and-copy path.
+//
+// The operation (section 4.2 of the paper): a buffer at a guest virtual
+// address is translated page by page -- a software walk of the guest's
+// x86-64 page tables to a guest-physical address, then the VM's memslots to
+// the host address (KVM style) -- and its bytes are copied between the guest
+// memory image ("arena") and a host buffer.  A fault ends the operation with
+// everything before the faulting byte copied, so the operation can be
+// re-executed (section 6.6).
+//
+// Work decomposition (wave64 throughout):
+//   translate  one wavefront owns a group of up to 64 consecutive requests.
+//              A wave prefix sum over their page counts flattens the group's
+//              pages; each pass gives every lane one page.  Lanes that start a
+//              2 MiB region ("heads") resolve the upper levels -- levels 5..3
+//              through a per-wavefront LDS cache of 1 GiB regions, level 2 by
+//              a load -- and hand the result to the rest of the region with
+//              cross-lane shuffles; every lane then reads its own leaf entry,
+//              so neighbouring lanes read neighbouring PTEs in one cache line.
+//              Because a group's pages are walked in order, the first fault
+//              of each request is exact (ballot + find-first-set) before any
+//              side effect: A/D bits are OR-ed only into entries on the paths
+//              of pages that will be copied.  Copy segments (runs of pages
+//              whose guest side is contiguous in the arena) are appended to a
+//              queue with one wave-aggregated atomic per pass.
+//   copy       every wavefront takes segments and moves them with 16-byte
+//              aligned stores; the source misalignment is absorbed with
+//              cross-lane shuffles and byte funnel shifts, never with a
+//              read-modify-write of bytes outside the segment.
+//   faults     the ordered fault list is a tile count, a single-workgroup
+//              scan and a ballot/mbcnt scatter.
+#include "dv_internal.h"
+
+namespace dv {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kCacheWays = 16;  // 1 GiB-region cache entries per wavefront
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t mask_le(int lane) {
+    return lane >= 63 ? ~0ull : ((2ull << lane) - 1ull);
+}
+__device__ __forceinline__ uint64_t mask_lt(int lane) { return lane <= 0 ? 0ull : ((1ull << lane) - 1ull); }
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    uint32_t lo = uniform_u32((uint32_t)x), hi = uniform_u32((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src) {
+    return __shfl((unsigned long long)x, src);
+}
+__device__ __forceinline__ uint32_t shfl32(uint32_t x, int src) { return (uint32_t)__shfl((int)x, src); }
+
+__device__ __forceinline__ uint64_t load_entry(const uint8_t *arena, uint64_t off) {
+    return *(const uint64_t *)(arena + off);
+}
+
+// OR bits into the low dword of a page-table entry (A and D live in bits 5, 6).
+__device__ __forceinline__ void or_entry(uint8_t *arena, uint64_t off, uint32_t bits) {
+    __hip_atomic_fetch_or((unsigned int *)(arena + off), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t now_ns(const DBatch &b) {
+    uint64_t t = wall_clock64();
+    uint64_t t0 = *b.t0;
+    return (t - t0) * b.ns_num / b.ns_den;
+}
+
+// ------------------------------------------------------------------ memslots
+// GPA -> arena offset (section 4.2: the guest-physical address is turned into
+// the host address backing it, as KVM does with its memslots).
+__device__ __forceinline__ bool slot_lookup(const DVm &v, uint64_t gpa, uint64_t &hpa) {
+    uint64_t blk = gpa >> 21;
+    if (blk < v.index_len) {
+        uint64_t e = v.index[blk];
+        if (e & 2) {
+            hpa = gpa + (e & ~0xFFFull);
+            return true;
+        }
+        if (!(e & 1)) return false;
+    } else if (v.index_complete) {
+        return false;
+    }
+    uint32_t lo = 0, hi = v.nslots;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (v.slots[mid].gpa <= gpa)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo == 0) return false;
+    DSlot s = v.slots[lo - 1];
+    if (gpa >= s.end) return false;
+    hpa = s.arena_off + (gpa - s.gpa);
+    return true;
+}
+
+// ------------------------------------------------------------ upper levels
+// Result of walking the levels above the page directory for one 1 GiB region
+// (x86-64: level 5 (LA57), level 4, level 3).
+struct CEnt {
+    uint64_t key;      // (asid << 27) | (gva >> 30); ~0 when empty
+    uint64_t base;     // table: GPA of the level-2 table; 1 GiB leaf: frame GPA
+    uint64_t path[3];  // arena offsets of the entries read, top level first
+    uint32_t info;     // code:4 level:4 leaf1g:1 u:1 w:1 npath:2 abits:3 dbit:1
+    uint32_t pad;
+};
+__device__ __forceinline__ uint32_t ci_code(uint32_t i) { return i & 15u; }
+__device__ __forceinline__ uint32_t ci_level(uint32_t i) { return (i >> 4) & 15u; }
+__device__ __forceinline__ uint32_t ci_leaf(uint32_t i) { return (i >> 8) & 1u; }
+__device__ __forceinline__ uint32_t ci_u(uint32_t i) { return (i >> 9) & 1u; }
+__device__ __forceinline__ uint32_t ci_w(uint32_t i) { return (i >> 10) & 1u; }
+__device__ __forceinline__ uint32_t ci_np(uint32_t i) { return (i >> 11) & 3u; }
+__device__ __forceinline__ uint32_t ci_abits(uint32_t i) { return (i >> 13) & 7u; }
+constexpr uint32_t kCiDbit = 1u << 16;
+
+template <int LEVELS>
+__device__ __forceinline__ void walk_upper_t(const DVm &v, uint64_t cr3, uint64_t gva, CEnt &c) {
+    uint64_t table = cr3 & kAddrMask;
+    uint32_t u = 1, w = 1, abits = 0;
+    c.path[0] = c.path[1] = c.path[2] = 0;
+#pragma unroll
+    for (int i = 0; i < LEVELS - 2; ++i) {
+        const int lvl = LEVELS - i;
+        const uint32_t shift = 12 + 9 * (lvl - 1);
+        uint64_t th;
+        if (!slot_lookup(v, table, th)) {
+            c.info = DEVIRT_NO_MEMSLOT | (lvl << 4) | (i << 11) | (abits << 13);
+            return;
+        }
+        uint64_t eoff = th + 8 * ((gva >> shift) & 511);
+        uint64_t e = load_entry(v.arena, eoff);
+        c.path[i] = eoff;
+        if (e & kA) abits |= 1u << i;
+        if (!(e & kP)) {
+            c.info = DEVIRT_NOT_PRESENT | (lvl << 4) | ((i + 1) << 11) | (abits << 13);
+            return;
+        }
+        u &= (uint32_t)(e >> 2) & 1u;
+        w &= (uint32_t)(e >> 1) & 1u;
+        if (lvl >= 4 && (e & kPS)) {
+            c.info = DEVIRT_RESERVED | (lvl << 4) | ((i + 1) << 11) | (abits << 13);
+            return;
+        }
+        if (lvl == 3 && (e & kPS)) {
+            if (e & 0x3FFFE000ull) {  // bits 29:13 of a 1 GiB leaf are reserved
+                c.info = DEVIRT_RESERVED | (3u << 4) | ((i + 1) << 11) | (abits << 13);
+                return;
+            }
+            c.base = e & kAddrMask & ~((1ull << 30) - 1);
+            c.info = DEVIRT_OK | (1u << 8) | (u << 9) | (w << 10) | ((i + 1) << 11) | (abits << 13) |
+                     ((e & kD) ? kCiDbit : 0u);
+            return;
+        }
+        table = e & kAddrMask;
+    }
+    c.base = table;
+    c.info = DEVIRT_OK | (u << 9) | (w << 10) | ((LEVELS - 2) << 11) | (abits << 13);
+}
+
+__device__ __forceinline__ void walk_upper(const DVm &v, uint64_t cr3, uint32_t levels, uint64_t gva, CEnt &c) {
+    if (levels == 5)
+        walk_upper_t<5>(v, cr3, gva, c);
+    else
+        walk_upper_t<4>(v, cr3, gva, c);
+}
+
+__device__ __forceinline__ uint32_t cache_slot(uint64_t key) {
+    uint64_t h = key ^ (key >> 7) ^ (key >> 17) ^ (key >> 29);
+    return (uint32_t)h & (kCacheWays - 1);
+}
+
+// Look up (or fill) the 1 GiB-region cache for the calling lanes with
+// `want` set.  Cross-lane safe: only the lane that wins a slot writes it.
+// Must be called by the whole wavefront (uniform control flow).
+__device__ __forceinline__ void cache_resolve(CEnt *cache, uint32_t *owner, bool want, uint64_t key,
+                                              const DVm &v, uint64_t cr3, uint32_t levels, uint64_t gva, CEnt &c,
+                                              uint32_t &slot, bool &hit) {
+    const int lane = lane_id();
+    hit = false;
+    slot = cache_slot(key);
+    if (want) {
+        c = cache[slot];
+        hit = (c.key == key);
+        if (!hit) {
+            walk_upper(v, cr3, levels, gva, c);
+            c.key = key;
+        }
+    }
+    bool miss = want && !hit;
+    if (miss) owner[slot] = (uint32_t)lane;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (miss && owner[slot] == (uint32_t)lane) cache[slot] = c;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------- copying
+__device__ __forceinline__ u32x4 funnel16(u32x4 a, u32x4 b, uint32_t o) {
+    // bytes [o, o+16) of the 32-byte window a:b (a low); o in 1..15
+    const uint32_t r = o & 3u;
+    u32x4 out;
+    switch (o >> 2) {
+        case 0:
+            out.x = __builtin_amdgcn_alignbyte(a.y, a.x, r);
+            out.y = __builtin_amdgcn_alignbyte(a.z, a.y, r);
+            out.z = __builtin_amdgcn_alignbyte(a.w, a.z, r);
+            out.w = __builtin_amdgcn_alignbyte(b.x, a.w, r);
+            break;
+        case 1:
+            out.x = __builtin_amdgcn_alignbyte(a.z, a.y, r);
+            out.y = __builtin_amdgcn_alignbyte(a.w, a.z, r);
+            out.z = __builtin_amdgcn_alignbyte(b.x, a.w, r);
+            out.w = __builtin_amdgcn_alignbyte(b.y, b.x, r);
+            break;
+        case 2:
+            out.x = __builtin_amdgcn_alignbyte(a.w, a.z, r);
+            out.y = __builtin_amdgcn_alignbyte(b.x, a.w, r);
+            out.z = __builtin_amdgcn_alignbyte(b.y, b.x, r);
+            out.w = __builtin_amdgcn_alignbyte(b.z, b.y, r);
+            break;
+        default:
+            out.x = __builtin_amdgcn_alignbyte(b.x, a.w, r);
+            out.y = __builtin_amdgcn_alignbyte(b.y, b.x, r);
+            out.z = __builtin_amdgcn_alignbyte(b.z, b.y, r);
+            out.w = __builtin_amdgcn_alignbyte(b.w, b.z, r);
+            break;
+    }
+    return out;
+}
+
+__device__ __forceinline__ u32x4 shfl_down1(u32x4 v) {
+    u32x4 r;
+    r.x = (uint32_t)__shfl_down((int)v.x, 1);
+    r.y = (uint32_t)__shfl_down((int)v.y, 1);
+    r.z = (uint32_t)__shfl_down((int)v.z, 1);
+    r.w = (uint32_t)__shfl_down((int)v.w, 1);
+    return r;
+}
+__device__ __forceinline__ u32x4 readlane0(u32x4 v) {
+    u32x4 r;
+    r.x = (uint32_t)__builtin_amdgcn_readlane((int)v.x, 0);
+    r.y = (uint32_t)__builtin_amdgcn_readlane((int)v.y, 0);
+    r.z = (uint32_t)__builtin_amdgcn_readlane((int)v.z, 0);
+    r.w = (uint32_t)__builtin_amdgcn_readlane((int)v.w, 0);
+    return r;
+}
+
+__device__ __forceinline__ void store16(uint8_t *p, u32x4 v, bool nt) {
+    if (nt)
+        __builtin_nontemporal_store(v, (u32x4 *)p);
+    else
+        *(u32x4 *)p = v;
+}
+
+// Whole-wavefront copy of n bytes (all arguments wave-uniform).  Every store
+// writes only bytes of [dst, dst+n); loads stay inside 16-byte blocks that
+// contain at least one source byte.
+__device__ void copy_wave(uint8_t *dst, const uint8_t *src, uint64_t n, bool nt) {
+    const int lane = lane_id();
+    uint64_t h = (16u - ((uintptr_t)dst & 15u)) & 15u;
+    if (h > n) h = n;
+    if ((uint64_t)lane < h) dst[lane] = src[lane];
+    dst += h;
+    src += h;
+    n -= h;
+    const uint64_t m = n >> 4;  // whole 16-byte destination blocks
+    const uint32_t o = (uint32_t)((uintptr_t)src & 15u);
+    const uint8_t *sa = src - o;
+    if (o == 0) {
+        for (uint64_t b0 = 0; b0 < m; b0 += 256) {
+            u32x4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                uint64_t blk = b0 + (uint64_t)(u * 64 + lane);
+                if (blk < m) v[u] = *(const u32x4 *)(sa + 16 * blk);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                uint64_t blk = b0 + (uint64_t)(u * 64 + lane);
+                if (blk < m) store16(dst + 16 * blk, v[u], nt);
+            }
+        }
+    } else {
+        // source blocks 0..m are needed (m+1 blocks, each holds a source byte)
+        for (uint64_t b0 = 0; b0 < m; b0 += 256) {
+            u32x4 cur[4], nxt[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                uint64_t blk = b0 + (uint64_t)(u * 64 + lane);
+                cur[u] = (u32x4){0u, 0u, 0u, 0u};
+                if (blk <= m) cur[u] = *(const u32x4 *)(sa + 16 * blk);
+            }
+            u32x4 tail = (u32x4){0u, 0u, 0u, 0u};
+            if (lane == 63 && b0 + 256 <= m) tail = *(const u32x4 *)(sa + 16 * (b0 + 256));
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                u32x4 down = shfl_down1(cur[u]);
+                u32x4 wrap = (u < 3) ? readlane0(cur[u + 1 < 4 ? u + 1 : 3]) : tail;
+                nxt[u] = (lane == 63) ? wrap : down;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                uint64_t blk = b0 + (uint64_t)(u * 64 + lane);
+                if (blk < m) store16(dst + 16 * blk, funnel16(cur[u], nxt[u], o), nt);
+            }
+        }
+    }
+    const uint64_t t = n & 15u;
+    if ((uint64_t)lane < t) dst[16 * m + lane] = src[16 * m + lane];
+}
+
+// Copy by one lane (short segments).
+__device__ __forceinline__ void copy_lane(uint8_t *dst, const uint8_t *src, uint32_t n) {
+    for (uint32_t i = 0; i < n; ++i) dst[i] = src[i];
+}
+
+// ------------------------------------------------------ translate a group
+// One wavefront, requests [r0, r0+gn) (or one request passed by value).
+// Must be entered by all 64 lanes.
+struct GroupOut {
+    unsigned long long pages, hits, misses, segs, inl, atomics;
+};
+
+template <bool kPlain>
+__device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint32_t gn,
+                              const devirt_request &preq, uint32_t epoch, CEnt *cache, uint32_t *owner,
+                              bool coop_all, DEpochCtr *ctr, GroupOut &st) {
+    const int lane = lane_id();
+    // ---- load and validate the group's requests (lane k owns request k)
+    uint64_t gva = 0, host = 0, cr3 = 0;
+    uint32_t len = 0, asid = 0, dir = 0, vm = 0, levels = 4, code0 = 0, nch = 0;
+    if ((uint32_t)lane < gn) {
+        devirt_request rq;
+        if (kPlain) {
+            rq = preq;
+        } else {
+            const u32x4 *p = (const u32x4 *)(B.reqs + r0 + lane);
+            u32x4 a = p[0], b = p[1];
+            rq.gva = ((uint64_t)a.y << 32) | a.x;
+            rq.host = ((uint64_t)a.w << 32) | a.z;
+            rq.len = b.x;
+            rq.asid = b.y;
+            rq.dir = (uint8_t)(b.z & 0xFF);
+        }
+        gva = rq.gva;
+        host = rq.host;
+        len = rq.len;
+        asid = rq.asid;
+        dir = rq.dir ? 1u : 0u;
+        if (asid >= V.nproc) {
+            code0 = DEVIRT_INVALID;
+        } else {
+            DProc p = V.procs[asid];
+            vm = p.vm;
+            levels = p.levels;
+            cr3 = p.cr3;
+            if (len != 0) {
+                uint64_t lim = levels == 5 ? (1ull << 56) : (1ull << 47);
+                if (gva >= lim || (uint64_t)len > lim - gva)
+                    code0 = DEVIRT_NONCANONICAL;
+                else
+                    nch = (uint32_t)(((gva + len - 1) >> 12) - (gva >> 12) + 1);
+            }
+        }
+    }
+    // ---- wave exclusive prefix sum of page counts
+    uint32_t incl = nch;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = shfl32(incl, lane >= d ? lane - d : lane);
+        if (lane >= d) incl += t;
+    }
+    const uint32_t start = incl - nch;
+    const uint32_t total = shfl32(incl, 63);
+
+    // per-request (owner lane) state
+    uint32_t ff = kNone, fcode = 0, flevel = 0, queued = 0;
+    uint64_t flo = 0;
+
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t c = base + (uint32_t)lane;
+        const bool active = c < total;
+        // owner of page c: the last request whose start <= c
+        int j = 0;
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            int cand = j + s;
+            int idx = cand < (int)gn ? cand : (int)gn - 1;
+            uint32_t sj = shfl32(start, idx);
+            if (cand < (int)gn && sj <= c) j = cand;
+        }
+        const uint64_t j_gva = shfl64(gva, j);
+        const uint64_t j_host = shfl64(host, j);
+        const uint64_t j_cr3 = shfl64(cr3, j);
+        const uint32_t j_len = shfl32(len, j);
+        const uint32_t j_meta = shfl32(dir | (levels << 1) | (vm << 4), j);
+        const uint32_t j_asid = shfl32(asid, j);
+        const uint32_t j_start = shfl32(start, j);
+        const uint32_t j_ff = shfl32(ff, j);
+        const uint32_t j_dir = j_meta & 1u, j_levels = (j_meta >> 1) & 7u, j_vm = j_meta >> 4;
+        const bool work = active && j_ff == kNone;
+
+        const uint32_t k = c - j_start;  // page index inside the request
+        const uint64_t page = (j_gva & ~0xFFFull) + ((uint64_t)k << 12);
+        const uint64_t lo = page > j_gva ? page : j_gva;
+        const uint64_t end = j_gva + j_len;
+        const uint64_t hi = page + 4096 < end ? page + 4096 : end;
+
+        // ---- heads: first lane of each (request, 2 MiB region) run
+        const int prev = lane > 0 ? lane - 1 : 0;
+        const uint32_t p_work = shfl32(work ? 1u : 0u, prev);
+        const uint32_t p_j = shfl32((uint32_t)j, prev);
+        const uint64_t p_lo = shfl64(lo, prev);
+        const bool head = work && (lane == 0 || !p_work || p_j != (uint32_t)j || (p_lo >> 21) != (lo >> 21));
+        const uint64_t head_mask = __ballot(head);
+
+        DVm vmv;
+        if (work) vmv = V.vms[j_vm];
+        // upper levels through the cache (heads only)
+        CEnt ce;
+        ce.info = 0;
+        ce.base = 0;
+        ce.path[0] = ce.path[1] = ce.path[2] = 0;
+        uint32_t cslot;
+        bool chit;
+        const uint64_t key1 = ((uint64_t)j_asid << 27) | (lo >> 30);
+        cache_resolve(cache, owner, head, key1, vmv, j_cr3, j_levels, lo, ce, cslot, chit);
+        if (head) {
+            if (chit)
+                st.hits++;
+            else
+                st.misses++;
+        }
+        // level 2 (heads): rkind 0 = 4 KiB table, 1 = 2 MiB leaf, 2 = 1 GiB leaf
+        uint32_t rcode = 0, rlevel = 0, rkind = 0, ru = 0, rw = 0, rhas = 0;
+        uint64_t rbase = 0, pde_off = 0;
+        if (head) {
+            rcode = ci_code(ce.info);
+            rlevel = ci_level(ce.info);
+            ru = ci_u(ce.info);
+            rw = ci_w(ce.info);
+            if (rcode == 0) {
+                if (ci_leaf(ce.info)) {
+                    rkind = 2;
+                    rbase = ce.base;
+                } else {
+                    uint64_t th;
+                    if (!slot_lookup(vmv, ce.base, th)) {
+                        rcode = DEVIRT_NO_MEMSLOT;
+                        rlevel = 2;
+                    } else {
+                        pde_off = th + 8 * ((lo >> 21) & 511);
+                        uint64_t e = load_entry(vmv.arena, pde_off);
+                        rhas = (e & kA) ? 1u : 0u;
+                        if (e & kD) rhas |= 2u;
+                        if (!(e & kP)) {
+                            rcode = DEVIRT_NOT_PRESENT;
+                            rlevel = 2;
+                        } else {
+                            ru &= (uint32_t)(e >> 2) & 1u;
+                            rw &= (uint32_t)(e >> 1) & 1u;
+                            if (e & kPS) {
+                                if (e & 0x1FE000ull) {  // bits 20:13 of a 2 MiB leaf are reserved
+                                    rcode = DEVIRT_RESERVED;
+                                    rlevel = 2;
+                                } else {
+                                    rkind = 1;
+                                    rbase = e & kAddrMask & ~((1ull << 21) - 1);
+                                }
+                            } else {
+                                uint64_t pt;
+                                if (!slot_lookup(vmv, e & kAddrMask, pt)) {
+                                    rcode = DEVIRT_NO_MEMSLOT;
+                                    rlevel = 1;
+                                } else {
+                                    rkind = 0;
+                                    rbase = pt;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // ---- broadcast the region result from each head to its lanes
+        const int h = 63 - __clzll(head_mask & mask_le(lane));
+        const int hsrc = (head_mask & mask_le(lane)) ? h : lane;
+        const uint32_t r_packed =
+            shfl32(rcode | (rlevel << 4) | (rkind << 8) | (ru << 10) | (rw << 11) | (rhas << 12), hsrc);
+        const uint64_t r_base = shfl64(rbase, hsrc);
+
+        // ---- leaf step (every working lane)
+        uint32_t code = 0, level = 0, shift = 0;
+        uint64_t gpa = 0, hpa = 0, leaf_off = 0, leaf_e = 0;
+        if (work) {
+            code = r_packed & 15u;
+            level = (r_packed >> 4) & 15u;
+            const uint32_t kind = (r_packed >> 8) & 3u;
+            uint32_t u = (r_packed >> 10) & 1u, w = (r_packed >> 11) & 1u;
+            uint32_t leaf_level = 0;
+            uint64_t frame = 0;
+            if (code == 0) {
+                if (kind == 0) {
+                    leaf_off = r_base + 8 * ((lo >> 12) & 511);
+                    leaf_e = load_entry(vmv.arena, leaf_off);
+                    if (!(leaf_e & kP)) {
+                        code = DEVIRT_NOT_PRESENT;
+                        level = 1;
+                    } else {
+                        u &= (uint32_t)(leaf_e >> 2) & 1u;
+                        w &= (uint32_t)(leaf_e >> 1) & 1u;
+                        frame = leaf_e & kAddrMask;
+                        shift = 12;
+                        leaf_level = 1;
+                    }
+                } else {
+                    frame = r_base;
+                    shift = kind == 1 ? 21 : 30;
+                    leaf_level = kind == 1 ? 2 : 3;
+                }
+            }
+            if (code == 0) {
+                gpa = frame | (lo & ((1ull << shift) - 1));
+                if (!u) {
+                    code = DEVIRT_PROT_USER;
+                    level = leaf_level;
+                } else if (j_dir && !w) {
+                    code = DEVIRT_PROT_WRITE;
+                    level = leaf_level;
+                } else if (!slot_lookup(vmv, gpa, hpa)) {
+                    code = DEVIRT_NO_MEMSLOT;
+                    level = 0;
+                }
+            }
+        }
+        st.pages += __popcll(__ballot(work));
+
+        // ---- first fault per request, pages that will be copied
+        const uint64_t fmask = __ballot(work && code != 0);
+        const uint32_t jfirst = j_start > base ? j_start - base : 0u;  // first lane of request j
+        const uint64_t jmask = mask_le(lane) & ~mask_lt((int)jfirst);
+        const bool copied = work && code == 0 && (fmask & jmask) == 0;
+        const uint64_t cmask = __ballot(copied);
+        const uint64_t cto_mask = __ballot(copied && j_dir);
+
+        // owner lanes pick up their request's first fault in this pass
+        {
+            const bool own = (uint32_t)lane < gn && nch > 0 && ff == kNone;
+            uint64_t my = 0;
+            if (own) {
+                uint32_t a = start > base ? start - base : 0u;
+                uint32_t b = start + nch - base;  // may exceed 64
+                if (start < base + 64 && start + nch > base) {
+                    uint64_t hi_m = b >= 64 ? ~0ull : ((1ull << b) - 1);
+                    my = fmask & hi_m & ~mask_lt((int)a);
+                }
+            }
+            const int f = my ? (__ffsll((unsigned long long)my) - 1) : lane;
+            const uint32_t f_code = shfl32(code, f);
+            const uint32_t f_level = shfl32(level, f);
+            const uint64_t f_lo = shfl64(lo, f);
+            if (own && my) {
+                ff = base + (uint32_t)f - start;
+                fcode = f_code;
+                flevel = f_level;
+                flo = f_lo;
+            }
+        }
+
+        // ---- A/D: leaf of 4 KiB pages per lane; region-level entries by heads
+        uint32_t atomics = 0;
+        if (copied && leaf_off) {
+            const uint32_t want = (uint32_t)kA | (j_dir ? (uint32_t)kD : 0u);
+            if (((uint32_t)leaf_e & want) != want) {
+                or_entry(vmv.arena, leaf_off, want);
+                atomics++;
+            }
+        }
+        if (head) {
+            const int nh_bit = __ffsll((unsigned long long)(head_mask & ~mask_le(lane)));
+            const int nh = nh_bit ? nh_bit - 1 : 64;
+            const uint64_t rmask = mask_lt(nh) & ~mask_lt(lane);
+            if (cmask & rmask) {
+                const bool rto = (cto_mask & rmask) != 0;
+                // level-2 entry (a table pointer or a 2 MiB leaf)
+                if (rkind == 0 || rkind == 1) {
+                    uint32_t want = (uint32_t)kA | ((rkind == 1 && rto) ? (uint32_t)kD : 0u);
+                    if ((rhas & want) != want) {
+                        or_entry(vmv.arena, pde_off, want);
+                        atomics++;
+                    }
+                }
+                // levels 5..3 from the cached walk
+                const uint32_t np = ci_np(ce.info), ab = ci_abits(ce.info);
+                uint32_t mark = 0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if ((uint32_t)i < np) {
+                        uint32_t want = (uint32_t)kA;
+                        const bool is_leaf = rkind == 2 && (uint32_t)i + 1 == np;
+                        bool need = !((ab >> i) & 1u);
+                        if (is_leaf && rto) {
+                            want |= (uint32_t)kD;
+                            need = need || !(ce.info & kCiDbit);
+                        }
+                        if (need) {
+                            or_entry(vmv.arena, ce.path[i], want);
+                            atomics++;
+                        }
+                        mark |= 1u << (13 + i);
+                        if (is_leaf && rto) mark |= kCiDbit;
+                    }
+                }
+                if (cache[cslot].key == key1) atomicOr(&cache[cslot].info, mark);
+            }
+        }
+        st.atomics += atomics;
+
+        // ---- copy segments: runs of pages whose guest side is contiguous
+        uint8_t *const arena = work ? vmv.arena : nullptr;
+        const uint64_t gptr = (uint64_t)(uintptr_t)arena + hpa;
+        const uint64_t hptr = j_host + (lo - j_gva);
+        const uint32_t nbytes = (uint32_t)(hi - lo);
+        const uint32_t p_copied = shfl32(copied ? 1u : 0u, prev);
+        const uint64_t p_gptr = shfl64(gptr, prev);
+        const uint32_t p_n = shfl32(nbytes, prev);
+        const bool cont = copied && lane > 0 && p_copied && p_j == (uint32_t)j && p_gptr + p_n == gptr &&
+                          (k % B.seg_chunks) != 0;
+        const bool rhead = copied && !cont;
+        const uint64_t cont_mask = __ballot(cont);
+        // run [lane, e): e = first later lane that does not continue the run
+        const int e_bit = __ffsll((unsigned long long)(~cont_mask & ~mask_le(lane)));
+        const int e = e_bit ? e_bit - 1 : 64;
+        const int last = rhead ? e - 1 : lane;
+        const uint64_t l_end = shfl64(lo + nbytes, last);
+        const uint32_t run = rhead ? (uint32_t)(l_end - lo) : 0u;
+        uint64_t src = 0, dst = 0;
+        if (rhead) {
+            src = j_dir ? hptr : gptr;
+            dst = j_dir ? gptr : hptr;
+        }
+        const bool small = rhead && !coop_all && run <= B.inline_bytes;
+        if (small) copy_lane((uint8_t *)dst, (const uint8_t *)src, run);
+        const bool want_q = rhead && !small && !coop_all;
+        const uint64_t qmask = __ballot(want_q);
+        bool coop = rhead && coop_all;
+        uint32_t q_ok = 0;
+        if (qmask) {
+            uint32_t qbase = 0;
+            if (lane == 0) qbase = atomicAdd(&ctr[epoch].nseg, (uint32_t)__popcll(qmask));
+            qbase = shfl32(qbase, 0);
+            if (want_q) {
+                const uint64_t pos = (uint64_t)qbase + (uint64_t)__popcll(qmask & mask_lt(lane));
+                if (pos < B.seg_cap) {
+                    DSeg sg;
+                    sg.src = src;
+                    sg.dst = dst;
+                    sg.len = run;
+                    sg.req = (uint32_t)(r0 + (uint64_t)j);
+                    sg.pad = 0;
+                    B.segs[pos] = sg;
+                    q_ok = 1;
+                } else {
+                    coop = true;  // queue full: the wavefront copies it below
+                }
+            }
+        }
+        st.segs += __popcll(__ballot(q_ok != 0));
+        st.inl += __popcll(__ballot(small));
+        // per-request count of queued segments (for completion times)
+        {
+            const uint64_t okm = __ballot(q_ok != 0);
+            if ((uint32_t)lane < gn && nch > 0 && start < base + 64 && start + nch > base) {
+                uint32_t a = start > base ? start - base : 0u;
+                uint32_t b = start + nch - base;
+                uint64_t hi_m = b >= 64 ? ~0ull : ((1ull << b) - 1);
+                queued += (uint32_t)__popcll(okm & hi_m & ~mask_lt((int)a));
+            }
+        }
+        uint64_t cm = __ballot(coop);
+        while (cm) {
+            const int l = __ffsll((unsigned long long)cm) - 1;
+            const uint64_t s = uniform_u64(shfl64(src, l)), d = uniform_u64(shfl64(dst, l));
+            const uint32_t n = uniform_u32(shfl32(run, l));
+            copy_wave((uint8_t *)d, (const uint8_t *)s, n, B.nontemporal != 0);
+            cm &= cm - 1;
+        }
+    }
+
+    // ---- results (owner lanes)
+    if ((uint32_t)lane < gn) {
+        devirt_result r;
+        r.pad = 0;
+        if (code0) {
+            r.bytes_done = 0;
+            r.fault_gva = gva;
+            r.code = code0;
+            r.level = 0;
+        } else if (ff == kNone) {
+            r.bytes_done = len;
+            r.fault_gva = 0;
+            r.code = 0;
+            r.level = 0;
+        } else {
+            r.bytes_done = flo - gva;
+            r.fault_gva = flo;
+            r.code = fcode;
+            r.level = (uint16_t)flevel;
+        }
+        B.res[kPlain ? 0 : r0 + lane] = r;
+        if (!kPlain && B.t_done) {
+            B.pending[r0 + lane] = queued;
+            if (queued == 0) B.t_done[r0 + lane] = now_ns(B);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+__global__ void k_reset(DBatch b, uint32_t n_epochs) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *b.t0 = wall_clock64();
+    for (; i < n_epochs; i += gridDim.x * blockDim.x) {
+        b.ctr[i].group_cursor = 0;
+        b.ctr[i].nseg = 0;
+        b.ctr[i].pad0 = 0;
+        b.ctr[i].pad1 = 0;
+    }
+}
+
+__device__ __forceinline__ void flush_counters(DCounters *c, const GroupOut &st) {
+    if (!c) return;
+    unsigned long long v[6] = {st.pages, st.hits, st.misses, st.segs, st.inl, st.atomics};
+    // lane-local partial sums -> one atomic per counter per wavefront
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        unsigned long long x = v[i];
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+        v[i] = x;
+    }
+    if (lane_id() == 0) {
+        atomicAdd(&c->pages_walked, v[0] / 64);
+        atomicAdd(&c->cache_hits, v[1]);
+        atomicAdd(&c->cache_misses, v[2]);
+        atomicAdd(&c->segments, v[3] / 64);
+        atomicAdd(&c->inline_segments, v[4] / 64);
+        atomicAdd(&c->ad_atomics, v[5]);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uint64_t r0, uint64_t r1,
+                                                           uint32_t epoch) {
+    extern __shared__ uint8_t smem[];
+    const int wave = threadIdx.x >> 6;
+    CEnt *cache = (CEnt *)smem + wave * kCacheWays;
+    uint32_t *owner = (uint32_t *)((CEnt *)smem + (blockDim.x >> 6) * kCacheWays) + wave * kCacheWays;
+    if ((threadIdx.x & 63) < kCacheWays) cache[threadIdx.x & 63].key = ~0ull;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t n = r1 - r0;
+    const uint32_t G = b.group;
+    const uint64_t ngroups = (n + G - 1) / G;
+    GroupOut st = {0, 0, 0, 0, 0, 0};
+    devirt_request dummy = {};
+    for (;;) {
+        uint32_t g = 0;
+        if (lane_id() == 0) g = atomicAdd(&b.ctr[epoch].group_cursor, 1u);
+        g = uniform_u32(shfl32(g, 0));
+        if ((uint64_t)g >= ngroups) break;
+        const uint64_t gs = r0 + (uint64_t)g * G;
+        const uint32_t gn = (uint32_t)((r1 - gs) < G ? (r1 - gs) : G);
+        process_group<false>(v, b, gs, gn, dummy, epoch, cache, owner, false, b.ctr, st);
+    }
+    flush_counters(b.counters, st);
+}
+
+__global__ void __launch_bounds__(1024) k_copy(DBatch b, uint32_t epoch) {
+    const uint32_t nq = b.ctr[epoch].nseg;
+    const uint64_t nseg = nq < b.seg_cap ? nq : b.seg_cap;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t w0 = uniform_u64((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const bool nt = b.nontemporal != 0;
+    for (uint64_t s = w0; s < nseg; s += waves) {
+        const DSeg sg = b.segs[s];
+        copy_wave((uint8_t *)uniform_u64(sg.dst), (const uint8_t *)uniform_u64(sg.src), uniform_u32(sg.len), nt);
+        if (b.t_done && lane_id() == 0) {
+            uint32_t old = atomicSub(&b.pending[sg.req], 1u);
+            if (old == 1) b.t_done[sg.req] = now_ns(b);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) k_plain(DView v, DBatch b, devirt_request req, int inline_copy) {
+    __shared__ CEnt cache[kCacheWays];
+    __shared__ uint32_t owner[kCacheWays];
+    if (threadIdx.x < kCacheWays) cache[threadIdx.x].key = ~0ull;
+    if (threadIdx.x == 0) {
+        b.ctr[0].nseg = 0;
+        *b.t0 = wall_clock64();
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    GroupOut st = {0, 0, 0, 0, 0, 0};
+    process_group<true>(v, b, 0, 1, req, 0, cache, owner, inline_copy != 0, b.ctr, st);
+    flush_counters(b.counters, st);
+}
+
+// translate-only: one lane per address
+__global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint64_t *gvas, uint64_t n,
+                                               uint32_t flags, devirt_xlat *out, DCounters *counters) {
+    extern __shared__ uint8_t smem[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    CEnt *cache = (CEnt *)smem + wave * kCacheWays;
+    uint32_t *owner = (uint32_t *)((CEnt *)smem + (blockDim.x >> 6) * kCacheWays) + wave * kCacheWays;
+    if (lane < kCacheWays) cache[lane].key = ~0ull;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const bool valid_asid = asid < v.nproc;
+    DProc p = {0, 0, 4};
+    DVm vmv = {};
+    if (valid_asid) {
+        p = v.procs[asid];
+        vmv = v.vms[p.vm];
+    }
+    const uint64_t lim = p.levels == 5 ? (1ull << 56) : (1ull << 47);
+    const bool write = (flags & DEVIRT_XLAT_WRITE) != 0;
+    const bool set_ad = (flags & DEVIRT_XLAT_SET_AD) != 0;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    unsigned long long hits = 0, misses = 0, atom = 0;
+    for (uint64_t b0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; b0 < n; b0 += waves * 64) {
+        const uint64_t i = b0 + lane;
+        const bool in = i < n;
+        const uint64_t gva = in ? gvas[i] : 0;
+        devirt_xlat x;
+        x.gpa = 0;
+        x.hpa = 0;
+        x.code = 0;
+        x.level = 0;
+        x.page_shift = 0;
+        x.vm = valid_asid ? (uint16_t)p.vm : (uint16_t)0xFFFF;
+        bool go = in && valid_asid;
+        if (in && !valid_asid) x.code = DEVIRT_INVALID;
+        if (go && gva >= lim) {
+            x.code = DEVIRT_NONCANONICAL;
+            go = false;
+        }
+        CEnt ce;
+        ce.info = 0;
+        ce.path[0] = ce.path[1] = ce.path[2] = 0;
+        ce.base = 0;
+        uint32_t cslot;
+        bool chit;
+        cache_resolve(cache, owner, go, ((uint64_t)asid << 27) | (gva >> 30), vmv, p.cr3, p.levels, gva, ce, cslot,
+                      chit);
+        if (go) {
+            if (chit)
+                hits++;
+            else
+                misses++;
+            uint32_t code = ci_code(ce.info), level = ci_level(ce.info);
+            uint32_t u = ci_u(ce.info), w = ci_w(ce.info), leaf_level = 0, shift = 0;
+            uint64_t frame = 0, pde_off = 0, pte_off = 0, e2 = 0, e1 = 0;
+            if (code == 0) {
+                if (ci_leaf(ce.info)) {
+                    frame = ce.base;
+                    shift = 30;
+                    leaf_level = 3;
+                } else {
+                    uint64_t th;
+                    if (!slot_lookup(vmv, ce.base, th)) {
+                        code = DEVIRT_NO_MEMSLOT;
+                        level = 2;
+                    } else {
+                        pde_off = th + 8 * ((gva >> 21) & 511);
+                        e2 = load_entry(vmv.arena, pde_off);
+                        if (!(e2 & kP)) {
+                            code = DEVIRT_NOT_PRESENT;
+                            level = 2;
+                        } else {
+                            u &= (uint32_t)(e2 >> 2) & 1u;
+                            w &= (uint32_t)(e2 >> 1) & 1u;
+                            if (e2 & kPS) {
+                                if (e2 & 0x1FE000ull) {
+                                    code = DEVIRT_RESERVED;
+                                    level = 2;
+                                } else {
+                                    frame = e2 & kAddrMask & ~((1ull << 21) - 1);
+                                    shift = 21;
+                                    leaf_level = 2;
+                                }
+                            } else {
+                                uint64_t pt;
+                                if (!slot_lookup(vmv, e2 & kAddrMask, pt)) {
+                                    code = DEVIRT_NO_MEMSLOT;
+                                    level = 1;
+                                } else {
+                                    pte_off = pt + 8 * ((gva >> 12) & 511);
+                                    e1 = load_entry(vmv.arena, pte_off);
+                                    if (!(e1 & kP)) {
+                                        code = DEVIRT_NOT_PRESENT;
+                                        level = 1;
+                                    } else {
+                                        u &= (uint32_t)(e1 >> 2) & 1u;
+                                        w &= (uint32_t)(e1 >> 1) & 1u;
+                                        frame = e1 & kAddrMask;
+                                        shift = 12;
+                                        leaf_level = 1;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            uint64_t gpa = 0, hpa = 0;
+            if (code == 0) {
+                gpa = frame | (gva & ((1ull << shift) - 1));
+                x.gpa = gpa;
+                x.page_shift = (uint8_t)shift;
+                if (!u) {
+                    code = DEVIRT_PROT_USER;
+                    level = leaf_level;
+                } else if (write && !w) {
+                    code = DEVIRT_PROT_WRITE;
+                    level = leaf_level;
+                } else if (!slot_lookup(vmv, gpa, hpa)) {
+                    code = DEVIRT_NO_MEMSLOT;
+                    level = 0;
+                }
+            }
+            x.code = code;
+            x.level = (uint8_t)level;
+            if (code == 0) {
+                x.hpa = hpa;
+                if (set_ad) {
+                    const uint32_t np = ci_np(ce.info), ab = ci_abits(ce.info);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        if ((uint32_t)q >= np) continue;
+                        uint32_t want = (uint32_t)kA;
+                        bool need = !((ab >> q) & 1u);
+                        if (leaf_level == 3 && (uint32_t)q + 1 == np && write) {
+                            want |= (uint32_t)kD;
+                            need = need || !(ce.info & kCiDbit);
+                        }
+                        if (need) {
+                            or_entry(vmv.arena, ce.path[q], want);
+                            atom++;
+                        }
+                    }
+                    if (leaf_level <= 2) {
+                        uint32_t want = (uint32_t)kA | ((leaf_level == 2 && write) ? (uint32_t)kD : 0u);
+                        if (((uint32_t)e2 & want) != want) {
+                            or_entry(vmv.arena, pde_off, want);
+                            atom++;
+                        }
+                    }
+                    if (leaf_level == 1) {
+                        uint32_t want = (uint32_t)kA | (write ? (uint32_t)kD : 0u);
+                        if (((uint32_t)e1 & want) != want) {
+                            or_entry(vmv.arena, pte_off, want);
+                            atom++;
+                        }
+                    }
+                }
+            }
+        }
+        if (in) out[i] = x;
+    }
+    if (counters) {
+        GroupOut st = {0, hits, misses, 0, 0, atom};
+        flush_counters(counters, st);
+    }
+}
+
+// ------------------------------------------------------------ fault list
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *lds, uint32_t &total) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = shfl32(incl, lane >= d ? lane - d : lane);
+        if (lane >= d) incl += t;
+    }
+    if (lane == 63) lds[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        uint32_t s = lds[w];
+        if (w < wave) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return before + incl - x;
+}
+
+__global__ void __launch_bounds__(256) k_fault_count(const devirt_result *res, uint64_t n, uint32_t *tile_cnt) {
+    __shared__ uint32_t lds[16];
+    const uint64_t t = blockIdx.x;
+    uint32_t c = 0;
+    for (int q = 0; q < 4; ++q) {
+        uint64_t i = t * kFaultTile + (uint64_t)threadIdx.x * 4 + q;
+        if (i < n && res[i].code != 0) c++;
+    }
+    uint32_t tot;
+    block_exclusive_scan(c, lds, tot);
+    if (threadIdx.x == 0) tile_cnt[t] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_fault_scan(uint32_t *tile_cnt, uint64_t ntiles, uint64_t *n_faults) {
+    __shared__ uint32_t lds[16];
+    uint64_t carry = 0;
+    for (uint64_t b0 = 0; b0 < ntiles; b0 += blockDim.x) {
+        const uint64_t i = b0 + threadIdx.x;
+        const uint32_t x = i < ntiles ? tile_cnt[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(x, lds, tot);
+        if (i < ntiles) tile_cnt[i] = (uint32_t)(carry + ex);
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && n_faults) *n_faults = carry;
+}
+
+__global__ void __launch_bounds__(256) k_fault_scatter(const devirt_result *res, uint64_t n, const uint32_t *tile_off,
+                                                       devirt_fault *faults) {
+    __shared__ uint32_t lds[16];
+    const uint64_t t = blockIdx.x;
+    uint32_t flags = 0, c = 0;
+    for (int q = 0; q < 4; ++q) {
+        uint64_t i = t * kFaultTile + (uint64_t)threadIdx.x * 4 + q;
+        if (i < n && res[i].code != 0) {
+            flags |= 1u << q;
+            c++;
+        }
+    }
+    uint32_t tot;
+    uint32_t pos = tile_off[t] + block_exclusive_scan(c, lds, tot);
+    for (int q = 0; q < 4; ++q) {
+        if (flags & (1u << q)) {
+            uint64_t i = t * kFaultTile + (uint64_t)threadIdx.x * 4 + q;
+            devirt_result r = res[i];
+            devirt_fault f;
+            f.req_index = i;
+            f.fault_gva = r.fault_gva;
+            f.code = r.code;
+            f.level = r.level;
+            f.pad = 0;
+            faults[pos++] = f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+static size_t wave_lds(int block) {
+    return (size_t)(block / 64) * kCacheWays * (sizeof(CEnt) + sizeof(uint32_t));
+}
+
+hipError_t launch_reset(hipStream_t s, DBatch b, uint32_t n_epochs) {
+    uint32_t blocks = (n_epochs + 255) / 256;
+    if (blocks == 0) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, s, b, n_epochs);
+    return hipGetLastError();
+}
+
+hipError_t launch_translate_groups(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0, uint64_t r1,
+                                   uint32_t epoch) {
+    hipLaunchKernelGGL(k_translate_groups, dim3(grid), dim3(block), wave_lds(block), s, v, b, r0, r1, epoch);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t s, int grid, int block, DBatch b, uint32_t epoch) {
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(block), 0, s, b, epoch);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(hipStream_t s, DView v, DBatch b, devirt_request req, int inline_copy) {
+    hipLaunchKernelGGL(k_plain, dim3(1), dim3(64), 0, s, v, b, req, inline_copy);
+    return hipGetLastError();
+}
+
+hipError_t launch_xlat(hipStream_t s, int grid, int block, DView v, uint32_t asid, const uint64_t *gva, uint64_t n,
+                       uint32_t flags, devirt_xlat *out, DCounters *counters) {
+    hipLaunchKernelGGL(k_xlat, dim3(grid), dim3(block), wave_lds(block), s, v, asid, gva, n, flags, out, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_fault_count(hipStream_t s, const devirt_result *res, uint64_t n, uint32_t *tile_cnt) {
+    uint64_t tiles = (n + kFaultTile - 1) / kFaultTile;
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fault_count, dim3((unsigned)tiles), dim3(256), 0, s, res, n, tile_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fault_scan(hipStream_t s, uint32_t *tile_cnt, uint64_t ntiles, uint64_t *n_faults) {
+    hipLaunchKernelGGL(k_fault_scan, dim3(1), dim3(1024), 0, s, tile_cnt, ntiles, n_faults);
+    return hipGetLastError();
+}
+
+hipError_t launch_fault_scatter(hipStream_t s, const devirt_result *res, uint64_t n, const uint32_t *tile_off,
+                                devirt_fault *faults) {
+    uint64_t tiles = (n + kFaultTile - 1) / kFaultTile;
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fault_scatter, dim3((unsigned)tiles), dim3(256), 0, s, res, n, tile_off, faults);
+    return hipGetLastError();
+}
+
+}  // namespace dv

@@ -1,0 +1,766 @@
+// Host runtime of the devirt C ABI: device tables (arenas, memslots with a
+// 2 MiB direct index, processes), per-stream workspaces, batch enqueue with
+// HIP-graph capture and replay, profiling, configuration and autotuning.
+#include <errno.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "dv_internal.h"
+#include "runtime.h"
+
+using namespace dv;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+int dv_fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+extern "C" const char *devirt_last_error(void) { return g_err.c_str(); }
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return dv_fail(-EIO, "%s: %s", #x, hipGetErrorString(e_));   \
+    } while (0)
+
+// ------------------------------------------------------------------ config
+static devirt_config default_config() {
+    devirt_config c;
+    c.group = 32;
+    c.seg_chunks = 16;
+    c.xlat_wg = 256;
+    c.xlat_wgs_per_cu = 8;
+    c.copy_wg = 256;
+    c.copy_wgs_per_cu = 8;
+    c.nontemporal = 0;
+    c.inline_bytes = 0;
+    c.use_graph = 1;
+    c.fused = 0;
+    return c;
+}
+
+static int check_config(const devirt_config &c) {
+    if (c.group < 1 || c.group > 64) return dv_fail(-EINVAL, "group must be 1..64");
+    if (c.seg_chunks < 1 || c.seg_chunks > 64) return dv_fail(-EINVAL, "seg_chunks must be 1..64");
+    if (c.xlat_wg < 64 || c.xlat_wg > 256 || c.xlat_wg % 64) return dv_fail(-EINVAL, "xlat_wg must be 64..256, x64");
+    if (c.copy_wg < 64 || c.copy_wg > 1024 || c.copy_wg % 64) return dv_fail(-EINVAL, "copy_wg must be 64..1024, x64");
+    if (c.xlat_wgs_per_cu < 1 || c.xlat_wgs_per_cu > 64) return dv_fail(-EINVAL, "xlat_wgs_per_cu must be 1..64");
+    if (c.copy_wgs_per_cu < 1 || c.copy_wgs_per_cu > 64) return dv_fail(-EINVAL, "copy_wgs_per_cu must be 1..64");
+    if (c.nontemporal > 1 || c.use_graph > 1) return dv_fail(-EINVAL, "nontemporal/use_graph must be 0 or 1");
+    if (c.inline_bytes > 256) return dv_fail(-EINVAL, "inline_bytes must be <= 256");
+    if (c.fused > 1) return dv_fail(-EINVAL, "fused must be 0 or 1");
+    return 0;
+}
+
+// ------------------------------------------------------------------ context
+Workspace::~Workspace() {
+    for (auto &g : graphs) hipGraphExecDestroy(g.exec);
+    hipFree(segs);
+    hipFree(ctr);
+    hipFree(pending);
+    hipFree(tiles);
+    hipFree(t0);
+}
+
+static int set_dev(devirt_ctx *c) {
+    HIPCHK(hipSetDevice(c->device));
+    return 0;
+}
+
+extern "C" int devirt_open(int hip_device, devirt_ctx **out) {
+    if (!out) return dv_fail(-EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev) return dv_fail(-EINVAL, "no HIP device %d (%d present)", hip_device, ndev);
+    HIPCHK(hipSetDevice(hip_device));
+    devirt_ctx *c = new devirt_ctx();
+    c->device = hip_device;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess || v <= 0) {
+        delete c;
+        return dv_fail(-EIO, "cannot read the CU count");
+    }
+    c->cus = v;
+    v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, hip_device) != hipSuccess || v <= 0) v = 100000;
+    c->wall_khz = (uint64_t)v;
+    c->cfg = default_config();
+    if (hipMalloc(&c->d_counters, sizeof(DCounters)) != hipSuccess) {
+        delete c;
+        return dv_fail(-ENOMEM, "hipMalloc counters");
+    }
+    hipMemset(c->d_counters, 0, sizeof(DCounters));
+    *out = c;
+    return 0;
+}
+
+extern "C" int devirt_close(devirt_ctx *c) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (auto &kv : c->ws) delete kv.second;
+    for (auto &vm : c->vms) {
+        hipFree(vm.arena);
+        hipFree(vm.d_index);
+        hipFree(vm.d_slots);
+    }
+    hipFree(c->d_vms);
+    hipFree(c->d_procs);
+    hipFree(c->d_counters);
+    for (auto &p : c->prof) {
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    delete c;
+    return 0;
+}
+
+// Re-upload the VM table (after a VM or memslot change).  Device must be idle.
+static int upload_vms(devirt_ctx *c) {
+    std::vector<DVm> h(c->vms.size());
+    for (size_t i = 0; i < c->vms.size(); ++i) {
+        const VmHost &v = c->vms[i];
+        h[i].arena = v.arena;
+        h[i].arena_bytes = v.bytes;
+        h[i].index = v.d_index;
+        h[i].slots = v.d_slots;
+        h[i].index_len = v.index_len;
+        h[i].nslots = v.nsorted;
+        h[i].index_complete = v.index_complete;
+        h[i].pad = 0;
+    }
+    if (c->vms.size() > c->d_vms_cap) {
+        size_t cap = std::max<size_t>(16, c->vms.size() * 2);
+        DVm *p = nullptr;
+        HIPCHK(hipMalloc(&p, cap * sizeof(DVm)));
+        hipFree(c->d_vms);
+        c->d_vms = p;
+        c->d_vms_cap = cap;
+    }
+    if (!h.empty()) HIPCHK(hipMemcpy(c->d_vms, h.data(), h.size() * sizeof(DVm), hipMemcpyHostToDevice));
+    c->tables_version++;
+    return 0;
+}
+
+static int upload_procs(devirt_ctx *c) {
+    if (c->procs.size() > c->d_procs_cap) {
+        size_t cap = std::max<size_t>(64, c->procs.size() * 2);
+        DProc *p = nullptr;
+        HIPCHK(hipMalloc(&p, cap * sizeof(DProc)));
+        hipFree(c->d_procs);
+        c->d_procs = p;
+        c->d_procs_cap = cap;
+    }
+    if (!c->procs.empty())
+        HIPCHK(hipMemcpy(c->d_procs, c->procs.data(), c->procs.size() * sizeof(DProc), hipMemcpyHostToDevice));
+    c->tables_version++;
+    return 0;
+}
+
+extern "C" int devirt_vm_create(devirt_ctx *c, uint64_t arena_bytes, uint32_t *vm) {
+    if (!c || !vm) return dv_fail(-EINVAL, "NULL argument");
+    if (arena_bytes == 0 || (arena_bytes & 4095)) return dv_fail(-EINVAL, "arena_bytes must be a non-zero multiple of 4096");
+    if (c->vms.size() >= 0xFFFF) return dv_fail(-EINVAL, "too many VMs");
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipDeviceSynchronize());
+    VmHost v;
+    if (hipMalloc(&v.arena, arena_bytes) != hipSuccess) return dv_fail(-ENOMEM, "cannot allocate a %llu-byte arena",
+                                                                     (unsigned long long)arena_bytes);
+    if (hipMemset(v.arena, 0, arena_bytes) != hipSuccess) {
+        hipFree(v.arena);
+        return dv_fail(-EIO, "hipMemset arena");
+    }
+    v.bytes = arena_bytes;
+    c->vms.push_back(v);
+    int rc = upload_vms(c);
+    if (rc) return rc;
+    *vm = (uint32_t)(c->vms.size() - 1);
+    return 0;
+}
+
+extern "C" int devirt_vm_arena(devirt_ctx *c, uint32_t vm, void **dev_ptr, uint64_t *bytes) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (vm >= c->vms.size()) return dv_fail(-ENOENT, "no VM %u", vm);
+    if (dev_ptr) *dev_ptr = c->vms[vm].arena;
+    if (bytes) *bytes = c->vms[vm].bytes;
+    return 0;
+}
+
+static int vm_copy(devirt_ctx *c, uint32_t vm, uint64_t off, void *host_or_dev, uint64_t bytes, bool write) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (vm >= c->vms.size()) return dv_fail(-ENOENT, "no VM %u", vm);
+    if (bytes == 0) return 0;
+    if (!host_or_dev) return dv_fail(-EINVAL, "NULL buffer");
+    const VmHost &v = c->vms[vm];
+    if (off > v.bytes || bytes > v.bytes - off) return dv_fail(-EINVAL, "range leaves the arena");
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipDeviceSynchronize());
+    if (write)
+        HIPCHK(hipMemcpy(v.arena + off, host_or_dev, bytes, hipMemcpyDefault));
+    else
+        HIPCHK(hipMemcpy(host_or_dev, v.arena + off, bytes, hipMemcpyDefault));
+    return 0;
+}
+
+extern "C" int devirt_vm_write(devirt_ctx *c, uint32_t vm, uint64_t off, const void *src, uint64_t bytes) {
+    return vm_copy(c, vm, off, const_cast<void *>(src), bytes, true);
+}
+extern "C" int devirt_vm_read(devirt_ctx *c, uint32_t vm, uint64_t off, void *dst, uint64_t bytes) {
+    return vm_copy(c, vm, off, dst, bytes, false);
+}
+
+// Build the sorted slot list and the 2 MiB direct index of one VM.
+static constexpr uint64_t kBlk = 2ull << 20;
+static constexpr uint64_t kIndexCap = 1ull << 20;  // blocks: covers 2 TiB of GPA
+
+int build_slot_index(const VmHost &v, std::vector<DSlot> &sorted, std::vector<uint64_t> &index, uint32_t &complete) {
+    sorted.clear();
+    for (const auto &s : v.slots)
+        if (s.used) sorted.push_back(DSlot{s.gpa, s.gpa + s.bytes, s.off});
+    std::sort(sorted.begin(), sorted.end(), [](const DSlot &a, const DSlot &b) { return a.gpa < b.gpa; });
+    uint64_t max_end = sorted.empty() ? 0 : sorted.back().end;
+    uint64_t nblk = (max_end + kBlk - 1) / kBlk;
+    complete = 1;
+    if (nblk > kIndexCap) {
+        nblk = kIndexCap;
+        complete = 0;
+    }
+    index.assign(nblk, 0);
+    for (const auto &s : sorted) {
+        uint64_t b0 = s.gpa / kBlk, b1 = (s.end - 1) / kBlk;
+        for (uint64_t b = b0; b <= b1 && b < nblk; ++b) {
+            uint64_t lo = b * kBlk, hi = lo + kBlk;
+            if (s.gpa <= lo && s.end >= hi)
+                index[b] = (s.arena_off - s.gpa) | 2ull;
+            else
+                index[b] = 1ull;
+        }
+    }
+    return 0;
+}
+
+extern "C" int devirt_memslot_set(devirt_ctx *c, uint32_t vm, uint32_t slot, uint64_t gpa, uint64_t bytes,
+                                  uint64_t arena_off) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (vm >= c->vms.size()) return dv_fail(-ENOENT, "no VM %u", vm);
+    if (slot >= 64) return dv_fail(-EINVAL, "slot must be 0..63");
+    VmHost &v = c->vms[vm];
+    if (bytes != 0) {
+        if ((gpa | bytes | arena_off) & 4095) return dv_fail(-EINVAL, "gpa, bytes and arena_off must be 4 KiB aligned");
+        if (gpa >= (1ull << 52) || bytes > (1ull << 52) - gpa) return dv_fail(-EINVAL, "slot passes 2^52");
+        if (arena_off > v.bytes || bytes > v.bytes - arena_off) return dv_fail(-EINVAL, "slot leaves the arena");
+        for (uint32_t i = 0; i < 64; ++i) {
+            const auto &o = v.slots[i];
+            if (i == slot || !o.used) continue;
+            if (gpa < o.gpa + o.bytes && o.gpa < gpa + bytes)
+                return dv_fail(-EEXIST, "GPA range overlaps slot %u", i);
+        }
+    }
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipDeviceSynchronize());
+    VmHost nv = v;
+    nv.slots[slot].used = bytes != 0;
+    nv.slots[slot].gpa = gpa;
+    nv.slots[slot].bytes = bytes;
+    nv.slots[slot].off = arena_off;
+    std::vector<DSlot> sorted;
+    std::vector<uint64_t> index;
+    uint32_t complete = 1;
+    build_slot_index(nv, sorted, index, complete);
+    DSlot *ds = nullptr;
+    uint64_t *di = nullptr;
+    if (!sorted.empty()) {
+        if (hipMalloc(&ds, sorted.size() * sizeof(DSlot)) != hipSuccess) return dv_fail(-ENOMEM, "hipMalloc slots");
+        HIPCHK(hipMemcpy(ds, sorted.data(), sorted.size() * sizeof(DSlot), hipMemcpyHostToDevice));
+    }
+    if (!index.empty()) {
+        if (hipMalloc(&di, index.size() * 8) != hipSuccess) {
+            hipFree(ds);
+            return dv_fail(-ENOMEM, "hipMalloc slot index");
+        }
+        HIPCHK(hipMemcpy(di, index.data(), index.size() * 8, hipMemcpyHostToDevice));
+    }
+    hipFree(v.d_slots);
+    hipFree(v.d_index);
+    v = nv;
+    v.d_slots = ds;
+    v.d_index = di;
+    v.nsorted = (uint32_t)sorted.size();
+    v.index_len = (uint32_t)index.size();
+    v.index_complete = complete;
+    return upload_vms(c);
+}
+
+extern "C" int devirt_process_create(devirt_ctx *c, uint32_t vm, uint64_t cr3_gpa, uint32_t levels, uint32_t *asid) {
+    if (!c || !asid) return dv_fail(-EINVAL, "NULL argument");
+    if (vm >= c->vms.size()) return dv_fail(-ENOENT, "no VM %u", vm);
+    if (levels != 4 && levels != 5) return dv_fail(-EINVAL, "levels must be 4 or 5");
+    if (c->procs.size() >= 0x7FFFFFFF) return dv_fail(-EINVAL, "too many processes");
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipDeviceSynchronize());
+    c->procs.push_back(DProc{cr3_gpa, vm, levels});
+    int rc = upload_procs(c);
+    if (rc) {
+        c->procs.pop_back();
+        return rc;
+    }
+    *asid = (uint32_t)(c->procs.size() - 1);
+    return 0;
+}
+
+DView view_of(const devirt_ctx *c) {
+    DView v;
+    v.vms = c->d_vms;
+    v.procs = c->d_procs;
+    v.nvm = (uint32_t)c->vms.size();
+    v.nproc = (uint32_t)c->procs.size();
+    return v;
+}
+
+// ---------------------------------------------------------------- workspaces
+static uint64_t default_seg_cap() {
+    const char *e = getenv("DEVIRT_SEG_CAP");
+    if (e && *e) {
+        unsigned long long v = strtoull(e, nullptr, 10);
+        if (v >= 64) return v;
+    }
+    return 4ull << 20;  // 4 Mi segments (128 MiB)
+}
+
+Workspace *get_ws(devirt_ctx *c, hipStream_t s) {
+    auto it = c->ws.find(s);
+    if (it != c->ws.end()) return it->second;
+    Workspace *w = new Workspace();
+    w->stream = s;
+    c->ws[s] = w;
+    return w;
+}
+
+static bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+template <class T>
+static int grow(devirt_ctx *c, Workspace *w, T *&p, uint64_t &cap, uint64_t need, const char *what) {
+    (void)c;
+    if (need <= cap && p) return 0;
+    if (stream_capturing(w->stream))
+        return dv_fail(-EBUSY, "workspace %s must grow while the stream is being captured; run once uncaptured first",
+                       what);
+    HIPCHK(hipStreamSynchronize(w->stream));
+    for (auto &g : w->graphs) hipGraphExecDestroy(g.exec);
+    w->graphs.clear();
+    uint64_t ncap = std::max<uint64_t>(need, cap * 2);
+    if (ncap < 64) ncap = 64;
+    T *np = nullptr;
+    if (hipMalloc(&np, ncap * sizeof(T)) != hipSuccess) return dv_fail(-ENOMEM, "hipMalloc workspace %s", what);
+    hipFree(p);
+    p = np;
+    cap = ncap;
+    return 0;
+}
+
+int ensure_ws(devirt_ctx *c, Workspace *w, uint64_t n_req, uint64_t n_epochs, bool need_pending, uint64_t min_segs) {
+    int rc;
+    const uint64_t segs = w->segs ? std::max<uint64_t>(w->seg_cap, min_segs) : std::max(default_seg_cap(), min_segs);
+    if ((rc = grow(c, w, w->segs, w->seg_cap, segs, "segments"))) return rc;
+    if ((rc = grow(c, w, w->ctr, w->ctr_cap, std::max<uint64_t>(n_epochs, 1), "epoch counters"))) return rc;
+    if ((rc = grow(c, w, w->t0, w->t0_cap, 1, "clock"))) return rc;
+    uint64_t tiles = (n_req + kFaultTile - 1) / kFaultTile;
+    if ((rc = grow(c, w, w->tiles, w->tiles_cap, std::max<uint64_t>(tiles, 1), "fault tiles"))) return rc;
+    if (need_pending && (rc = grow(c, w, w->pending, w->pending_cap, std::max<uint64_t>(n_req, 1), "pending")))
+        return rc;
+    return 0;
+}
+
+DBatch make_batch(devirt_ctx *c, Workspace *w) {
+    DBatch b;
+    memset(&b, 0, sizeof b);
+    b.segs = w->segs;
+    b.seg_cap = w->seg_cap;
+    b.ctr = w->ctr;
+    b.pending = w->pending;
+    b.t0 = w->t0;
+    b.counters = c->profiling ? c->d_counters : nullptr;
+    b.ns_num = 1000000ull;
+    b.ns_den = c->wall_khz;
+    b.group = c->cfg.group;
+    b.seg_chunks = c->cfg.seg_chunks;
+    b.inline_bytes = c->cfg.inline_bytes;
+    b.nontemporal = c->cfg.nontemporal;
+    return b;
+}
+
+// ------------------------------------------------------------- profiling
+int prof_begin(devirt_ctx *c, hipStream_t s, int kind, ProfEv **out) {
+    *out = nullptr;
+    if (!c->profiling) return 0;
+    ProfEv e;
+    e.kind = kind;
+    HIPCHK(hipEventCreate(&e.a));
+    HIPCHK(hipEventCreate(&e.b));
+    HIPCHK(hipEventRecord(e.a, s));
+    c->prof.push_back(e);
+    *out = &c->prof.back();
+    return 0;
+}
+
+int prof_end(devirt_ctx *c, hipStream_t s, ProfEv *e) {
+    if (!e) return 0;
+    (void)c;
+    HIPCHK(hipEventRecord(e->b, s));
+    return 0;
+}
+
+static int prof_collect(devirt_ctx *c) {
+    for (auto &e : c->prof) {
+        float ms = 0;
+        HIPCHK(hipEventSynchronize(e.b));
+        HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+        if (e.kind == 0) {
+            c->stats.copy_ms += ms;
+            c->stats.copy_launches++;
+        } else {
+            c->stats.xlat_ms += ms;
+            c->stats.xlat_launches++;
+        }
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    c->prof.clear();
+    return 0;
+}
+
+extern "C" int devirt_set_profiling(devirt_ctx *c, int on) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    c->profiling = on ? 1 : 0;
+    return 0;
+}
+
+extern "C" int devirt_get_stats(devirt_ctx *c, devirt_stats *out) {
+    if (!c || !out) return dv_fail(-EINVAL, "NULL argument");
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipDeviceSynchronize());
+    int rc = prof_collect(c);
+    if (rc) return rc;
+    DCounters h;
+    HIPCHK(hipMemcpy(&h, c->d_counters, sizeof h, hipMemcpyDeviceToHost));
+    *out = c->stats;
+    out->pages_walked = h.pages_walked;
+    out->cache_hits = h.cache_hits;
+    out->cache_misses = h.cache_misses;
+    out->segments = h.segments;
+    out->inline_segments = h.inline_segments;
+    out->ad_atomics = h.ad_atomics;
+    return 0;
+}
+
+extern "C" int devirt_reset_stats(devirt_ctx *c) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipDeviceSynchronize());
+    int rc = prof_collect(c);
+    if (rc) return rc;
+    memset(&c->stats, 0, sizeof c->stats);
+    HIPCHK(hipMemset(c->d_counters, 0, sizeof(DCounters)));
+    return 0;
+}
+
+// ------------------------------------------------------------- data path
+static int grid_for(devirt_ctx *c, uint64_t waves_needed, uint32_t block, uint32_t per_cu) {
+    uint64_t wpb = block / 64;
+    uint64_t g = (waves_needed + wpb - 1) / wpb;
+    uint64_t cap = (uint64_t)c->cus * per_cu;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+extern "C" int devirt_translate(devirt_ctx *c, uint32_t asid, const uint64_t *gva_dev, uint64_t n, uint32_t flags,
+                                devirt_xlat *out_dev, void *stream) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (flags & ~(DEVIRT_XLAT_WRITE | DEVIRT_XLAT_SET_AD)) return dv_fail(-EINVAL, "unknown flags");
+    if (n == 0) return 0;
+    if (!gva_dev || !out_dev) return dv_fail(-EINVAL, "NULL buffer");
+    if (set_dev(c)) return -EIO;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t block = 256;
+    int grid = grid_for(c, (n + 63) / 64, block, 8);
+    ProfEv *pe;
+    int rc = prof_begin(c, s, 1, &pe);
+    if (rc) return rc;
+    HIPCHK(launch_xlat(s, grid, block, view_of(c), asid, gva_dev, n, flags, out_dev,
+                       c->profiling ? c->d_counters : nullptr));
+    return prof_end(c, s, pe);
+}
+
+// Pages a request touches, 0 when it is empty or not user-canonical for any depth.
+static uint64_t pages_of(uint64_t gva, uint64_t len) {
+    if (len == 0 || gva >= (1ull << 56) || len > (1ull << 56) - gva) return 0;
+    return ((gva + len - 1) >> 12) - (gva >> 12) + 1;
+}
+
+static const uint64_t kPlainInlinePages = 16;
+
+static int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host, uint64_t len, uint32_t dir,
+                      devirt_result *res, void *stream) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (!res) return dv_fail(-EINVAL, "res_dev is NULL");
+    if (len >= (1ull << 32)) return dv_fail(-EINVAL, "len must be < 2^32");
+    if (len && !host) return dv_fail(-EINVAL, "NULL host buffer");
+    if (set_dev(c)) return -EIO;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *w = get_ws(c, s);
+    const uint64_t pages = pages_of(gva, len);
+    const bool inl = pages <= kPlainInlinePages;
+    int rc = ensure_ws(c, w, 1, 1, false, inl ? 0 : pages);
+    if (rc) return rc;
+    DBatch b = make_batch(c, w);
+    b.res = res;
+    devirt_request rq;
+    memset(&rq, 0, sizeof rq);
+    rq.gva = gva;
+    rq.host = host;
+    rq.len = (uint32_t)len;
+    rq.asid = asid;
+    rq.dir = (uint8_t)dir;
+    c->stats.plain_calls++;
+    HIPCHK(launch_plain(s, view_of(c), b, rq, inl ? 1 : 0));
+    if (!inl) {
+        ProfEv *pe;
+        if ((rc = prof_begin(c, s, 0, &pe))) return rc;
+        HIPCHK(launch_copy(s, grid_for(c, pages, c->cfg.copy_wg, c->cfg.copy_wgs_per_cu), c->cfg.copy_wg, b, 0));
+        if ((rc = prof_end(c, s, pe))) return rc;
+    }
+    return 0;
+}
+
+extern "C" int devirt_copy_from_guest(devirt_ctx *c, uint32_t asid, uint64_t gva, void *dst, uint64_t len,
+                                      devirt_result *res, void *stream) {
+    return plain_copy(c, asid, gva, (uint64_t)(uintptr_t)dst, len, DEVIRT_FROM_GUEST, res, stream);
+}
+extern "C" int devirt_copy_to_guest(devirt_ctx *c, uint32_t asid, uint64_t gva, const void *src, uint64_t len,
+                                    devirt_result *res, void *stream) {
+    return plain_copy(c, asid, gva, (uint64_t)(uintptr_t)src, len, DEVIRT_TO_GUEST, res, stream);
+}
+
+// Enqueue one batch (no capture logic here).
+static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a) {
+    hipStream_t s = w->stream;
+    DBatch b = make_batch(c, w);
+    b.reqs = a.reqs;
+    b.res = a.res;
+    b.t_done = a.t_done;
+    const DView v = view_of(c);
+    HIPCHK(launch_reset(s, b, (uint32_t)a.epochs.size()));
+    uint64_t r0 = 0;
+    int rc;
+    for (size_t e = 0; e < a.epochs.size(); ++e) {
+        uint64_t r1 = a.epochs[e];
+        if (r1 > r0) {
+            uint64_t groups = (r1 - r0 + c->cfg.group - 1) / c->cfg.group;
+            ProfEv *pe;
+            if ((rc = prof_begin(c, s, 1, &pe))) return rc;
+            HIPCHK(launch_translate_groups(s, grid_for(c, groups, c->cfg.xlat_wg, c->cfg.xlat_wgs_per_cu),
+                                           (int)c->cfg.xlat_wg, v, b, r0, r1, (uint32_t)e));
+            if ((rc = prof_end(c, s, pe))) return rc;
+            if ((rc = prof_begin(c, s, 0, &pe))) return rc;
+            HIPCHK(launch_copy(s, (int)((uint64_t)c->cus * c->cfg.copy_wgs_per_cu), (int)c->cfg.copy_wg, b,
+                               (uint32_t)e));
+            if ((rc = prof_end(c, s, pe))) return rc;
+        }
+        r0 = r1;
+    }
+    if (a.faults || a.n_faults) {
+        uint64_t tiles = (a.n + kFaultTile - 1) / kFaultTile;
+        HIPCHK(launch_fault_count(s, a.res, a.n, w->tiles));
+        HIPCHK(launch_fault_scan(s, w->tiles, tiles, a.n_faults));
+        if (a.faults) HIPCHK(launch_fault_scatter(s, a.res, a.n, w->tiles, a.faults));
+    }
+    return 0;
+}
+
+static uint64_t hash_key(const std::vector<uint64_t> &k) {
+    uint64_t h = 1469598103934665603ull;
+    for (uint64_t x : k) {
+        h ^= x;
+        h *= 1099511628211ull;
+        h ^= h >> 29;
+    }
+    return h;
+}
+
+extern "C" int devirt_submit_batch(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint64_t *epoch_end,
+                                   uint32_t n_epochs, devirt_result *res, devirt_fault *faults, uint64_t *n_faults,
+                                   uint64_t *t_done, void *stream) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (n && (!reqs || !res)) return dv_fail(-EINVAL, "NULL request or result buffer");
+    if (((uintptr_t)reqs & 15) || ((uintptr_t)res & 7)) return dv_fail(-EINVAL, "reqs must be 16-byte aligned");
+    BatchArgs a;
+    a.reqs = reqs;
+    a.n = n;
+    a.res = res;
+    a.faults = faults;
+    a.n_faults = n_faults;
+    a.t_done = t_done;
+    if (epoch_end) {
+        if (n_epochs == 0) return dv_fail(-EINVAL, "n_epochs is 0 with an epoch array");
+        uint64_t prev = 0;
+        for (uint32_t e = 0; e < n_epochs; ++e) {
+            if (epoch_end[e] < prev || epoch_end[e] > n) return dv_fail(-EINVAL, "epoch ends must ascend within [0, n]");
+            prev = epoch_end[e];
+        }
+        if (prev != n) return dv_fail(-EINVAL, "the last epoch must end at n");
+        a.epochs.assign(epoch_end, epoch_end + n_epochs);
+    } else {
+        a.epochs.assign(1, n);
+    }
+    if (set_dev(c)) return -EIO;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *w = get_ws(c, s);
+    int rc = ensure_ws(c, w, n, a.epochs.size(), t_done != nullptr, 0);
+    if (rc) return rc;
+    c->stats.batches++;
+    c->stats.epochs += a.epochs.size();
+    const bool capturing = stream_capturing(s);
+    if (!c->cfg.use_graph || c->profiling || capturing || n == 0) return enqueue_batch(c, w, a);
+    // graph cache: key = every argument that ends up in a kernel parameter
+    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)reqs, n, (uint64_t)(uintptr_t)res, (uint64_t)(uintptr_t)faults,
+                                 (uint64_t)(uintptr_t)n_faults, (uint64_t)(uintptr_t)t_done, c->tables_version,
+                                 c->cfg_version, (uint64_t)(uintptr_t)w->segs, w->seg_cap};
+    key.insert(key.end(), a.epochs.begin(), a.epochs.end());
+    const uint64_t h = hash_key(key);
+    for (auto &g : w->graphs) {
+        if (g.hash == h && g.key == key) {
+            c->stats.graph_replays++;
+            HIPCHK(hipGraphLaunch(g.exec, s));
+            return 0;
+        }
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_batch(c, w, a);
+    hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (rc) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ee != hipSuccess) return dv_fail(-EIO, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) return dv_fail(-EIO, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    if (w->graphs.size() >= 8) {
+        HIPCHK(hipStreamSynchronize(s));
+        hipGraphExecDestroy(w->graphs.front().exec);
+        w->graphs.erase(w->graphs.begin());
+    }
+    w->graphs.push_back(GraphEntry{h, key, exec});
+    HIPCHK(hipGraphLaunch(exec, s));
+    return 0;
+}
+
+extern "C" int devirt_sync(devirt_ctx *c, void *stream) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    return 0;
+}
+
+// ---------------------------------------------------------------- config
+extern "C" int devirt_get_config(devirt_ctx *c, devirt_config *cfg) {
+    if (!c || !cfg) return dv_fail(-EINVAL, "NULL argument");
+    *cfg = c->cfg;
+    return 0;
+}
+
+extern "C" int devirt_set_config(devirt_ctx *c, const devirt_config *cfg) {
+    if (!c || !cfg) return dv_fail(-EINVAL, "NULL argument");
+    int rc = check_config(*cfg);
+    if (rc) return rc;
+    if (cfg->fused) return dv_fail(-EINVAL, "the fused persistent batch launch is not available in this build");
+    c->cfg = *cfg;
+    c->cfg_version++;
+    return 0;
+}
+
+extern "C" int devirt_autotune(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint64_t *epoch_end,
+                               uint32_t n_epochs, devirt_result *res, devirt_fault *faults, uint64_t *n_faults,
+                               void *stream, uint32_t reps, devirt_config *best, double *best_ms) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (reps == 0) reps = 3;
+    if (set_dev(c)) return -EIO;
+    hipStream_t s = (hipStream_t)stream;
+    const devirt_config base = c->cfg;
+    std::vector<devirt_config> cand;
+    for (uint32_t group : {16u, 32u, 64u})
+        for (uint32_t segc : {4u, 16u, 64u})
+            for (uint32_t cwpc : {4u, 8u})
+                for (uint32_t nt : {0u, 1u}) {
+                    devirt_config k = base;
+                    k.group = group;
+                    k.seg_chunks = segc;
+                    k.copy_wgs_per_cu = cwpc;
+                    k.nontemporal = nt;
+                    cand.push_back(k);
+                }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best_t = 1e300;
+    devirt_config best_c = base;
+    const int prof = c->profiling;
+    c->profiling = 0;
+    int rc = 0;
+    for (const auto &k : cand) {
+        c->cfg = k;
+        c->cfg_version++;
+        // warm-up (also captures the graph)
+        if ((rc = devirt_submit_batch(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, nullptr, stream))) break;
+        std::vector<double> ts;
+        for (uint32_t r = 0; r < reps; ++r) {
+            hipEventRecord(e0, s);
+            if ((rc = devirt_submit_batch(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, nullptr, stream)))
+                break;
+            hipEventRecord(e1, s);
+            hipEventSynchronize(e1);
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            ts.push_back(ms);
+        }
+        if (rc) break;
+        std::sort(ts.begin(), ts.end());
+        double med = ts[ts.size() / 2];
+        if (med < best_t) {
+            best_t = med;
+            best_c = k;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->profiling = prof;
+    c->cfg = rc ? base : best_c;
+    c->cfg_version++;
+    if (rc) return rc;
+    if (best) *best = best_c;
+    if (best_ms) *best_ms = best_t;
+    return 0;
+}

@@ -1,0 +1,88 @@
+// Host-side state of a devirt context (shared by the runtime and the server).
+#pragma once
+#include <stdint.h>
+
+#include <list>
+#include <map>
+#include <vector>
+
+#include "dv_internal.h"
+
+struct VmHost {
+    uint8_t *arena = nullptr;
+    uint64_t bytes = 0;
+    struct Slot {
+        uint64_t gpa = 0, bytes = 0, off = 0;
+        bool used = false;
+    } slots[64];
+    uint64_t *d_index = nullptr;
+    dv::DSlot *d_slots = nullptr;
+    uint32_t index_len = 0, nsorted = 0, index_complete = 1;
+};
+
+struct GraphEntry {
+    uint64_t hash;
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+};
+
+// Per-stream scratch: the copy-segment queue, epoch counters, per-request
+// pending counts (completion times), fault-list tile sums, the clock origin
+// and the captured graphs that reference them.
+struct Workspace {
+    hipStream_t stream = nullptr;
+    dv::DSeg *segs = nullptr;
+    uint64_t seg_cap = 0;
+    dv::DEpochCtr *ctr = nullptr;
+    uint64_t ctr_cap = 0;
+    uint32_t *pending = nullptr;
+    uint64_t pending_cap = 0;
+    uint32_t *tiles = nullptr;
+    uint64_t tiles_cap = 0;
+    uint64_t *t0 = nullptr;
+    uint64_t t0_cap = 0;
+    std::vector<GraphEntry> graphs;
+    ~Workspace();
+};
+
+struct ProfEv {
+    int kind;  // 0 copy, 1 translate
+    hipEvent_t a, b;
+};
+
+struct devirt_ctx {
+    int device = 0;
+    int cus = 0;
+    uint64_t wall_khz = 100000;
+    std::vector<VmHost> vms;
+    std::vector<dv::DProc> procs;
+    dv::DVm *d_vms = nullptr;
+    size_t d_vms_cap = 0;
+    dv::DProc *d_procs = nullptr;
+    size_t d_procs_cap = 0;
+    uint64_t tables_version = 0;
+    devirt_config cfg;
+    uint64_t cfg_version = 0;
+    std::map<hipStream_t, Workspace *> ws;
+    int profiling = 0;
+    devirt_stats stats = {};
+    dv::DCounters *d_counters = nullptr;
+    std::list<ProfEv> prof;
+    void *server = nullptr;  // non-null while a serving loop owns the context
+};
+
+struct BatchArgs {
+    const devirt_request *reqs = nullptr;
+    uint64_t n = 0;
+    devirt_result *res = nullptr;
+    devirt_fault *faults = nullptr;
+    uint64_t *n_faults = nullptr;
+    uint64_t *t_done = nullptr;
+    std::vector<uint64_t> epochs;
+};
+
+int dv_fail(int code, const char *fmt, ...);
+dv::DView view_of(const devirt_ctx *c);
+Workspace *get_ws(devirt_ctx *c, hipStream_t s);
+int ensure_ws(devirt_ctx *c, Workspace *w, uint64_t n_req, uint64_t n_epochs, bool need_pending, uint64_t min_segs);
+dv::DBatch make_batch(devirt_ctx *c, Workspace *w);

@@ -1,0 +1,315 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Bar: bit-exact (everything is integer): translation records, results, the
+ordered fault list, every arena byte (A/D bits included) and every pool byte.
+"""
+import numpy as np
+import pytest
+
+import pins
+from gpu_util import compare, gpu_batch, log, new_ctx, oracle_batch
+from workload import device, gen
+
+pytestmark = pytest.mark.gpu
+
+SPECS = pins.small_specs()
+_WL = {}
+
+
+def wl(name):
+    if name not in _WL:
+        _WL[name] = gen.make_workload(SPECS[name])
+    return _WL[name]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1304_3771_amd as dv
+    dv.lib()
+
+
+# ------------------------------------------------------------ golden walks
+def _golden_ctx(world):
+    import torch
+    import paper_1304_3771_amd as dv
+    ctx = new_ctx()
+    H = pins.H
+    o, arena, pool = pins.build_golden(world)
+    vm = ctx.vm_create(H(world["arena_bytes"]))
+    ctx.vm_write(vm, 0, arena)
+    for i, s in enumerate(world["slots"]):
+        ctx.memslot_set(vm, i, H(s["gpa"]), H(s["bytes"]), H(s["arena_off"]))
+    asid = ctx.process_create(vm, H(world["cr3"]), world["levels"])
+    assert asid == 0
+    dpool = torch.from_numpy(pool.copy()).cuda()
+    return ctx, vm, o, arena, pool, dpool, dv
+
+
+@pytest.mark.parametrize("widx", [0, 1])
+def test_golden_translate(widx):
+    import torch
+    world = pins.golden_worlds()[widx]
+    log(f"golden translate {world['name']}")
+    ctx, vm, o, arena, pool, dpool, dv = _golden_ctx(world)
+    try:
+        for write in (0, 1):
+            qs = [q for q in world["queries"]]
+            g = torch.tensor([pins.H(q["gva"]) for q in qs], dtype=torch.int64).cuda()
+            out = torch.zeros(len(qs) * 24, dtype=torch.uint8).cuda()
+            ctx.translate(0, g, len(qs), dv.XLAT_WRITE if write else 0, out)
+            ctx.sync()
+            x = out.cpu().numpy().view(dv.XLAT_DTYPE)
+            e = o.translate(0, [pins.H(q["gva"]) for q in qs], dv.XLAT_WRITE if write else 0)
+            for i, q in enumerate(qs):
+                assert x[i].tobytes() == e[i].tobytes(), (q["gva"], write, x[i], e[i])
+                if q["write"] == write:
+                    assert (int(x[i]["code"]), int(x[i]["level"]), int(x[i]["gpa"]), int(x[i]["hpa"]),
+                            int(x[i]["page_shift"])) == (q["code"], q["level"], pins.H(q["gpa"]), pins.H(q["hpa"]),
+                                                         q["shift"])
+        # invalid asid
+        out = torch.zeros(24, dtype=torch.uint8).cuda()
+        g = torch.tensor([0x1000], dtype=torch.int64).cuda()
+        ctx.translate(7, g, 1, 0, out)
+        ctx.sync()
+        x = out.cpu().numpy().view(dv.XLAT_DTYPE)[0]
+        assert int(x["code"]) == dv.CODES["INVALID"] and int(x["vm"]) == 0xFFFF
+    finally:
+        ctx.close()
+
+
+def test_golden_set_ad():
+    import torch
+    world = pins.golden_worlds()[0]
+    ad = world["ad_after_set_ad_write"]
+    ctx, vm, o, arena, pool, dpool, dv = _golden_ctx(world)
+    try:
+        g = torch.tensor([pins.H(ad["gva"])], dtype=torch.int64).cuda()
+        out = torch.zeros(24, dtype=torch.uint8).cuda()
+        ctx.translate(0, g, 1, dv.XLAT_WRITE | dv.XLAT_SET_AD, out)
+        ctx.sync()
+        a = np.empty(pins.H(world["arena_bytes"]), np.uint8)
+        ctx.vm_read(vm, 0, a)
+        o.translate(0, [pins.H(ad["gva"])], dv.XLAT_WRITE | dv.XLAT_SET_AD)
+        assert np.array_equal(a, o.arenas[0])
+        for e in ad["expect"]:
+            assert int.from_bytes(a[pins.H(e["arena_off"]):pins.H(e["arena_off"]) + 8].tobytes(), "little") == \
+                pins.H(e["value"])
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("path", ["plain", "batch"])
+def test_golden_copies(path):
+    import torch
+    world = pins.golden_worlds()[0]
+    for c in world["copies"]:
+        log(f"golden copy {path} {c['gva']} dir {c['dir']}")
+        ctx, vm, o, arena, pool, dpool, dv = _golden_ctx(world)
+        try:
+            H = pins.H
+            res = torch.zeros(24, dtype=torch.uint8).cuda()
+            if path == "plain":
+                f = ctx.copy_to_guest if c["dir"] == 1 else ctx.copy_from_guest
+                f(0, H(c["gva"]), dpool.data_ptr(), H(c["len"]), res)
+            else:
+                req = np.zeros(1, dv.REQUEST_DTYPE)
+                req[0] = (H(c["gva"]), dpool.data_ptr(), H(c["len"]), 0, c["dir"], (0, 0, 0), 0)
+                dreq = device.upload_requests(req)
+                ctx.submit_batch(dreq, 1, res)
+            ctx.sync()
+            r = res.cpu().numpy().view(dv.RESULT_DTYPE)[0]
+            req = np.zeros(1, dv.REQUEST_DTYPE)
+            req[0] = (H(c["gva"]), 0, H(c["len"]), 0, c["dir"], (0, 0, 0), 0)
+            er = o.copy(req[0])
+            assert r.tobytes() == er.tobytes()
+            assert (int(r["code"]), int(r["bytes_done"])) == (c["code"], H(c["bytes_done"]))
+            a = np.empty(H(world["arena_bytes"]), np.uint8)
+            ctx.vm_read(vm, 0, a)
+            assert np.array_equal(a, o.arenas[0])
+            assert np.array_equal(dpool.cpu().numpy(), o.pool)
+        finally:
+            ctx.close()
+
+
+# ------------------------------------------------------------ batches
+@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "prot"])
+def test_batch_matches_oracle(name):
+    w = wl(name)
+    log(f"batch {name}: {w.n_requests} requests, {len(w.epoch_end)} epochs")
+    got = gpu_batch(w)
+    exp = oracle_batch(w)
+    assert compare(name, got, exp) == []
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(group=1, seg_chunks=1),
+    dict(group=64, seg_chunks=64, nontemporal=1),
+    dict(group=7, seg_chunks=3, inline_bytes=256, xlat_wg=64, copy_wg=64),
+    dict(use_graph=0, copy_wg=1024, copy_wgs_per_cu=1),
+])
+def test_batch_configs_agree(cfg):
+    w = wl("multi_vm")
+    log(f"config {cfg}")
+    got = gpu_batch(w, cfg=cfg)
+    exp = oracle_batch(w)
+    assert compare(str(cfg), got, exp) == []
+
+
+def test_batch_single_epoch_when_conflict_free():
+    # C1 has one epoch; run it without the epoch array as well
+    w = wl("c1")
+    got = gpu_batch(w, epochs=False)
+    exp = oracle_batch(w)
+    assert compare("c1 no epochs", got, exp) == []
+
+
+def test_plain_per_request_matches_oracle():
+    import torch
+    import paper_1304_3771_amd as dv
+    w = wl("mix2m")
+    log("plain per-request mix2m")
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        n = dw.n
+        res = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+        for i, r in enumerate(dw.reqs_host):
+            f = ctx.copy_to_guest if int(r["dir"]) == 1 else ctx.copy_from_guest
+            f(int(r["asid"]), int(r["gva"]), int(r["host"]), int(r["len"]), res.data_ptr() + 24 * i)
+        ctx.sync()
+        got_r = res.cpu().numpy().view(dv.RESULT_DTYPE)
+        arenas = device.read_arenas(ctx, dw)
+        pool = dw.pool.cpu().numpy()
+    finally:
+        ctx.close()
+    er, ef, ea, ep = oracle_batch(w)
+    fidx = np.nonzero(got_r["code"] != 0)[0]
+    gf = np.zeros(len(fidx), dv.FAULT_DTYPE)
+    gf["req_index"], gf["fault_gva"], gf["code"], gf["level"] = fidx, got_r["fault_gva"][fidx], \
+        got_r["code"][fidx], got_r["level"][fidx]
+    assert compare("plain", (got_r, gf, arenas, pool), (er, ef, ea, ep)) == []
+
+
+def test_translate_matches_oracle():
+    import torch
+    import paper_1304_3771_amd as dv
+    from oracle import Oracle
+    for name in ("mix2m", "lvl5_1g", "prot", "multi_vm"):
+        w = wl(name)
+        log(f"translate {name}")
+        rng = np.random.default_rng(3)
+        ctx = new_ctx()
+        try:
+            dw = device.load(ctx, w)
+            o = Oracle.from_workload(w)
+            for p in w.procs[:3]:
+                k = min(len(p.leaf_va), 3000)
+                sel = rng.choice(len(p.leaf_va), k, replace=False)
+                g = p.leaf_va[sel] + rng.integers(0, 4096, k, dtype=np.uint64)
+                g = np.concatenate([g, rng.integers(0, 1 << 48, 500, dtype=np.uint64),
+                                    p.vmas[:, 0] + p.vmas[:, 1]]).astype(np.uint64)
+                for flags in (0, dv.XLAT_WRITE, dv.XLAT_WRITE | dv.XLAT_SET_AD, dv.XLAT_SET_AD):
+                    dg = torch.from_numpy(g.view(np.int64)).cuda()
+                    out = torch.zeros(len(g) * 24, dtype=torch.uint8, device="cuda")
+                    ctx.translate(p.asid, dg, len(g), flags, out)
+                    ctx.sync()
+                    x = out.cpu().numpy().view(dv.XLAT_DTYPE)
+                    e = o.translate(p.asid, g, flags)
+                    bad = np.nonzero(x.view(np.uint8).reshape(-1, 24).tobytes() != e.view(np.uint8).reshape(-1, 24)
+                                     .tobytes())
+                    if not np.array_equal(x.view(np.uint8), e.view(np.uint8)):
+                        i = int(np.nonzero((x.view(np.uint8).reshape(-1, 24) != e.view(np.uint8).reshape(-1, 24))
+                                           .any(axis=1))[0][0])
+                        raise AssertionError(f"{name} asid {p.asid} flags {flags} gva {hex(int(g[i]))}: "
+                                             f"gpu {x[i]} oracle {e[i]}")
+                    del bad
+            arenas = device.read_arenas(ctx, dw)
+            for v in range(len(arenas)):
+                assert np.array_equal(arenas[v], o.arenas[v]), f"{name}: A/D state differs in vm {v}"
+        finally:
+            ctx.close()
+
+
+def test_edge_cases():
+    """Empty batch, zero length, bad asid, non-canonical and wrapping ranges,
+    a 4 MiB request spanning many passes, requests ending at the user limit."""
+    import torch
+    import paper_1304_3771_amd as dv
+    w = wl("lvl5")
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        # empty batch
+        res = torch.zeros(24, dtype=torch.uint8, device="cuda")
+        nf = torch.full((1,), 77, dtype=torch.int64, device="cuda")
+        ctx.submit_batch(dw.reqs, 0, res, None, None, nf)
+        ctx.sync()
+        assert int(nf.item()) == 0
+        p0 = w.procs[0]
+        big = int(p0.vmas[np.argmax(p0.vmas[:, 1]), 0])
+        span = int(p0.vmas[:, 1].max())
+        # a dedicated 16 MiB host pool: every host range below stays inside it
+        hpool = gen.fill_bytes(np.empty(16 << 20, np.uint8), 5, 9)
+        epool = torch.from_numpy(hpool.copy()).cuda()
+        base = epool.data_ptr()
+        edge = [
+            (int(p0.leaf_va[0]), base, 0, 0, 1),                       # len 0
+            (int(p0.leaf_va[0]), base, 100, 9999, 0),                  # bad asid
+            ((1 << 56) - 8, base, 16, 0, 0),                           # runs past the 5-level limit
+            ((1 << 64) - 8, base, 16, 0, 1),                           # wraps
+            ((1 << 56) - 4096, base, 4096, 0, 0),                      # last user page (unmapped)
+            (big + 123, base + 64, min(span - 200, 4 << 20), 0, 0),    # up to 4 MiB, many passes
+            (big + 77, base + (8 << 20), min(span - 100, 3 << 20), 0, 1),
+        ]
+        req = np.zeros(len(edge), dv.REQUEST_DTYPE)
+        for i, (g, h, n, a, d) in enumerate(edge):
+            req[i] = (g, h, n, a, d, (0, 0, 0), 0)
+        hreq = req.copy()
+        hreq["host"] -= np.uint64(base)
+        dreq = device.upload_requests(req)
+        res = torch.zeros(len(edge) * 24, dtype=torch.uint8, device="cuda")
+        faults = torch.zeros(len(edge) * 24, dtype=torch.uint8, device="cuda")
+        nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ctx.submit_batch(dreq, len(edge), res, [len(edge) - 1, len(edge)], faults, nf)
+        ctx.sync()
+        r = res.cpu().numpy().view(dv.RESULT_DTYPE)
+        assert all(h - base + n <= hpool.size for (g, h, n, a, d) in edge)
+        from oracle import Oracle
+        o = Oracle.from_workload(w, pool=hpool.copy())
+        er, ef = o.batch(hreq)
+        assert np.array_equal(r.view(np.uint8), er.view(np.uint8)), (r, er)
+        k = int(nf.item())
+        assert np.array_equal(faults.cpu().numpy()[:24 * k].view(dv.FAULT_DTYPE).view(np.uint8), ef.view(np.uint8))
+        assert np.array_equal(epool.cpu().numpy(), o.pool)
+        for v, a in enumerate(device.read_arenas(ctx, dw)):
+            assert np.array_equal(a, o.arenas[v])
+        # API misuse is an error, not a fault
+        with pytest.raises(dv.DevirtError):
+            ctx.submit_batch(dreq, len(edge), res, [3, 2, len(edge)])
+        with pytest.raises(dv.DevirtError):
+            ctx.memslot_set(0, 0, 4096, 4096 * 3, 1)
+        with pytest.raises(dv.DevirtError):
+            ctx.set_config(group=0)
+    finally:
+        ctx.close()
+
+
+def test_queue_overflow_copies_inline(monkeypatch):
+    """With a tiny segment queue the translating wavefronts copy the rest themselves."""
+    monkeypatch.setenv("DEVIRT_SEG_CAP", "64")
+    w = wl("mix2m")
+    got = gpu_batch(w)
+    exp = oracle_batch(w)
+    assert compare("overflow", got, exp) == []
+
+
+def test_completion_times_and_repeat():
+    w = wl("multi_vm")
+    got = gpu_batch(w, t_done=True)
+    exp = oracle_batch(w)
+    assert compare("t_done", got, exp) == []
+    td = got[4]["t_done"]
+    assert np.all(td > 0) and np.all(td < 60e9)
