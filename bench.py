@@ -87,6 +87,89 @@ def measured_traffic(workload):
     return d.get("bytes_per_launch")
 
 
+def serving(args):
+    """C4: Poisson arrivals through the serving loop, one JSON line."""
+    import torch
+    import paper_1304_3771_amd as dv
+    from workload import device, gen
+
+    sp = gen.spec("C4")
+    log("serving: generating C4 (8 VMs x 4 GiB)")
+    wl = gen.make_workload(sp, requests=False)
+    ctx = dv.Context(0)
+    dw = device.load(ctx, wl)
+    log("serving: uploaded")
+    rates = [float(x) for x in args.rates.split(",")]
+    out_rates = []
+    pool = None
+    for lam in rates:
+        n_ops = int(max(lam * args.serve_seconds, args.serve_min_ops))
+        tr = gen.make_serving_trace(wl, n_ops, lam)
+        if pool is None or pool.numel() < tr.pool_bytes:
+            pool = torch.empty(tr.pool_bytes, dtype=torch.uint8, device="cuda")
+        reqs = tr.requests.copy()
+        reqs["host"] += np.uint64(pool.data_ptr())
+        srv = ctx.server_start(max_inflight=args.max_inflight, pool_bytes=args.pool_gib << 30,
+                               max_batch=args.max_batch, streams=args.streams)
+        comps = []
+        t0 = time.monotonic_ns()
+        i = 0
+        try:
+            while i < n_ops:
+                now = time.monotonic_ns() - t0
+                j = int(np.searchsorted(tr.arrival_ns, now, side="right"))
+                if j > i:
+                    srv.submit(reqs[i:j])
+                    i = j
+                c = srv.poll(1 << 16)
+                if len(c):
+                    comps.append(c)
+            srv.drain()
+            while True:
+                c = srv.poll(1 << 20)
+                if not len(c):
+                    break
+                comps.append(c)
+        finally:
+            srv.stop()
+        c = np.concatenate(comps)
+        c = c[np.argsort(c["ticket"])]
+        lat = (c["t_done_ns"].astype(np.int64) - (t0 + tr.arrival_ns.astype(np.int64))) / 1e3
+        span = (c["t_done_ns"].max() - t0) / 1e9
+        nbytes = int(c["bytes_done"].sum())
+        rec = {"rate_mreq_s": lam / 1e6, "ops": n_ops, "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
+               "throughput_mreq_s": n_ops / span / 1e6, "gbs": nbytes / span / 1e9}
+        # the plain per-request path at the same arrival rate (bounded sample)
+        m = min(n_ops, args.serve_plain_ops)
+        stream = torch.cuda.current_stream()
+        res = torch.zeros(m * 24, dtype=torch.uint8, device="cuda")
+        done = np.zeros(m, np.int64)
+        t0p = time.monotonic_ns()
+        for k in range(m):
+            while time.monotonic_ns() - t0p < int(tr.arrival_ns[k]):
+                pass
+            q = reqs[k]
+            f = ctx.copy_to_guest if int(q["dir"]) == 1 else ctx.copy_from_guest
+            f(int(q["asid"]), int(q["gva"]), int(q["host"]), int(q["len"]), res.data_ptr() + 24 * k, stream)
+            stream.synchronize()
+            done[k] = time.monotonic_ns()
+        plat = (done - (t0p + tr.arrival_ns[:m].astype(np.int64))) / 1e3
+        rec["per_request"] = {"ops": m, "p50_us": pct(plat, 50), "p99_us": pct(plat, 99),
+                              "throughput_mreq_s": m / ((done[-1] - t0p) / 1e9) / 1e6}
+        log(f"lambda {lam / 1e6:.2f} M/s: served p50 {rec['p50_us']:.0f} us p99 {rec['p99_us']:.0f} us, "
+            f"{rec['throughput_mreq_s']:.3f} Mreq/s, {rec['gbs']:.1f} GB/s; per-request p50 "
+            f"{rec['per_request']['p50_us']:.0f} us p99 {rec['per_request']['p99_us']:.0f} us")
+        out_rates.append(rec)
+    ctx.close()
+    print(json.dumps({"metric": "serving p50/p99 latency and throughput, C4", "unit": "us", "n_gpus": 1,
+                      "data": "synthetic", "dtype": "u8",
+                      "config": {"workload": "C4: 8 VMs x 4 GiB, 4 processes x 64 guest threads each, Poisson "
+                                             "arrivals, 60% 24B / 25% 4KiB / 14% 16-256KiB / 1% 4147200B",
+                                 "max_inflight": args.max_inflight, "pool_gib": args.pool_gib,
+                                 "max_batch": args.max_batch, "streams": args.streams},
+                      "rates": out_rates}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +183,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="autotune the batch launch first")
     ap.add_argument("--profile-only", action="store_true", help="only run K timed steps (for rocprofv3)")
+    ap.add_argument("--serving", action="store_true", help="run the C4 serving sweep instead")
+    ap.add_argument("--rates", default="1e5,2.5e5,5e5,1e6,2e6,5e6")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-min-ops", type=int, default=200000)
+    ap.add_argument("--serve-plain-ops", type=int, default=20000)
+    ap.add_argument("--max-inflight", type=int, default=8192)
+    ap.add_argument("--pool-gib", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=4096)
+    ap.add_argument("--streams", type=int, default=4)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -115,6 +207,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dv.lib()
+    if args.serving:
+        return serving(args)
 
     t_gen = time.time()
     sp = gen.spec(args.workload)

@@ -77,6 +77,9 @@ Workspace::~Workspace() {
     hipFree(t0);
 }
 
+// While a serving loop runs, only its own thread may drive the context.
+static bool server_owns(const devirt_ctx *c) { return c->server != nullptr && !dv_in_server_thread(); }
+
 static int set_dev(devirt_ctx *c) {
     HIPCHK(hipSetDevice(c->device));
     return 0;
@@ -127,6 +130,7 @@ extern "C" int devirt_close(devirt_ctx *c) {
         hipEventDestroy(p.a);
         hipEventDestroy(p.b);
     }
+    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
     delete c;
     return 0;
 }
@@ -176,6 +180,7 @@ static int upload_procs(devirt_ctx *c) {
 extern "C" int devirt_vm_create(devirt_ctx *c, uint64_t arena_bytes, uint32_t *vm) {
     if (!c || !vm) return dv_fail(-EINVAL, "NULL argument");
     if (arena_bytes == 0 || (arena_bytes & 4095)) return dv_fail(-EINVAL, "arena_bytes must be a non-zero multiple of 4096");
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
     if (c->vms.size() >= 0xFFFF) return dv_fail(-EINVAL, "too many VMs");
     if (set_dev(c)) return -EIO;
     HIPCHK(hipDeviceSynchronize());
@@ -206,6 +211,7 @@ static int vm_copy(devirt_ctx *c, uint32_t vm, uint64_t off, void *host_or_dev, 
     if (!c) return dv_fail(-EINVAL, "ctx is NULL");
     if (vm >= c->vms.size()) return dv_fail(-ENOENT, "no VM %u", vm);
     if (bytes == 0) return 0;
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
     if (!host_or_dev) return dv_fail(-EINVAL, "NULL buffer");
     const VmHost &v = c->vms[vm];
     if (off > v.bytes || bytes > v.bytes - off) return dv_fail(-EINVAL, "range leaves the arena");
@@ -260,6 +266,7 @@ extern "C" int devirt_memslot_set(devirt_ctx *c, uint32_t vm, uint32_t slot, uin
     if (!c) return dv_fail(-EINVAL, "ctx is NULL");
     if (vm >= c->vms.size()) return dv_fail(-ENOENT, "no VM %u", vm);
     if (slot >= 64) return dv_fail(-EINVAL, "slot must be 0..63");
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
     VmHost &v = c->vms[vm];
     if (bytes != 0) {
         if ((gpa | bytes | arena_off) & 4095) return dv_fail(-EINVAL, "gpa, bytes and arena_off must be 4 KiB aligned");
@@ -311,6 +318,7 @@ extern "C" int devirt_process_create(devirt_ctx *c, uint32_t vm, uint64_t cr3_gp
     if (!c || !asid) return dv_fail(-EINVAL, "NULL argument");
     if (vm >= c->vms.size()) return dv_fail(-ENOENT, "no VM %u", vm);
     if (levels != 4 && levels != 5) return dv_fail(-EINVAL, "levels must be 4 or 5");
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
     if (c->procs.size() >= 0x7FFFFFFF) return dv_fail(-EINVAL, "too many processes");
     if (set_dev(c)) return -EIO;
     HIPCHK(hipDeviceSynchronize());
@@ -498,6 +506,7 @@ extern "C" int devirt_translate(devirt_ctx *c, uint32_t asid, const uint64_t *gv
                                 devirt_xlat *out_dev, void *stream) {
     if (!c) return dv_fail(-EINVAL, "ctx is NULL");
     if (flags & ~(DEVIRT_XLAT_WRITE | DEVIRT_XLAT_SET_AD)) return dv_fail(-EINVAL, "unknown flags");
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
     if (n == 0) return 0;
     if (!gva_dev || !out_dev) return dv_fail(-EINVAL, "NULL buffer");
     if (set_dev(c)) return -EIO;
@@ -525,6 +534,7 @@ static int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host,
     if (!c) return dv_fail(-EINVAL, "ctx is NULL");
     if (!res) return dv_fail(-EINVAL, "res_dev is NULL");
     if (len >= (1ull << 32)) return dv_fail(-EINVAL, "len must be < 2^32");
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
     if (len && !host) return dv_fail(-EINVAL, "NULL host buffer");
     if (set_dev(c)) return -EIO;
     hipStream_t s = (hipStream_t)stream;
@@ -562,9 +572,8 @@ extern "C" int devirt_copy_to_guest(devirt_ctx *c, uint32_t asid, uint64_t gva, 
     return plain_copy(c, asid, gva, (uint64_t)(uintptr_t)src, len, DEVIRT_TO_GUEST, res, stream);
 }
 
-// Enqueue one batch (no capture logic here).
-static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a) {
-    hipStream_t s = w->stream;
+// Enqueue one batch on stream `s` using workspace `w` (no capture logic here).
+static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStream_t s) {
     DBatch b = make_batch(c, w);
     b.reqs = a.reqs;
     b.res = a.res;
@@ -612,6 +621,13 @@ extern "C" int devirt_submit_batch(devirt_ctx *c, const devirt_request *reqs, ui
                                    uint32_t n_epochs, devirt_result *res, devirt_fault *faults, uint64_t *n_faults,
                                    uint64_t *t_done, void *stream) {
     if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
+    return dv_submit(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, t_done, (hipStream_t)stream, true);
+}
+
+int dv_submit(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint64_t *epoch_end, uint32_t n_epochs,
+              devirt_result *res, devirt_fault *faults, uint64_t *n_faults, uint64_t *t_done, hipStream_t s,
+              bool allow_graph) {
     if (n && (!reqs || !res)) return dv_fail(-EINVAL, "NULL request or result buffer");
     if (((uintptr_t)reqs & 15) || ((uintptr_t)res & 7)) return dv_fail(-EINVAL, "reqs must be 16-byte aligned");
     BatchArgs a;
@@ -634,14 +650,13 @@ extern "C" int devirt_submit_batch(devirt_ctx *c, const devirt_request *reqs, ui
         a.epochs.assign(1, n);
     }
     if (set_dev(c)) return -EIO;
-    hipStream_t s = (hipStream_t)stream;
     Workspace *w = get_ws(c, s);
     int rc = ensure_ws(c, w, n, a.epochs.size(), t_done != nullptr, 0);
     if (rc) return rc;
     c->stats.batches++;
     c->stats.epochs += a.epochs.size();
-    const bool capturing = stream_capturing(s);
-    if (!c->cfg.use_graph || c->profiling || capturing || n == 0) return enqueue_batch(c, w, a);
+    if (!allow_graph || !c->cfg.use_graph || c->profiling || n == 0 || stream_capturing(s))
+        return enqueue_batch(c, w, a, s);
     // graph cache: key = every argument that ends up in a kernel parameter
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)reqs, n, (uint64_t)(uintptr_t)res, (uint64_t)(uintptr_t)faults,
                                  (uint64_t)(uintptr_t)n_faults, (uint64_t)(uintptr_t)t_done, c->tables_version,
@@ -655,10 +670,13 @@ extern "C" int devirt_submit_batch(devirt_ctx *c, const devirt_request *reqs, ui
             return 0;
         }
     }
+    // Capture on a private non-blocking stream (the legacy null stream cannot be
+    // captured), then launch the graph on the caller's stream.
+    if (!c->capture_stream) HIPCHK(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
-    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_batch(c, w, a);
-    hipError_t ee = hipStreamEndCapture(s, &graph);
+    HIPCHK(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_batch(c, w, a, c->capture_stream);
+    hipError_t ee = hipStreamEndCapture(c->capture_stream, &graph);
     if (rc) {
         if (graph) hipGraphDestroy(graph);
         return rc;

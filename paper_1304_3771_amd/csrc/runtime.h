@@ -69,6 +69,7 @@ struct devirt_ctx {
     dv::DCounters *d_counters = nullptr;
     std::list<ProfEv> prof;
     void *server = nullptr;  // non-null while a serving loop owns the context
+    hipStream_t capture_stream = nullptr;  // private stream batches are captured on
 };
 
 struct BatchArgs {
@@ -86,3 +87,7 @@ dv::DView view_of(const devirt_ctx *c);
 Workspace *get_ws(devirt_ctx *c, hipStream_t s);
 int ensure_ws(devirt_ctx *c, Workspace *w, uint64_t n_req, uint64_t n_epochs, bool need_pending, uint64_t min_segs);
 dv::DBatch make_batch(devirt_ctx *c, Workspace *w);
+int dv_submit(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint64_t *epoch_end, uint32_t n_epochs,
+              devirt_result *res, devirt_fault *faults, uint64_t *n_faults, uint64_t *t_done, hipStream_t s,
+              bool allow_graph);
+bool dv_in_server_thread();

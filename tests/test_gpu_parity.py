@@ -57,7 +57,7 @@ def test_golden_translate(widx):
     try:
         for write in (0, 1):
             qs = [q for q in world["queries"]]
-            g = torch.tensor([pins.H(q["gva"]) for q in qs], dtype=torch.int64).cuda()
+            g = torch.from_numpy(np.array([pins.H(q["gva"]) for q in qs], dtype=np.uint64).view(np.int64)).cuda()
             out = torch.zeros(len(qs) * 24, dtype=torch.uint8).cuda()
             ctx.translate(0, g, len(qs), dv.XLAT_WRITE if write else 0, out)
             ctx.sync()
@@ -218,14 +218,11 @@ def test_translate_matches_oracle():
                     ctx.sync()
                     x = out.cpu().numpy().view(dv.XLAT_DTYPE)
                     e = o.translate(p.asid, g, flags)
-                    bad = np.nonzero(x.view(np.uint8).reshape(-1, 24).tobytes() != e.view(np.uint8).reshape(-1, 24)
-                                     .tobytes())
                     if not np.array_equal(x.view(np.uint8), e.view(np.uint8)):
                         i = int(np.nonzero((x.view(np.uint8).reshape(-1, 24) != e.view(np.uint8).reshape(-1, 24))
                                            .any(axis=1))[0][0])
                         raise AssertionError(f"{name} asid {p.asid} flags {flags} gva {hex(int(g[i]))}: "
                                              f"gpu {x[i]} oracle {e[i]}")
-                    del bad
             arenas = device.read_arenas(ctx, dw)
             for v in range(len(arenas)):
                 assert np.array_equal(arenas[v], o.arenas[v]), f"{name}: A/D state differs in vm {v}"

@@ -1,0 +1,135 @@
+"""Serving loop: every operation's result, and all memory, are the same alone
+(one operation at a time through the plain per-request path) and in the mix
+(continuous batching over several streams), and both equal the oracle.
+Tolerance: none (bit-exact)."""
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import log, new_ctx
+from oracle import Oracle
+from workload import device, gen
+
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+CLASSES = ((0.60, "uniform", 24, 24, 1), (0.25, "uniform", 4096, 4096, 0),
+           (0.14, "loguniform", 16 << 10, 256 << 10, 0), (0.01, "uniform", 1 << 20, 1 << 20, 1))
+
+
+@pytest.fixture(scope="module")
+def trace():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wl = gen.make_workload(gen.spec("C4", n_vms=2, procs_per_vm=2, mem_bytes=256 * MiB, seed=44), requests=False)
+    tr = gen.make_serving_trace(wl, 3000, 2e5, threads_per_proc=8, window=2 * MiB, classes=CLASSES,
+                                host_mode="unique", seed=45)
+    return wl, tr
+
+
+def _load(ctx, wl, tr):
+    import torch
+    dw = device.load(ctx, wl)
+    pool = torch.from_numpy(gen.fill_bytes(np.empty(tr.pool_bytes, np.uint8), wl.seed, gen.POOL_KEY)).cuda()
+    reqs = tr.requests.copy()
+    reqs["host"] += np.uint64(pool.data_ptr())
+    return dw, pool, reqs
+
+
+def test_alone_vs_mix(trace):
+    import torch
+    import paper_1304_3771_amd as dv
+    wl, tr = trace
+    n = len(tr.requests)
+    # alone: one operation at a time, in submission order
+    log("serving: alone")
+    ctx = new_ctx()
+    try:
+        dw, pool, reqs = _load(ctx, wl, tr)
+        res = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+        stream = torch.cuda.current_stream()
+        for i, r in enumerate(reqs):
+            f = ctx.copy_to_guest if int(r["dir"]) == 1 else ctx.copy_from_guest
+            f(int(r["asid"]), int(r["gva"]), int(r["host"]), int(r["len"]), res.data_ptr() + 24 * i, stream)
+            stream.synchronize()
+        alone_res = res.cpu().numpy().view(dv.RESULT_DTYPE).copy()
+        alone_arenas = device.read_arenas(ctx, dw)
+        alone_pool = pool.cpu().numpy()
+    finally:
+        ctx.close()
+    # in the mix: Poisson arrivals replayed in bursts into the serving loop
+    log("serving: mix")
+    ctx = new_ctx()
+    try:
+        dw, pool, reqs = _load(ctx, wl, tr)
+        srv = ctx.server_start(max_inflight=256, pool_bytes=4 * MiB, max_batch=64, streams=3)
+        comps = []
+        try:
+            t0 = time.monotonic_ns()
+            i = 0
+            while i < n:
+                now = time.monotonic_ns() - t0
+                j = int(np.searchsorted(tr.arrival_ns, now, side="right"))
+                j = max(j, i + 1)
+                srv.submit(reqs[i:j])
+                i = j
+                comps.append(srv.poll())
+            srv.drain()
+            comps.append(srv.poll(n))
+        finally:
+            srv.stop()
+        c = np.concatenate(comps)
+        assert len(c) == n and np.array_equal(np.sort(c["ticket"]), np.arange(n))
+        c = c[np.argsort(c["ticket"])]
+        mix_arenas = device.read_arenas(ctx, dw)
+        mix_pool = pool.cpu().numpy()
+    finally:
+        ctx.close()
+    for f in ("bytes_done", "fault_gva", "code", "level"):
+        assert np.array_equal(c[f], alone_res[f]), f
+    for a, b in zip(mix_arenas, alone_arenas):
+        assert np.array_equal(a, b)
+    assert np.array_equal(mix_pool, alone_pool)
+    # one operation in flight per guest thread; admitted ones overlap in time
+    key = reqs["asid"].astype(np.uint64) << np.uint64(32) | reqs["tag"].astype(np.uint64)
+    for k in np.unique(key):
+        idx = np.nonzero(key == k)[0]
+        assert np.all(c["t_admit_ns"][idx[1:]] >= c["t_done_ns"][idx[:-1]]), "two ops of one thread overlapped"
+    # the byte budget: at every admission the admitted-and-unfinished bytes fit the pool
+    ev = sorted([(int(t), 1, int(b)) for t, b in zip(c["t_admit_ns"], reqs["len"])] +
+                [(int(t), 0, -int(b)) for t, b in zip(c["t_done_ns"], reqs["len"])])
+    cur = peak = 0
+    for t, kind, b in ev:
+        cur += b
+        peak = max(peak, cur)
+    assert peak <= 4 * MiB or peak <= int(reqs["len"].max())
+    # both equal the oracle applied in submission order
+    arenas = [wl.arena_image(v) for v in range(len(wl.vms))]
+    opool = gen.fill_bytes(np.empty(tr.pool_bytes, np.uint8), wl.seed, gen.POOL_KEY)
+    o = Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], opool)
+    er, _ = o.batch(tr.requests)
+    for f in ("bytes_done", "fault_gva", "code", "level"):
+        assert np.array_equal(c[f], er[f]), f
+    for a, b in zip(mix_arenas, o.arenas):
+        assert np.array_equal(a, b)
+    assert np.array_equal(mix_pool, o.pool)
+
+
+def test_server_refuses_misuse(trace):
+    import paper_1304_3771_amd as dv
+    wl, tr = trace
+    ctx = new_ctx()
+    try:
+        with pytest.raises(dv.DevirtError):
+            ctx.server_start(max_inflight=0)
+        srv = ctx.server_start(max_inflight=16, pool_bytes=MiB, streams=2)
+        try:
+            with pytest.raises(dv.DevirtError):   # the server owns the context
+                ctx.vm_create(1 << 20)
+        finally:
+            srv.stop()
+        ctx.vm_create(1 << 20)                     # usable again after stop
+    finally:
+        ctx.close()

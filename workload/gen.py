@@ -586,3 +586,76 @@ def _make_requests(rng, sp: Spec, wl: Workload) -> None:
     wl.epoch_end = epoch_end
     wl.pool_bytes = pool
     wl.req_vma = vma
+
+
+# ---------------------------------------------------------------------------
+# serving traces
+# ---------------------------------------------------------------------------
+# Operation classes of the device classes the paper devirtualizes (input,
+# audio, GPU, camera): (share, length kind, lo, hi, direction).
+C4_CLASSES = (
+    (0.60, "uniform", 24, 24, TO_GUEST),                     # 64-bit input events, read() into the guest
+    (0.25, "uniform", 4096, 4096, FROM_GUEST),               # audio periods, write() from the guest
+    (0.14, "loguniform", 16 * KiB, 256 * KiB, FROM_GUEST),   # GPU command buffers, ioctl() submit
+    (0.01, "uniform", 4147200, 4147200, TO_GUEST),           # 1920x1080 YUYV camera frames, read()
+)
+
+
+@dataclass
+class ServingTrace:
+    requests: np.ndarray      # REQ_DTYPE; host = offset into the trace pool; tag = guest thread id
+    arrival_ns: np.ndarray    # uint64, ascending, from 0
+    pool_bytes: int
+    windows: np.ndarray       # (threads, 3) uint64: asid, tag, window base
+    rate_per_s: float
+
+
+def make_serving_trace(wl: Workload, n_ops: int, rate_per_s: float, threads_per_proc: int = 64,
+                       window: int = 6 * MiB, classes=C4_CLASSES, host_mode: str = "per_thread",
+                       seed: int | None = None) -> ServingTrace:
+    """Poisson arrivals of class-mixed operations from guest threads that each
+    own a private window of mapped virtual memory (so operations of different
+    threads never overlap, and one thread's operations run one at a time).
+
+    host_mode "per_thread": each thread owns one host buffer of `window` bytes
+    (enough for any of its operations, which never overlap in time);
+    "unique": every operation gets its own host bytes."""
+    rng = np.random.default_rng(wl.seed * 7 + 1 if seed is None else seed)
+    wins = []
+    for p in wl.procs:
+        k = 0
+        for b, s in p.vmas:
+            for j in range(int(s) // window):
+                if k < threads_per_proc:
+                    wins.append((p.asid, k, int(b) + j * window))
+                    k += 1
+        if k < threads_per_proc:
+            raise ValueError(f"process {p.asid} has room for {k} windows of {window} bytes, "
+                             f"{threads_per_proc} needed")
+    wins = np.array(wins, np.uint64)
+    nt = len(wins)
+    shares = np.array([c[0] for c in classes])
+    cls = rng.choice(len(classes), n_ops, p=shares / shares.sum())
+    length = np.zeros(n_ops, np.uint64)
+    direction = np.zeros(n_ops, np.uint8)
+    for i, (_, kind, lo, hi, d) in enumerate(classes):
+        m = cls == i
+        length[m] = np.minimum(draw_lengths(rng, kind, lo, hi, int(m.sum())), window)
+        direction[m] = d
+    th = rng.integers(0, nt, n_ops)
+    off = (rng.random(n_ops) * (np.uint64(window) - length + np.uint64(1)).astype(np.float64)).astype(np.uint64)
+    gva = wins[th, 2] + off
+    if host_mode == "unique":
+        skew = rng.integers(0, 64, n_ops).astype(np.uint64)
+        host = np.cumsum(length + skew) - length
+        pool = int(host[-1] + length[-1]) if n_ops else 0
+    else:
+        host = th.astype(np.uint64) * np.uint64(window) + rng.integers(0, 64, n_ops).astype(np.uint64)
+        host = np.minimum(host, th.astype(np.uint64) * np.uint64(window) + np.uint64(window) - length)
+        pool = nt * window
+    gaps = rng.exponential(1e9 / rate_per_s, n_ops)
+    arrival = np.cumsum(gaps).astype(np.uint64)
+    req = np.zeros(n_ops, REQ_DTYPE)
+    req["gva"], req["host"], req["len"] = gva, host, length.astype(np.uint32)
+    req["asid"], req["dir"], req["tag"] = wins[th, 0].astype(np.uint32), direction, wins[th, 1].astype(np.uint32)
+    return ServingTrace(req, arrival, (pool + 4095) & ~4095, wins, rate_per_s)
