@@ -183,6 +183,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="autotune the batch launch first")
     ap.add_argument("--profile-only", action="store_true", help="only run K timed steps (for rocprofv3)")
+    ap.add_argument("--set", default="", help="launch config overrides, e.g. seg_chunks=64,nontemporal=1")
     ap.add_argument("--serving", action="store_true", help="run the C4 serving sweep instead")
     ap.add_argument("--rates", default="1e5,2.5e5,5e5,1e6,2e6,5e6")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
@@ -217,8 +218,10 @@ def main():
     n = wl.n_requests
     log(f"generated {n} requests, {len(wl.epoch_end)} epochs in {time.time() - t_gen:.1f}s; uploading")
     ctx = dv.Context(0)
+    if args.set:
+        ctx.set_config(**{k: int(v) for k, v in (kv.split("=") for kv in args.set.split(","))})
     dw = device.load(ctx, wl)
-    log("uploaded")
+    log(f"uploaded; launch config {ctx.get_config()}")
     res = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
     faults = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
     nf = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -257,7 +260,15 @@ def main():
     gbs = copied / (ms_step * 1e-3) / 1e9
     log(f"batched: {ms_step:.3f} ms/step, {gbs:.1f} GB/s copied, {int(nf.item())} faults")
     if args.profile_only:
-        print(json.dumps({"workload": args.workload, "ms_per_step": ms_step, "gbs": gbs}))
+        # a plain copy-like kernel of known size (1 GiB read + 1 GiB written) to scale HBM counters
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        for _ in range(3):
+            torch.add(a, 1, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": args.workload, "ms_per_step": ms_step, "gbs": gbs,
+                          "copy_launches_per_step": int(len(wl.epoch_end)),
+                          "alg_copy_bytes_per_step": 2 * copied, "calibration_bytes_each_way": 1 << 30}))
         return
 
     # ---- roofline of the dominant kernel (copy), HIP events around each launch
@@ -278,7 +289,10 @@ def main():
             "kernel": "k_copy", "launches": copy_launches,
             "avg_launch_ms": round(copy_ms / copy_launches, 4),
             "alg_bytes_per_launch": alg_copy // copy_launches}
-    log(f"copy kernel: {copy_launches} launches, {copy_ms:.3f} ms, {achieved:.1f} GB/s algorithmic")
+    log(f"copy kernel: {copy_launches} launches, {copy_ms:.3f} ms, {achieved:.1f} GB/s algorithmic; "
+        f"translate kernel: {st['xlat_launches']} launches, {st['xlat_ms']:.3f} ms; pages {st['pages_walked']}, "
+        f"cache hits {st['cache_hits']} misses {st['cache_misses']}, segments {st['segments']}, "
+        f"A/D ORs {st['ad_atomics']}")
     path_alg = 2 * copied + 56 * n + 8 * st["pages_walked"] + 24 * int(nf.item())
     path_frac = path_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 

@@ -174,8 +174,9 @@ int devirt_copy_to_guest(devirt_ctx *ctx, uint32_t asid, uint64_t gva, const voi
 /* Many operations from many guests in one submission.  Results equal
  * applying the requests one after another in index order, provided that
  * inside each epoch no two requests touch overlapping guest bytes of one VM
- * or overlapping host bytes where one of them writes, and none writes a page
- * table; epochs run in order.  epoch_end_host: n_epochs ascending exclusive
+ * or overlapping host bytes where one of them writes, and that no request
+ * writes a guest page table; epochs run in order (translation of an epoch
+ * may run ahead, during the copies of the previous one).  epoch_end_host: n_epochs ascending exclusive
  * end indices, the last == n (NULL: one epoch).  res_dev: n devirt_result;
  * faults_dev: room for n devirt_fault (may be NULL together with
  * n_faults_dev); n_faults_dev: one uint64_t; t_done_dev: NULL or n uint64_t
@@ -205,6 +206,8 @@ typedef struct {
                                  and replay it                                     */
     uint32_t fused;           /* 1: run all epochs of a batch in one persistent
                                  launch with device-side epoch barriers             */
+    uint32_t overlap;         /* 1: translate epoch e+1 on a second stream while
+                                 epoch e is being copied                          */
 } devirt_config;
 
 int devirt_get_config(devirt_ctx *ctx, devirt_config *cfg);

@@ -265,59 +265,61 @@ __device__ __forceinline__ void store16(uint8_t *p, u32x4 v, bool nt) {
 
 // Whole-wavefront copy of n bytes (all arguments wave-uniform).  Every store
 // writes only bytes of [dst, dst+n); loads stay inside 16-byte blocks that
-// contain at least one source byte.
-__device__ void copy_wave(uint8_t *dst, const uint8_t *src, uint64_t n, bool nt) {
+// contain at least one source byte.  Each iteration moves up to 4 KiB of
+// 16-byte destination blocks and issues all of its loads -- the unaligned
+// head bytes, the body blocks and the tail bytes -- before any store, so a
+// segment of up to 4 KiB costs one memory round trip.
+__device__ void copy_wave(uint8_t *__restrict__ dst, const uint8_t *__restrict__ src, uint32_t n, bool nt) {
     const int lane = lane_id();
-    uint64_t h = (16u - ((uintptr_t)dst & 15u)) & 15u;
+    uint32_t h = (16u - (uint32_t)((uintptr_t)dst & 15u)) & 15u;
     if (h > n) h = n;
-    if ((uint64_t)lane < h) dst[lane] = src[lane];
-    dst += h;
-    src += h;
-    n -= h;
-    const uint64_t m = n >> 4;  // whole 16-byte destination blocks
-    const uint32_t o = (uint32_t)((uintptr_t)src & 15u);
-    const uint8_t *sa = src - o;
-    if (o == 0) {
-        for (uint64_t b0 = 0; b0 < m; b0 += 256) {
+    const int32_t m = (int32_t)((n - h) >> 4);  // whole 16-byte destination blocks
+    const uint32_t t = (n - h) & 15u;
+    const uint32_t o = (uint32_t)((uintptr_t)(src + h) & 15u);
+    const uint8_t *__restrict__ sa = src + h - o;  // 16-byte aligned source of the body
+    uint8_t *__restrict__ db = dst + h;
+    const uint32_t tail_off = h + 16u * (uint32_t)m;
+    int32_t b0 = 0;
+    do {
+        const bool first = b0 == 0;
+        const bool last = b0 + 256 >= m;
+        const int32_t rem = m - b0 - lane;  // this lane's block u exists when 64*u < rem
+        const u32x4 *ps = (const u32x4 *)(sa + 16 * (int64_t)(b0 + lane));
+        u32x4 *pd = (u32x4 *)(db + 16 * (int64_t)(b0 + lane));
+        uint8_t hb = 0, tb = 0;
+        if (first && (uint32_t)lane < h) hb = src[lane];
+        if (last && (uint32_t)lane < t) tb = src[tail_off + lane];
+        if (o == 0) {
             u32x4 v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                uint64_t blk = b0 + (uint64_t)(u * 64 + lane);
-                if (blk < m) v[u] = *(const u32x4 *)(sa + 16 * blk);
-            }
+            for (int u = 0; u < 4; ++u)
+                if (64 * u < rem) v[u] = ps[64 * u];
+            if (first && (uint32_t)lane < h) dst[lane] = hb;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (64 * u < rem) store16((uint8_t *)(pd + 64 * u), v[u], nt);
+        } else {
+            // source blocks 0..m are needed (m+1 blocks, each holds a source byte)
+            u32x4 cur[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                uint64_t blk = b0 + (uint64_t)(u * 64 + lane);
-                if (blk < m) store16(dst + 16 * blk, v[u], nt);
-            }
-        }
-    } else {
-        // source blocks 0..m are needed (m+1 blocks, each holds a source byte)
-        for (uint64_t b0 = 0; b0 < m; b0 += 256) {
-            u32x4 cur[4], nxt[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                uint64_t blk = b0 + (uint64_t)(u * 64 + lane);
                 cur[u] = (u32x4){0u, 0u, 0u, 0u};
-                if (blk <= m) cur[u] = *(const u32x4 *)(sa + 16 * blk);
+                if (64 * u <= rem) cur[u] = ps[64 * u];
             }
-            u32x4 tail = (u32x4){0u, 0u, 0u, 0u};
-            if (lane == 63 && b0 + 256 <= m) tail = *(const u32x4 *)(sa + 16 * (b0 + 256));
+            u32x4 extra = (u32x4){0u, 0u, 0u, 0u};
+            if (lane == 63 && 256 <= rem + 63) extra = ps[193];  // block b0 + 256
+            if (first && (uint32_t)lane < h) dst[lane] = hb;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                u32x4 down = shfl_down1(cur[u]);
-                u32x4 wrap = (u < 3) ? readlane0(cur[u + 1 < 4 ? u + 1 : 3]) : tail;
-                nxt[u] = (lane == 63) ? wrap : down;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                uint64_t blk = b0 + (uint64_t)(u * 64 + lane);
-                if (blk < m) store16(dst + 16 * blk, funnel16(cur[u], nxt[u], o), nt);
+                const u32x4 down = shfl_down1(cur[u]);
+                const u32x4 wrap = (u < 3) ? readlane0(cur[u + 1 < 4 ? u + 1 : 3]) : extra;
+                const u32x4 nxt = (lane == 63) ? wrap : down;
+                if (64 * u < rem) store16((uint8_t *)(pd + 64 * u), funnel16(cur[u], nxt, o), nt);
             }
         }
-    }
-    const uint64_t t = n & 15u;
-    if ((uint64_t)lane < t) dst[16 * m + lane] = src[16 * m + lane];
+        if (last && (uint32_t)lane < t) dst[tail_off + lane] = tb;
+        b0 += 256;
+    } while (b0 < m);
 }
 
 // Copy by one lane (short segments).
@@ -790,8 +792,11 @@ __global__ void __launch_bounds__(1024) k_copy(DBatch b, uint32_t epoch) {
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t w0 = uniform_u64((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const bool nt = b.nontemporal != 0;
+    if (w0 >= nseg) return;
+    DSeg next = b.segs[w0];
     for (uint64_t s = w0; s < nseg; s += waves) {
-        const DSeg sg = b.segs[s];
+        const DSeg sg = next;
+        if (s + waves < nseg) next = b.segs[s + waves];  // prefetch the next record
         copy_wave((uint8_t *)uniform_u64(sg.dst), (const uint8_t *)uniform_u64(sg.src), uniform_u32(sg.len), nt);
         if (b.t_done && lane_id() == 0) {
             uint32_t old = atomicSub(&b.pending[sg.req], 1u);

@@ -41,16 +41,17 @@ extern "C" const char *devirt_last_error(void) { return g_err.c_str(); }
 // ------------------------------------------------------------------ config
 static devirt_config default_config() {
     devirt_config c;
-    c.group = 32;
+    c.group = 64;
     c.seg_chunks = 16;
     c.xlat_wg = 256;
     c.xlat_wgs_per_cu = 8;
     c.copy_wg = 256;
-    c.copy_wgs_per_cu = 8;
+    c.copy_wgs_per_cu = 16;
     c.nontemporal = 0;
     c.inline_bytes = 0;
     c.use_graph = 1;
     c.fused = 0;
+    c.overlap = 0;
     return c;
 }
 
@@ -63,13 +64,18 @@ static int check_config(const devirt_config &c) {
     if (c.copy_wgs_per_cu < 1 || c.copy_wgs_per_cu > 64) return dv_fail(-EINVAL, "copy_wgs_per_cu must be 1..64");
     if (c.nontemporal > 1 || c.use_graph > 1) return dv_fail(-EINVAL, "nontemporal/use_graph must be 0 or 1");
     if (c.inline_bytes > 256) return dv_fail(-EINVAL, "inline_bytes must be <= 256");
-    if (c.fused > 1) return dv_fail(-EINVAL, "fused must be 0 or 1");
+    if (c.fused > 1 || c.overlap > 1) return dv_fail(-EINVAL, "fused/overlap must be 0 or 1");
     return 0;
 }
 
 // ------------------------------------------------------------------ context
 Workspace::~Workspace() {
     for (auto &g : graphs) hipGraphExecDestroy(g.exec);
+    for (auto e : events) hipEventDestroy(e);
+    if (side) {
+        hipStreamSynchronize(side);
+        hipStreamDestroy(side);
+    }
     hipFree(segs);
     hipFree(ctr);
     hipFree(pending);
@@ -573,31 +579,65 @@ extern "C" int devirt_copy_to_guest(devirt_ctx *c, uint32_t asid, uint64_t gva, 
 }
 
 // Enqueue one batch on stream `s` using workspace `w` (no capture logic here).
+//
+// Translation of an epoch does not depend on the copies of earlier epochs
+// (page tables only change in their A/D bits, which are OR-ed), so with
+// several epochs the translate launches run on a side stream ahead of the
+// copies: translate(e) overlaps copy(e-1).  The segment queue is split in two
+// halves used by alternate epochs; translate(e) waits for copy(e-2), the last
+// user of its half.  Copies stay in epoch order on `s`.
 static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStream_t s) {
     DBatch b = make_batch(c, w);
     b.reqs = a.reqs;
     b.res = a.res;
     b.t_done = a.t_done;
     const DView v = view_of(c);
-    HIPCHK(launch_reset(s, b, (uint32_t)a.epochs.size()));
+    const size_t ne = a.epochs.size();
+    HIPCHK(launch_reset(s, b, (uint32_t)ne));
+    const bool overlap = ne > 1 && c->cfg.overlap;
+    hipStream_t side = s;
+    if (overlap) {
+        if (!w->side) HIPCHK(hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking));
+        side = w->side;
+        while (w->events.size() < 2 * ne + 1) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            w->events.push_back(e);
+        }
+        HIPCHK(hipEventRecord(w->events[2 * ne], s));  // fork: the side stream starts after the reset
+        HIPCHK(hipStreamWaitEvent(side, w->events[2 * ne], 0));
+    }
+    const uint64_t half = overlap ? w->seg_cap / 2 : w->seg_cap;
     uint64_t r0 = 0;
     int rc;
-    for (size_t e = 0; e < a.epochs.size(); ++e) {
-        uint64_t r1 = a.epochs[e];
+    for (size_t e = 0; e < ne; ++e) {
+        const uint64_t r1 = a.epochs[e];
+        DBatch be = b;
+        be.segs = w->segs + (overlap ? (e & 1) * half : 0);
+        be.seg_cap = half;
+        hipEvent_t t_done = overlap ? w->events[2 * e] : nullptr;
+        hipEvent_t c_done = overlap ? w->events[2 * e + 1] : nullptr;
         if (r1 > r0) {
-            uint64_t groups = (r1 - r0 + c->cfg.group - 1) / c->cfg.group;
+            const uint64_t groups = (r1 - r0 + c->cfg.group - 1) / c->cfg.group;
+            if (overlap && e >= 2) HIPCHK(hipStreamWaitEvent(side, w->events[2 * (e - 2) + 1], 0));
             ProfEv *pe;
-            if ((rc = prof_begin(c, s, 1, &pe))) return rc;
-            HIPCHK(launch_translate_groups(s, grid_for(c, groups, c->cfg.xlat_wg, c->cfg.xlat_wgs_per_cu),
-                                           (int)c->cfg.xlat_wg, v, b, r0, r1, (uint32_t)e));
-            if ((rc = prof_end(c, s, pe))) return rc;
+            if ((rc = prof_begin(c, side, 1, &pe))) return rc;
+            HIPCHK(launch_translate_groups(side, grid_for(c, groups, c->cfg.xlat_wg, c->cfg.xlat_wgs_per_cu),
+                                           (int)c->cfg.xlat_wg, v, be, r0, r1, (uint32_t)e));
+            if ((rc = prof_end(c, side, pe))) return rc;
+            if (overlap) {
+                HIPCHK(hipEventRecord(t_done, side));
+                HIPCHK(hipStreamWaitEvent(s, t_done, 0));
+            }
             if ((rc = prof_begin(c, s, 0, &pe))) return rc;
-            HIPCHK(launch_copy(s, (int)((uint64_t)c->cus * c->cfg.copy_wgs_per_cu), (int)c->cfg.copy_wg, b,
+            HIPCHK(launch_copy(s, (int)((uint64_t)c->cus * c->cfg.copy_wgs_per_cu), (int)c->cfg.copy_wg, be,
                                (uint32_t)e));
             if ((rc = prof_end(c, s, pe))) return rc;
         }
+        if (overlap) HIPCHK(hipEventRecord(c_done, s));
         r0 = r1;
     }
+    // every translate launch is already joined into `s` through its copy's wait
     if (a.faults || a.n_faults) {
         uint64_t tiles = (a.n + kFaultTile - 1) / kFaultTile;
         HIPCHK(launch_fault_count(s, a.res, a.n, w->tiles));
