@@ -322,9 +322,11 @@ void orc_translate(orc_state *s, uint32_t asid, const uint64_t *gvas, uint64_t n
 
 /* ----------------------------------------------------------------- copy -- */
 /* One copy between guest memory at req->gva and the pool at req->host,
- * page by page (section 4.2).  Returns -1 if the request names pool bytes
- * outside the pool (a caller error the tests never make). */
-int orc_copy(orc_state *s, const orc_req *req, orc_result *res) {
+ * page by page (section 4.2).  With move == 0 only the result is computed:
+ * no byte moves and no A/D update (a result depends only on the page tables,
+ * whose translation bits copies never change).  Returns -1 if the request
+ * names pool bytes outside the pool (a caller error the tests never make). */
+static int copy_req(orc_state *s, const orc_req *req, orc_result *res, int move) {
     memset(res, 0, sizeof(*res));
     if (req->asid >= s->nproc) {
         res->code = ORC_INVALID;
@@ -339,7 +341,7 @@ int orc_copy(orc_state *s, const orc_req *req, orc_result *res) {
         res->fault_gva = req->gva;
         return 0;
     }
-    if (req->host > s->pool_bytes || (uint64_t)req->len > s->pool_bytes - req->host) return -1;
+    if (move && (req->host > s->pool_bytes || (uint64_t)req->len > s->pool_bytes - req->host)) return -1;
     int to_guest = req->dir != 0;
     uint8_t *arena = s->vms[p->vm].arena;
     uint64_t end = req->gva + req->len;
@@ -355,6 +357,7 @@ int orc_copy(orc_state *s, const orc_req *req, orc_result *res) {
             res->level = (uint16_t)w.level;
             return 0;
         }
+        if (!move) continue;
         set_ad(s, p, &w, to_guest);
         uint8_t *g = arena + w.hpa;
         uint8_t *h = s->pool + req->host + (lo - req->gva);
@@ -367,13 +370,15 @@ int orc_copy(orc_state *s, const orc_req *req, orc_result *res) {
     return 0;
 }
 
+int orc_copy(orc_state *s, const orc_req *req, orc_result *res) { return copy_req(s, req, res, 1); }
+
 /* A batch is its requests applied one after another in index order; the
  * fault list holds one record per request whose code is not OK, ascending
  * by request index.  Returns the number of faults, or -1 on a pool error. */
-int64_t orc_batch(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res, orc_fault *faults) {
+static int64_t batch(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res, orc_fault *faults, int move) {
     int64_t nf = 0;
     for (uint64_t i = 0; i < n; i++) {
-        if (orc_copy(s, &reqs[i], &res[i]) != 0) return -1;
+        if (copy_req(s, &reqs[i], &res[i], move) != 0) return -1;
         if (res[i].code != ORC_OK) {
             if (faults) {
                 faults[nf].req_index = i;
@@ -386,6 +391,15 @@ int64_t orc_batch(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res
         }
     }
     return nf;
+}
+
+int64_t orc_batch(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res, orc_fault *faults) {
+    return batch(s, reqs, n, res, faults, 1);
+}
+
+/* Results and fault list of a batch, without moving bytes or touching A/D. */
+int64_t orc_batch_results(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res, orc_fault *faults) {
+    return batch(s, reqs, n, res, faults, 0);
 }
 
 /* ------------------------------------------------------ conflict checker -- */

@@ -62,6 +62,8 @@ def _load(path: str | None = None):
         lib.orc_copy.restype = ctypes.c_int
         lib.orc_batch.argtypes = [vp, vp, u64, vp, vp]
         lib.orc_batch.restype = ctypes.c_int64
+        lib.orc_batch_results.argtypes = [vp, vp, u64, vp, vp]
+        lib.orc_batch_results.restype = ctypes.c_int64
         lib.orc_check_conflicts.argtypes = [vp, vp, u64, vp, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         lib.orc_check_conflicts.restype = ctypes.c_int
         _libs[key] = lib
@@ -134,6 +136,15 @@ class Oracle:
         nf = self._lib.orc_batch(self._h, r.ctypes.data, n, res.ctypes.data, faults.ctypes.data)
         if nf < 0:
             raise ValueError("request names pool bytes outside the pool")
+        return res, faults[:nf].copy()
+
+    def batch_results(self, reqs):
+        """Results and fault list only (no byte moves, no A/D updates)."""
+        r = np.ascontiguousarray(reqs)
+        n = len(r)
+        res = np.zeros(n, RESULT_DTYPE)
+        faults = np.zeros(n, FAULT_DTYPE)
+        nf = self._lib.orc_batch_results(self._h, r.ctypes.data, n, res.ctypes.data, faults.ctypes.data)
         return res, faults[:nf].copy()
 
     def check_conflicts(self, reqs, epoch_end=None):

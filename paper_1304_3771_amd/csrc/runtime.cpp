@@ -44,14 +44,14 @@ static devirt_config default_config() {
     c.group = 64;
     c.seg_chunks = 16;
     c.xlat_wg = 256;
-    c.xlat_wgs_per_cu = 8;
-    c.copy_wg = 256;
-    c.copy_wgs_per_cu = 16;
+    c.xlat_wgs_per_cu = 1;
+    c.copy_wg = 512;
+    c.copy_wgs_per_cu = 8;
     c.nontemporal = 0;
     c.inline_bytes = 0;
     c.use_graph = 1;
     c.fused = 0;
-    c.overlap = 0;
+    c.overlap = 1;
     return c;
 }
 
@@ -769,17 +769,22 @@ extern "C" int devirt_autotune(devirt_ctx *c, const devirt_request *reqs, uint64
     hipStream_t s = (hipStream_t)stream;
     const devirt_config base = c->cfg;
     std::vector<devirt_config> cand;
-    for (uint32_t group : {16u, 32u, 64u})
-        for (uint32_t segc : {4u, 16u, 64u})
-            for (uint32_t cwpc : {4u, 8u})
-                for (uint32_t nt : {0u, 1u}) {
-                    devirt_config k = base;
-                    k.group = group;
-                    k.seg_chunks = segc;
-                    k.copy_wgs_per_cu = cwpc;
-                    k.nontemporal = nt;
-                    cand.push_back(k);
-                }
+    for (uint32_t group : {32u, 64u})
+        for (uint32_t segc : {16u, 64u})
+            for (uint32_t cwg : {256u, 512u})
+                for (uint32_t cwpc : {4u, 8u, 16u})
+                    for (uint32_t ov : {0u, 1u})
+                        for (uint32_t xw : {1u, 2u}) {
+                            if (!ov && xw != 1) continue;
+                            devirt_config k = base;
+                            k.group = group;
+                            k.seg_chunks = segc;
+                            k.copy_wg = cwg;
+                            k.copy_wgs_per_cu = cwpc;
+                            k.overlap = ov;
+                            k.xlat_wgs_per_cu = ov ? xw : 8;
+                            cand.push_back(k);
+                        }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));

@@ -70,3 +70,18 @@ def test_conflict_checker_finds_planted_overlap():
     x = o.translate(int(r["asid"][0]), [int(r["gva"][0])])[0]
     if x["code"] == 0:
         assert o.check_conflicts(r, [len(r)]) is not None
+
+
+@pytest.mark.parametrize("name", ["c1", "multi_vm", "lvl5_1g", "prot"])
+def test_results_only_mode_matches_full_batch(name):
+    """Results do not depend on bytes or A/D: the results-only walk equals the full batch."""
+    import numpy as np
+    from oracle import Oracle
+    w = wl(name)
+    full = Oracle.from_workload(w).batch(w.requests)
+    o = Oracle.from_workload(w)
+    a0 = [a.copy() for a in o.arenas]
+    p0 = o.pool.copy()
+    only = o.batch_results(w.requests)
+    assert np.array_equal(full[0], only[0]) and np.array_equal(full[1], only[1])
+    assert all(np.array_equal(a, b) for a, b in zip(a0, o.arenas)) and np.array_equal(p0, o.pool)
