@@ -34,6 +34,28 @@
 namespace dv {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// Global-address-space views: the copy path and the table walks address HBM
+// through integers, so without these the compiler emits flat instructions
+// (which also count against the LDS counter and serialise with shuffles).
+// (The host compilation pass only parses device functions; it gets no qualifier.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define DV_GLOBAL __attribute__((address_space(1)))
+#else
+#define DV_GLOBAL
+#endif
+typedef DV_GLOBAL u32x4 g_u32x4;
+typedef DV_GLOBAL uint8_t g_u8;
+typedef DV_GLOBAL uint64_t g_u64;
+typedef DV_GLOBAL unsigned int g_u32;
+
+template <class T>
+__device__ __forceinline__ T *gp(uint64_t a) {
+    return (T *)(uintptr_t)a;
+}
+template <class T, class P>
+__device__ __forceinline__ T *gp(P *a) {
+    return (T *)(uintptr_t)a;
+}
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kCacheWays = 16;  // 1 GiB-region cache entries per wavefront
@@ -60,12 +82,12 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t x, int src) {
 __device__ __forceinline__ uint32_t shfl32(uint32_t x, int src) { return (uint32_t)__shfl((int)x, src); }
 
 __device__ __forceinline__ uint64_t load_entry(const uint8_t *arena, uint64_t off) {
-    return *(const uint64_t *)(arena + off);
+    return *gp<const g_u64>(arena + off);
 }
 
 // OR bits into the low dword of a page-table entry (A and D live in bits 5, 6).
 __device__ __forceinline__ void or_entry(uint8_t *arena, uint64_t off, uint32_t bits) {
-    __hip_atomic_fetch_or((unsigned int *)(arena + off), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_or(gp<g_u32>(arena + off), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t now_ns(const DBatch &b) {
@@ -80,7 +102,7 @@ __device__ __forceinline__ uint64_t now_ns(const DBatch &b) {
 __device__ __forceinline__ bool slot_lookup(const DVm &v, uint64_t gpa, uint64_t &hpa) {
     uint64_t blk = gpa >> 21;
     if (blk < v.index_len) {
-        uint64_t e = v.index[blk];
+        uint64_t e = gp<const g_u64>(v.index)[blk];
         if (e & 2) {
             hpa = gpa + (e & ~0xFFFull);
             return true;
@@ -89,16 +111,18 @@ __device__ __forceinline__ bool slot_lookup(const DVm &v, uint64_t gpa, uint64_t
     } else if (v.index_complete) {
         return false;
     }
+    typedef DV_GLOBAL DSlot g_slot;
+    const g_slot *slots = gp<const g_slot>(v.slots);
     uint32_t lo = 0, hi = v.nslots;
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
-        if (v.slots[mid].gpa <= gpa)
+        if (slots[mid].gpa <= gpa)
             lo = mid + 1;
         else
             hi = mid;
     }
     if (lo == 0) return false;
-    DSlot s = v.slots[lo - 1];
+    DSlot s = slots[lo - 1];
     if (gpa >= s.end) return false;
     hpa = s.arena_off + (gpa - s.gpa);
     return true;
@@ -256,11 +280,11 @@ __device__ __forceinline__ u32x4 readlane0(u32x4 v) {
     return r;
 }
 
-__device__ __forceinline__ void store16(uint8_t *p, u32x4 v, bool nt) {
+__device__ __forceinline__ void store16(g_u32x4 *p, u32x4 v, bool nt) {
     if (nt)
-        __builtin_nontemporal_store(v, (u32x4 *)p);
+        __builtin_nontemporal_store(v, p);
     else
-        *(u32x4 *)p = v;
+        *p = v;
 }
 
 // Whole-wavefront copy of n bytes (all arguments wave-uniform).  Every store
@@ -269,23 +293,25 @@ __device__ __forceinline__ void store16(uint8_t *p, u32x4 v, bool nt) {
 // 16-byte destination blocks and issues all of its loads -- the unaligned
 // head bytes, the body blocks and the tail bytes -- before any store, so a
 // segment of up to 4 KiB costs one memory round trip.
-__device__ void copy_wave(uint8_t *__restrict__ dst, const uint8_t *__restrict__ src, uint32_t n, bool nt) {
+__device__ void copy_wave(uint8_t *dst_, const uint8_t *src_, uint32_t n, bool nt) {
+    g_u8 *__restrict__ dst = gp<g_u8>(dst_);
+    const g_u8 *__restrict__ src = gp<const g_u8>(src_);
     const int lane = lane_id();
-    uint32_t h = (16u - (uint32_t)((uintptr_t)dst & 15u)) & 15u;
+    uint32_t h = (16u - (uint32_t)((uintptr_t)dst_ & 15u)) & 15u;
     if (h > n) h = n;
     const int32_t m = (int32_t)((n - h) >> 4);  // whole 16-byte destination blocks
     const uint32_t t = (n - h) & 15u;
-    const uint32_t o = (uint32_t)((uintptr_t)(src + h) & 15u);
-    const uint8_t *__restrict__ sa = src + h - o;  // 16-byte aligned source of the body
-    uint8_t *__restrict__ db = dst + h;
+    const uint32_t o = (uint32_t)((uintptr_t)(src_ + h) & 15u);
+    const g_u8 *__restrict__ sa = src + h - o;  // 16-byte aligned source of the body
+    g_u8 *__restrict__ db = dst + h;
     const uint32_t tail_off = h + 16u * (uint32_t)m;
     int32_t b0 = 0;
     do {
         const bool first = b0 == 0;
         const bool last = b0 + 256 >= m;
         const int32_t rem = m - b0 - lane;  // this lane's block u exists when 64*u < rem
-        const u32x4 *ps = (const u32x4 *)(sa + 16 * (int64_t)(b0 + lane));
-        u32x4 *pd = (u32x4 *)(db + 16 * (int64_t)(b0 + lane));
+        const g_u32x4 *ps = (const g_u32x4 *)(sa + 16 * (int64_t)(b0 + lane));
+        g_u32x4 *pd = (g_u32x4 *)(db + 16 * (int64_t)(b0 + lane));
         uint8_t hb = 0, tb = 0;
         if (first && (uint32_t)lane < h) hb = src[lane];
         if (last && (uint32_t)lane < t) tb = src[tail_off + lane];
@@ -297,7 +323,7 @@ __device__ void copy_wave(uint8_t *__restrict__ dst, const uint8_t *__restrict__
             if (first && (uint32_t)lane < h) dst[lane] = hb;
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (64 * u < rem) store16((uint8_t *)(pd + 64 * u), v[u], nt);
+                if (64 * u < rem) store16(pd + 64 * u, v[u], nt);
         } else {
             // source blocks 0..m are needed (m+1 blocks, each holds a source byte)
             u32x4 cur[4];
@@ -314,7 +340,7 @@ __device__ void copy_wave(uint8_t *__restrict__ dst, const uint8_t *__restrict__
                 const u32x4 down = shfl_down1(cur[u]);
                 const u32x4 wrap = (u < 3) ? readlane0(cur[u + 1 < 4 ? u + 1 : 3]) : extra;
                 const u32x4 nxt = (lane == 63) ? wrap : down;
-                if (64 * u < rem) store16((uint8_t *)(pd + 64 * u), funnel16(cur[u], nxt, o), nt);
+                if (64 * u < rem) store16(pd + 64 * u, funnel16(cur[u], nxt, o), nt);
             }
         }
         if (last && (uint32_t)lane < t) dst[tail_off + lane] = tb;
@@ -323,7 +349,9 @@ __device__ void copy_wave(uint8_t *__restrict__ dst, const uint8_t *__restrict__
 }
 
 // Copy by one lane (short segments).
-__device__ __forceinline__ void copy_lane(uint8_t *dst, const uint8_t *src, uint32_t n) {
+__device__ __forceinline__ void copy_lane(uint8_t *dst_, const uint8_t *src_, uint32_t n) {
+    g_u8 *dst = gp<g_u8>(dst_);
+    const g_u8 *src = gp<const g_u8>(src_);
     for (uint32_t i = 0; i < n; ++i) dst[i] = src[i];
 }
 
@@ -347,7 +375,7 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         if (kPlain) {
             rq = preq;
         } else {
-            const u32x4 *p = (const u32x4 *)(B.reqs + r0 + lane);
+            const g_u32x4 *p = gp<const g_u32x4>(B.reqs + r0 + lane);
             u32x4 a = p[0], b = p[1];
             rq.gva = ((uint64_t)a.y << 32) | a.x;
             rq.host = ((uint64_t)a.w << 32) | a.z;
@@ -363,7 +391,7 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         if (asid >= V.nproc) {
             code0 = DEVIRT_INVALID;
         } else {
-            DProc p = V.procs[asid];
+            DProc p = gp<const DV_GLOBAL DProc>(V.procs)[asid];
             vm = p.vm;
             levels = p.levels;
             cr3 = p.cr3;
@@ -428,7 +456,7 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         const uint64_t head_mask = __ballot(head);
 
         DVm vmv;
-        if (work) vmv = V.vms[j_vm];
+        if (work) vmv = gp<const DV_GLOBAL DVm>(V.vms)[j_vm];
         // upper levels through the cache (heads only)
         CEnt ce;
         ce.info = 0;
@@ -671,7 +699,7 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                     sg.len = run;
                     sg.req = (uint32_t)(r0 + (uint64_t)j);
                     sg.pad = 0;
-                    B.segs[pos] = sg;
+                    gp<DV_GLOBAL DSeg>(B.segs)[pos] = sg;
                     q_ok = 1;
                 } else {
                     coop = true;  // queue full: the wavefront copies it below
@@ -720,7 +748,7 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
             r.code = fcode;
             r.level = (uint16_t)flevel;
         }
-        B.res[kPlain ? 0 : r0 + lane] = r;
+        gp<DV_GLOBAL devirt_result>(B.res)[kPlain ? 0 : r0 + lane] = r;
         if (!kPlain && B.t_done) {
             B.pending[r0 + lane] = queued;
             if (queued == 0) B.t_done[r0 + lane] = now_ns(B);
@@ -793,10 +821,11 @@ __global__ void __launch_bounds__(1024) k_copy(DBatch b, uint32_t epoch) {
     const uint64_t w0 = uniform_u64((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const bool nt = b.nontemporal != 0;
     if (w0 >= nseg) return;
-    DSeg next = b.segs[w0];
+    const DV_GLOBAL DSeg *segs = gp<const DV_GLOBAL DSeg>(b.segs);
+    DSeg next = segs[w0];
     for (uint64_t s = w0; s < nseg; s += waves) {
         const DSeg sg = next;
-        if (s + waves < nseg) next = b.segs[s + waves];  // prefetch the next record
+        if (s + waves < nseg) next = segs[s + waves];  // prefetch the next record
         copy_wave((uint8_t *)uniform_u64(sg.dst), (const uint8_t *)uniform_u64(sg.src), uniform_u32(sg.len), nt);
         if (b.t_done && lane_id() == 0) {
             uint32_t old = atomicSub(&b.pending[sg.req], 1u);
@@ -835,8 +864,8 @@ __global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint
     DProc p = {0, 0, 4};
     DVm vmv = {};
     if (valid_asid) {
-        p = v.procs[asid];
-        vmv = v.vms[p.vm];
+        p = gp<const DV_GLOBAL DProc>(v.procs)[asid];
+        vmv = gp<const DV_GLOBAL DVm>(v.vms)[p.vm];
     }
     const uint64_t lim = p.levels == 5 ? (1ull << 56) : (1ull << 47);
     const bool write = (flags & DEVIRT_XLAT_WRITE) != 0;
@@ -846,7 +875,7 @@ __global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint
     for (uint64_t b0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; b0 < n; b0 += waves * 64) {
         const uint64_t i = b0 + lane;
         const bool in = i < n;
-        const uint64_t gva = in ? gvas[i] : 0;
+        const uint64_t gva = in ? gp<const g_u64>(gvas)[i] : 0;
         devirt_xlat x;
         x.gpa = 0;
         x.hpa = 0;
@@ -981,7 +1010,7 @@ __global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint
                 }
             }
         }
-        if (in) out[i] = x;
+        if (in) gp<DV_GLOBAL devirt_xlat>(out)[i] = x;
     }
     if (counters) {
         GroupOut st = {0, hits, misses, 0, 0, atom};

@@ -9,8 +9,9 @@
 //   - each guest thread (asid, tag) has a FIFO; a thread with nothing in
 //     flight and a non-empty FIFO is "ready";
 //   - whenever a launch slot (stream) is free, ready operations are admitted
-//     while descriptor slots and the byte budget allow, copied to the device
-//     and launched as one batch on that slot's stream, while earlier batches
+//     while descriptor slots and the byte budget allow, written to the slot's
+//     pinned buffer and launched as one batch on that slot's stream (the
+//     kernels read the descriptors and write results in place), while earlier batches
 //     are still running on the other streams (their work overlaps on the
 //     GPU);
 //   - finished batches are found by polling their events; their results
@@ -43,13 +44,14 @@ struct Op {
     uint64_t t_submit;
 };
 
+// A launch slot: its own stream and workspace, and pinned host buffers that
+// the kernels read descriptors from and write results to directly (no
+// staging copies on the way in or out).
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    devirt_request *d_reqs = nullptr;
-    devirt_result *d_res = nullptr;
-    devirt_request *h_reqs = nullptr;  // pinned
-    devirt_result *h_res = nullptr;    // pinned
+    devirt_request *h_reqs = nullptr;  // pinned, device-visible
+    devirt_result *h_res = nullptr;    // pinned, device-visible
     std::vector<Op> ops;
     std::vector<uint64_t> t_admit;
     bool busy = false;
@@ -88,14 +90,8 @@ static uint64_t thread_key(const devirt_request &r) { return ((uint64_t)r.asid <
 static int launch_slot(devirt_server *s, Slot &sl) {
     const uint32_t n = (uint32_t)sl.ops.size();
     for (uint32_t i = 0; i < n; ++i) sl.h_reqs[i] = sl.ops[i].r;
-    if (hipMemcpyAsync(sl.d_reqs, sl.h_reqs, (size_t)n * sizeof(devirt_request), hipMemcpyHostToDevice, sl.stream) !=
-        hipSuccess)
-        return dv_fail(-EIO, "server: request upload failed");
-    int rc = dv_submit(s->ctx, sl.d_reqs, n, nullptr, 0, sl.d_res, nullptr, nullptr, nullptr, sl.stream, false);
+    int rc = dv_submit(s->ctx, sl.h_reqs, n, nullptr, 0, sl.h_res, nullptr, nullptr, nullptr, sl.stream, false);
     if (rc) return rc;
-    if (hipMemcpyAsync(sl.h_res, sl.d_res, (size_t)n * sizeof(devirt_result), hipMemcpyDeviceToHost, sl.stream) !=
-        hipSuccess)
-        return dv_fail(-EIO, "server: result download failed");
     if (hipEventRecord(sl.ev, sl.stream) != hipSuccess) return dv_fail(-EIO, "server: event record failed");
     sl.busy = true;
     s->launches++;
@@ -195,8 +191,6 @@ static void server_loop(devirt_server *s) {
 static void free_server(devirt_server *s) {
     for (auto &sl : s->slots) {
         if (sl.stream) hipStreamSynchronize(sl.stream);
-        hipFree(sl.d_reqs);
-        hipFree(sl.d_res);
         hipHostFree(sl.h_reqs);
         hipHostFree(sl.h_res);
         if (sl.ev) hipEventDestroy(sl.ev);
@@ -230,10 +224,10 @@ extern "C" int devirt_server_start(devirt_ctx *c, const devirt_server_cfg *cfg, 
     for (auto &sl : s->slots) {
         bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess &&
-                  hipMalloc(&sl.d_reqs, (size_t)max_batch * sizeof(devirt_request)) == hipSuccess &&
-                  hipMalloc(&sl.d_res, (size_t)max_batch * sizeof(devirt_result)) == hipSuccess &&
-                  hipHostMalloc(&sl.h_reqs, (size_t)max_batch * sizeof(devirt_request), 0) == hipSuccess &&
-                  hipHostMalloc(&sl.h_res, (size_t)max_batch * sizeof(devirt_result), 0) == hipSuccess;
+                  hipHostMalloc(&sl.h_reqs, (size_t)max_batch * sizeof(devirt_request),
+                                hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+                  hipHostMalloc(&sl.h_res, (size_t)max_batch * sizeof(devirt_result),
+                                hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
         if (!ok) {
             free_server(s);
             return dv_fail(-ENOMEM, "server: cannot allocate launch slots");

@@ -298,11 +298,13 @@ class Server:
         _check("devirt_server_submit", lib().devirt_server_submit(self._h, r.ctypes.data, len(r), ctypes.byref(n)))
         return n.value
 
-    def poll(self, max_n: int = 4096) -> np.ndarray:
-        out = np.zeros(max_n, COMPLETION_DTYPE)
+    def poll(self, max_n: int = 4096, out: np.ndarray | None = None) -> np.ndarray:
+        """Take up to max_n completions (into `out` when given, which is reused)."""
+        if out is None or len(out) < max_n:
+            out = np.empty(max_n, COMPLETION_DTYPE)
         n = u32()
         _check("devirt_server_poll", lib().devirt_server_poll(self._h, out.ctypes.data, max_n, ctypes.byref(n)))
-        return out[:n.value]
+        return out[:n.value].copy()
 
     def drain(self):
         _check("devirt_server_drain", lib().devirt_server_drain(self._h))

@@ -12,7 +12,8 @@ Workload recipe (each VM, each process):
   virtual address space, split by mapped bytes into 4 KiB, 2 MiB and 1 GiB
   leaves.  The space is built from 1 GiB blocks (one 1 GiB leaf), 2 MiB
   blocks (one 2 MiB leaf) and page-table blocks (up to 512 4 KiB leaves),
-  grouped into ``vmas_per_proc`` VMAs at random 1 GiB-aligned user addresses.
+  shuffled and grouped into ``vmas_per_proc`` VMAs of near-equal size at
+  random 1 GiB-aligned user addresses.
 * Data frames are a random permutation of free GPA frames of the right
   alignment (1 GiB first, then 2 MiB, then 4 KiB); page-table frames are
   random free 4 KiB frames.  Leaves are not-present with probability
@@ -332,10 +333,12 @@ def _layout_process(rng, sp: Spec, n1: int, n2: int, n4: int):
         blk_ptes[-1] = n4 - 512 * (nblk4 - 1)
     nb = len(kinds)
     k = max(1, min(sp.vmas_per_proc, nb + n1))
-    # split the 2 MiB-block sequence into k contiguous groups
-    if nb and k > 1:
-        cuts = np.sort(rng.choice(np.arange(1, max(nb, 2)), min(k - 1, max(nb - 1, 0)), replace=False)) \
-            if nb > 1 else np.zeros(0, np.int64)
+    # split the 2 MiB-block sequence into k contiguous groups of near-equal size
+    # (each cut jittered by up to 20% of a group), so no VMA starves an epoch
+    if nb > 1 and k > 1:
+        even = np.arange(1, k) * nb / k
+        jitter = (rng.random(k - 1) - 0.5) * 0.4 * nb / k
+        cuts = np.unique(np.clip(np.round(even + jitter), 1, nb - 1).astype(np.int64))
     else:
         cuts = np.zeros(0, np.int64)
     groups = np.split(np.arange(nb), cuts) if nb else [np.zeros(0, np.int64)]
