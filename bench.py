@@ -223,7 +223,7 @@ def main():
     ap.add_argument("--xlat-n", type=int, default=16_000_000, help="addresses for the translate-only rate")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="autotune the batch launch first")
+    ap.add_argument("--no-autotune", action="store_true", help="skip autotuning the batch launch")
     ap.add_argument("--profile-only", action="store_true", help="only run K timed steps (for rocprofv3)")
     ap.add_argument("--set", default="", help="launch config overrides, e.g. seg_chunks=64,nontemporal=1")
     ap.add_argument("--serving", action="store_true", help="run the C4 serving sweep instead")
@@ -269,10 +269,10 @@ def main():
     nf = torch.zeros(1, dtype=torch.int64, device="cuda")
     flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
 
-    if args.autotune:
-        log("autotuning")
-        best, ms = ctx.autotune(dw.reqs, n, res, wl.epoch_end, faults, nf, reps=3)
-        log(f"autotuned: {best} {ms:.3f} ms")
+    if not args.no_autotune and not args.set:
+        t_at = time.time()
+        best, ms = ctx.autotune(dw.reqs, n, res, wl.epoch_end, faults, nf, reps=3 if n <= 2_000_000 else 1)
+        log(f"autotuned in {time.time() - t_at:.1f}s: {best} ({ms:.3f} ms)")
 
     def reset():
         restore_tables(ctx, wl)

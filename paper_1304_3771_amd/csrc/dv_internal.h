@@ -59,11 +59,18 @@ struct DSeg {
     uint64_t pad;
 };
 
-// Per-epoch device counters (16 B each).
+// Runs of at most this many bytes go to the short-segment queue, whose
+// segments are copied four to a wavefront (one per 16 lanes): one pass of a
+// 16-lane group moves 4 x 16 x 16 B = 1 KiB.
+constexpr uint32_t kShortRun = 1024;
+
+// Per-epoch device counters (16 B each).  A count may exceed the queue's
+// capacity; segments past it were copied by the translating wavefront.
 struct DEpochCtr {
     uint32_t group_cursor;  // next request group to translate
-    uint32_t nseg;          // segments queued (may exceed capacity: overflow copied inline)
-    uint32_t pad0, pad1;
+    uint32_t nseg;          // long segments queued
+    uint32_t nshort;        // short segments queued
+    uint32_t pad;
 };
 
 // Device counters gathered while profiling.
@@ -82,8 +89,9 @@ struct DBatch {
     devirt_result *res;
     uint64_t *t_done;         // may be null
     uint32_t *pending;        // per request, queued segments not yet copied (t_done only)
-    DSeg *segs;
-    uint64_t seg_cap;
+    DSeg *segs;               // long segments
+    DSeg *shorts;             // short segments (len <= kShortRun)
+    uint64_t seg_cap;         // capacity of each of the two queues
     DEpochCtr *ctr;           // per epoch
     DCounters *counters;      // null unless profiling
     uint64_t *t0;             // device wall clock at batch start

@@ -230,53 +230,14 @@ __device__ __forceinline__ void cache_resolve(CEnt *cache, uint32_t *owner, bool
 }
 
 // ---------------------------------------------------------------- copying
-__device__ __forceinline__ u32x4 funnel16(u32x4 a, u32x4 b, uint32_t o) {
-    // bytes [o, o+16) of the 32-byte window a:b (a low); o in 1..15
-    const uint32_t r = o & 3u;
-    u32x4 out;
-    switch (o >> 2) {
-        case 0:
-            out.x = __builtin_amdgcn_alignbyte(a.y, a.x, r);
-            out.y = __builtin_amdgcn_alignbyte(a.z, a.y, r);
-            out.z = __builtin_amdgcn_alignbyte(a.w, a.z, r);
-            out.w = __builtin_amdgcn_alignbyte(b.x, a.w, r);
-            break;
-        case 1:
-            out.x = __builtin_amdgcn_alignbyte(a.z, a.y, r);
-            out.y = __builtin_amdgcn_alignbyte(a.w, a.z, r);
-            out.z = __builtin_amdgcn_alignbyte(b.x, a.w, r);
-            out.w = __builtin_amdgcn_alignbyte(b.y, b.x, r);
-            break;
-        case 2:
-            out.x = __builtin_amdgcn_alignbyte(a.w, a.z, r);
-            out.y = __builtin_amdgcn_alignbyte(b.x, a.w, r);
-            out.z = __builtin_amdgcn_alignbyte(b.y, b.x, r);
-            out.w = __builtin_amdgcn_alignbyte(b.z, b.y, r);
-            break;
-        default:
-            out.x = __builtin_amdgcn_alignbyte(b.x, a.w, r);
-            out.y = __builtin_amdgcn_alignbyte(b.y, b.x, r);
-            out.z = __builtin_amdgcn_alignbyte(b.z, b.y, r);
-            out.w = __builtin_amdgcn_alignbyte(b.w, b.z, r);
-            break;
-    }
-    return out;
-}
-
-__device__ __forceinline__ u32x4 shfl_down1(u32x4 v) {
+// 16 output bytes from the 20-byte window (c.x c.y c.z c.w nx), starting at
+// byte a (0..3); v_alignbyte takes the shift per lane.
+__device__ __forceinline__ u32x4 funnel4(u32x4 c, uint32_t nx, uint32_t a) {
     u32x4 r;
-    r.x = (uint32_t)__shfl_down((int)v.x, 1);
-    r.y = (uint32_t)__shfl_down((int)v.y, 1);
-    r.z = (uint32_t)__shfl_down((int)v.z, 1);
-    r.w = (uint32_t)__shfl_down((int)v.w, 1);
-    return r;
-}
-__device__ __forceinline__ u32x4 readlane0(u32x4 v) {
-    u32x4 r;
-    r.x = (uint32_t)__builtin_amdgcn_readlane((int)v.x, 0);
-    r.y = (uint32_t)__builtin_amdgcn_readlane((int)v.y, 0);
-    r.z = (uint32_t)__builtin_amdgcn_readlane((int)v.z, 0);
-    r.w = (uint32_t)__builtin_amdgcn_readlane((int)v.w, 0);
+    r.x = __builtin_amdgcn_alignbyte(c.y, c.x, a);
+    r.y = __builtin_amdgcn_alignbyte(c.z, c.y, a);
+    r.z = __builtin_amdgcn_alignbyte(c.w, c.z, a);
+    r.w = __builtin_amdgcn_alignbyte(nx, c.w, a);
     return r;
 }
 
@@ -287,65 +248,78 @@ __device__ __forceinline__ void store16(g_u32x4 *p, u32x4 v, bool nt) {
         *p = v;
 }
 
-// Whole-wavefront copy of n bytes (all arguments wave-uniform).  Every store
-// writes only bytes of [dst, dst+n); loads stay inside 16-byte blocks that
-// contain at least one source byte.  Each iteration moves up to 4 KiB of
-// 16-byte destination blocks and issues all of its loads -- the unaligned
-// head bytes, the body blocks and the tail bytes -- before any store, so a
-// segment of up to 4 KiB costs one memory round trip.
-__device__ void copy_wave(uint8_t *dst_, const uint8_t *src_, uint32_t n, bool nt) {
+// 16 bytes read at a 4-byte aligned address (one global_load_dwordx4).
+typedef u32x4 u32x4_w4 __attribute__((aligned(4)));
+typedef DV_GLOBAL u32x4_w4 g_u32x4_w4;
+
+// Copy of n bytes by a group of G consecutive lanes of one wavefront; l is
+// the lane's index in its group.  G = 64: the whole wavefront, arguments
+// wave-uniform.  G = 16: each quarter of the wavefront copies its own
+// segment, so a wavefront keeps four short segments in flight.
+//
+// The destination is written as aligned 16-byte blocks, with byte stores for
+// the unaligned head and the tail (< 16 bytes each): no store touches a byte
+// outside [dst, dst+n).  Block i takes its bytes from the 20-byte window at
+// sa + 16 i, where sa is the 4-byte aligned address a bytes below the first
+// body byte: the lane loads 16 bytes and takes the next dword from the next
+// lane of its group (or, for the group's last lane, from the first lane of
+// the next row).  Every load lies in an aligned dword that holds at least one
+// source byte.  A pass moves 4 rows of G blocks and issues all of its loads
+// before any store.
+template <int G>
+__device__ __forceinline__ void copy_span(uint8_t *dst_, const uint8_t *src_, uint32_t n, bool nt, int l) {
+    constexpr int R = 4;
+    if (n == 0) return;
     g_u8 *__restrict__ dst = gp<g_u8>(dst_);
     const g_u8 *__restrict__ src = gp<const g_u8>(src_);
-    const int lane = lane_id();
     uint32_t h = (16u - (uint32_t)((uintptr_t)dst_ & 15u)) & 15u;
     if (h > n) h = n;
     const int32_t m = (int32_t)((n - h) >> 4);  // whole 16-byte destination blocks
     const uint32_t t = (n - h) & 15u;
-    const uint32_t o = (uint32_t)((uintptr_t)(src_ + h) & 15u);
-    const g_u8 *__restrict__ sa = src + h - o;  // 16-byte aligned source of the body
+    const uint32_t a = (uint32_t)((uintptr_t)(src_ + h) & 3u);
+    const g_u8 *__restrict__ sa = src + h - a;
     g_u8 *__restrict__ db = dst + h;
     const uint32_t tail_off = h + 16u * (uint32_t)m;
+    const int lane = lane_id();
+    const int nb = (lane & ~(G - 1)) | ((lane + 1) & (G - 1));  // next lane of the group, cyclically
     int32_t b0 = 0;
     do {
         const bool first = b0 == 0;
-        const bool last = b0 + 256 >= m;
-        const int32_t rem = m - b0 - lane;  // this lane's block u exists when 64*u < rem
-        const g_u32x4 *ps = (const g_u32x4 *)(sa + 16 * (int64_t)(b0 + lane));
-        g_u32x4 *pd = (g_u32x4 *)(db + 16 * (int64_t)(b0 + lane));
+        const bool last = b0 + R * G >= m;
+        const int32_t rem = m - b0 - l;  // block b0 + l + G*u exists when G*u < rem
+        const g_u8 *__restrict__ ps = sa + 16 * (int64_t)(b0 + l);
+        g_u32x4 *pd = (g_u32x4 *)(db + 16 * (int64_t)(b0 + l));
         uint8_t hb = 0, tb = 0;
-        if (first && (uint32_t)lane < h) hb = src[lane];
-        if (last && (uint32_t)lane < t) tb = src[tail_off + lane];
-        if (o == 0) {
-            u32x4 v[4];
+        if (first && (uint32_t)l < h) hb = src[l];
+        if (last && (uint32_t)l < t) tb = src[tail_off + l];
+        u32x4 cur[R];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (64 * u < rem) v[u] = ps[64 * u];
-            if (first && (uint32_t)lane < h) dst[lane] = hb;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (64 * u < rem) store16(pd + 64 * u, v[u], nt);
-        } else {
-            // source blocks 0..m are needed (m+1 blocks, each holds a source byte)
-            u32x4 cur[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                cur[u] = (u32x4){0u, 0u, 0u, 0u};
-                if (64 * u <= rem) cur[u] = ps[64 * u];
-            }
-            u32x4 extra = (u32x4){0u, 0u, 0u, 0u};
-            if (lane == 63 && 256 <= rem + 63) extra = ps[193];  // block b0 + 256
-            if (first && (uint32_t)lane < h) dst[lane] = hb;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const u32x4 down = shfl_down1(cur[u]);
-                const u32x4 wrap = (u < 3) ? readlane0(cur[u + 1 < 4 ? u + 1 : 3]) : extra;
-                const u32x4 nxt = (lane == 63) ? wrap : down;
-                if (64 * u < rem) store16(pd + 64 * u, funnel16(cur[u], nxt, o), nt);
-            }
+        for (int u = 0; u < R; ++u) {
+            cur[u] = (u32x4){0u, 0u, 0u, 0u};
+            if (G * u < rem)
+                cur[u] = *(const g_u32x4_w4 *)(ps + 16 * G * u);
+            else if (a != 0 && G * u == rem)  // block m: only its first dword is needed
+                cur[u].x = *(const g_u32 *)(ps + 16 * G * u);
         }
-        if (last && (uint32_t)lane < t) dst[tail_off + lane] = tb;
-        b0 += 256;
+        uint32_t ex = 0;  // first dword of block b0 + R*G, for the group's last lane
+        if (a != 0 && l == G - 1 && R * G <= rem + G - 1) ex = *(const g_u32 *)(ps + 16 * (G * (R - 1) + 1));
+        if (first && (uint32_t)l < h) dst[l] = hb;
+        uint32_t rot[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) rot[u] = (uint32_t)__shfl((int)cur[u].x, nb);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const uint32_t nx = (l == G - 1) ? (u + 1 < R ? rot[u + 1 < R ? u + 1 : 0] : ex) : rot[u];
+            if (G * u < rem) store16(pd + G * u, funnel4(cur[u], nx, a), nt);
+        }
+        if (last && (uint32_t)l < t) dst[tail_off + l] = tb;
+        b0 += R * G;
     } while (b0 < m);
+}
+
+// Whole-wavefront copy (all arguments wave-uniform).
+__device__ __forceinline__ void copy_wave(uint8_t *dst, const uint8_t *src, uint32_t n, bool nt) {
+    copy_span<64>(dst, src, n, nt, lane_id());
 }
 
 // Copy by one lane (short segments).
@@ -683,15 +657,22 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         const bool small = rhead && !coop_all && run <= B.inline_bytes;
         if (small) copy_lane((uint8_t *)dst, (const uint8_t *)src, run);
         const bool want_q = rhead && !small && !coop_all;
-        const uint64_t qmask = __ballot(want_q);
+        const bool is_short = run <= kShortRun;
+        const uint64_t lmask = __ballot(want_q && !is_short);
+        const uint64_t smask = __ballot(want_q && is_short);
         bool coop = rhead && coop_all;
         uint32_t q_ok = 0;
-        if (qmask) {
-            uint32_t qbase = 0;
-            if (lane == 0) qbase = atomicAdd(&ctr[epoch].nseg, (uint32_t)__popcll(qmask));
-            qbase = shfl32(qbase, 0);
+        if (lmask | smask) {
+            uint32_t lbase = 0, sbase = 0;
+            if (lane == 0) {
+                if (lmask) lbase = atomicAdd(&ctr[epoch].nseg, (uint32_t)__popcll(lmask));
+                if (smask) sbase = atomicAdd(&ctr[epoch].nshort, (uint32_t)__popcll(smask));
+            }
+            lbase = shfl32(lbase, 0);
+            sbase = shfl32(sbase, 0);
             if (want_q) {
-                const uint64_t pos = (uint64_t)qbase + (uint64_t)__popcll(qmask & mask_lt(lane));
+                const uint64_t qm = is_short ? smask : lmask;
+                const uint64_t pos = (uint64_t)(is_short ? sbase : lbase) + (uint64_t)__popcll(qm & mask_lt(lane));
                 if (pos < B.seg_cap) {
                     DSeg sg;
                     sg.src = src;
@@ -699,7 +680,7 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                     sg.len = run;
                     sg.req = (uint32_t)(r0 + (uint64_t)j);
                     sg.pad = 0;
-                    gp<DV_GLOBAL DSeg>(B.segs)[pos] = sg;
+                    gp<DV_GLOBAL DSeg>(is_short ? B.shorts : B.segs)[pos] = sg;
                     q_ok = 1;
                 } else {
                     coop = true;  // queue full: the wavefront copies it below
@@ -763,8 +744,8 @@ __global__ void k_reset(DBatch b, uint32_t n_epochs) {
     for (; i < n_epochs; i += gridDim.x * blockDim.x) {
         b.ctr[i].group_cursor = 0;
         b.ctr[i].nseg = 0;
-        b.ctr[i].pad0 = 0;
-        b.ctr[i].pad1 = 0;
+        b.ctr[i].nshort = 0;
+        b.ctr[i].pad = 0;
     }
 }
 
@@ -814,22 +795,39 @@ __global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uin
     flush_counters(b.counters, st);
 }
 
-__global__ void __launch_bounds__(1024) k_copy(DBatch b, uint32_t epoch) {
-    const uint32_t nq = b.ctr[epoch].nseg;
-    const uint64_t nseg = nq < b.seg_cap ? nq : b.seg_cap;
+// Copy of one epoch's queued segments.  The copy is bound by the bytes it
+// keeps in flight: hence at most 64 VGPRs, so that 8 wavefronts (the most a
+// SIMD holds) stay resident, and short segments a 16-lane quarter each, so
+// that a wavefront keeps up to four of them in flight.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_copy(DBatch b, uint32_t epoch) {
+    const uint32_t nl = b.ctr[epoch].nseg, ns = b.ctr[epoch].nshort;
+    const uint64_t nlong = nl < b.seg_cap ? nl : b.seg_cap;
+    const uint64_t nshort = ns < b.seg_cap ? ns : b.seg_cap;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t w0 = uniform_u64((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const bool nt = b.nontemporal != 0;
-    if (w0 >= nseg) return;
+    const int lane = lane_id();
+    // long segments: one per wavefront
     const DV_GLOBAL DSeg *segs = gp<const DV_GLOBAL DSeg>(b.segs);
-    DSeg next = segs[w0];
-    for (uint64_t s = w0; s < nseg; s += waves) {
-        const DSeg sg = next;
-        if (s + waves < nseg) next = segs[s + waves];  // prefetch the next record
+    for (uint64_t s = w0; s < nlong; s += waves) {
+        const DSeg sg = segs[s];
         copy_wave((uint8_t *)uniform_u64(sg.dst), (const uint8_t *)uniform_u64(sg.src), uniform_u32(sg.len), nt);
-        if (b.t_done && lane_id() == 0) {
+        if (b.t_done && lane == 0) {
             uint32_t old = atomicSub(&b.pending[sg.req], 1u);
             if (old == 1) b.t_done[sg.req] = now_ns(b);
+        }
+    }
+    // short segments: one per 16-lane quarter
+    const DV_GLOBAL DSeg *sh = gp<const DV_GLOBAL DSeg>(b.shorts);
+    const int l = lane & 15;
+    for (uint64_t s = 4 * w0 + (uint64_t)(lane >> 4); s < nshort; s += 4 * waves) {
+        const uint64_t src = sh[s].src, dst = sh[s].dst;
+        const uint32_t len = sh[s].len;
+        copy_span<16>((uint8_t *)dst, (const uint8_t *)src, len, nt, l);
+        if (b.t_done && l == 0) {
+            const uint32_t req = sh[s].req;
+            uint32_t old = atomicSub(&b.pending[req], 1u);
+            if (old == 1) b.t_done[req] = now_ns(b);
         }
     }
 }
@@ -840,6 +838,7 @@ __global__ void __launch_bounds__(64) k_plain(DView v, DBatch b, devirt_request 
     if (threadIdx.x < kCacheWays) cache[threadIdx.x].key = ~0ull;
     if (threadIdx.x == 0) {
         b.ctr[0].nseg = 0;
+        b.ctr[0].nshort = 0;
         *b.t0 = wall_clock64();
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

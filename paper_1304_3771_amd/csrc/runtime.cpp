@@ -77,6 +77,7 @@ Workspace::~Workspace() {
         hipStreamDestroy(side);
     }
     hipFree(segs);
+    hipFree(shorts);
     hipFree(ctr);
     hipFree(pending);
     hipFree(tiles);
@@ -396,6 +397,7 @@ int ensure_ws(devirt_ctx *c, Workspace *w, uint64_t n_req, uint64_t n_epochs, bo
     int rc;
     const uint64_t segs = w->segs ? std::max<uint64_t>(w->seg_cap, min_segs) : std::max(default_seg_cap(), min_segs);
     if ((rc = grow(c, w, w->segs, w->seg_cap, segs, "segments"))) return rc;
+    if ((rc = grow(c, w, w->shorts, w->short_cap, w->seg_cap, "short segments"))) return rc;
     if ((rc = grow(c, w, w->ctr, w->ctr_cap, std::max<uint64_t>(n_epochs, 1), "epoch counters"))) return rc;
     if ((rc = grow(c, w, w->t0, w->t0_cap, 1, "clock"))) return rc;
     uint64_t tiles = (n_req + kFaultTile - 1) / kFaultTile;
@@ -409,7 +411,8 @@ DBatch make_batch(devirt_ctx *c, Workspace *w) {
     DBatch b;
     memset(&b, 0, sizeof b);
     b.segs = w->segs;
-    b.seg_cap = w->seg_cap;
+    b.shorts = w->shorts;
+    b.seg_cap = std::min(w->seg_cap, w->short_cap);
     b.ctr = w->ctr;
     b.pending = w->pending;
     b.t0 = w->t0;
@@ -607,13 +610,15 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
         HIPCHK(hipEventRecord(w->events[2 * ne], s));  // fork: the side stream starts after the reset
         HIPCHK(hipStreamWaitEvent(side, w->events[2 * ne], 0));
     }
-    const uint64_t half = overlap ? w->seg_cap / 2 : w->seg_cap;
+    const uint64_t cap = std::min(w->seg_cap, w->short_cap);
+    const uint64_t half = overlap ? cap / 2 : cap;
     uint64_t r0 = 0;
     int rc;
     for (size_t e = 0; e < ne; ++e) {
         const uint64_t r1 = a.epochs[e];
         DBatch be = b;
         be.segs = w->segs + (overlap ? (e & 1) * half : 0);
+        be.shorts = w->shorts + (overlap ? (e & 1) * half : 0);
         be.seg_cap = half;
         hipEvent_t t_done = overlap ? w->events[2 * e] : nullptr;
         hipEvent_t c_done = overlap ? w->events[2 * e + 1] : nullptr;
@@ -700,7 +705,8 @@ int dv_submit(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint6
     // graph cache: key = every argument that ends up in a kernel parameter
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)reqs, n, (uint64_t)(uintptr_t)res, (uint64_t)(uintptr_t)faults,
                                  (uint64_t)(uintptr_t)n_faults, (uint64_t)(uintptr_t)t_done, c->tables_version,
-                                 c->cfg_version, (uint64_t)(uintptr_t)w->segs, w->seg_cap};
+                                 c->cfg_version, (uint64_t)(uintptr_t)w->segs, w->seg_cap,
+                                 (uint64_t)(uintptr_t)w->shorts, w->short_cap};
     key.insert(key.end(), a.epochs.begin(), a.epochs.end());
     const uint64_t h = hash_key(key);
     for (auto &g : w->graphs) {
@@ -760,70 +766,89 @@ extern "C" int devirt_set_config(devirt_ctx *c, const devirt_config *cfg) {
     return 0;
 }
 
+// Median time of `reps` executions of the batch under the current config.
+static int time_batch(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint64_t *epoch_end,
+                      uint32_t n_epochs, devirt_result *res, devirt_fault *faults, uint64_t *n_faults, void *stream,
+                      uint32_t reps, hipEvent_t e0, hipEvent_t e1, double *ms_out) {
+    hipStream_t s = (hipStream_t)stream;
+    int rc = devirt_submit_batch(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, nullptr, stream);  // warm-up
+    if (rc) return rc;
+    std::vector<double> ts;
+    for (uint32_t r = 0; r < reps; ++r) {
+        HIPCHK(hipEventRecord(e0, s));
+        if ((rc = devirt_submit_batch(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, nullptr, stream)))
+            return rc;
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        ts.push_back(ms);
+    }
+    std::sort(ts.begin(), ts.end());
+    *ms_out = ts[ts.size() / 2];
+    return 0;
+}
+
+// Coordinate descent over the launch knobs: each knob in turn is set to each
+// of its candidate values, with the others at the best found so far.
 extern "C" int devirt_autotune(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint64_t *epoch_end,
                                uint32_t n_epochs, devirt_result *res, devirt_fault *faults, uint64_t *n_faults,
                                void *stream, uint32_t reps, devirt_config *best, double *best_ms) {
     if (!c) return dv_fail(-EINVAL, "ctx is NULL");
     if (reps == 0) reps = 3;
     if (set_dev(c)) return -EIO;
-    hipStream_t s = (hipStream_t)stream;
     const devirt_config base = c->cfg;
-    std::vector<devirt_config> cand;
-    for (uint32_t group : {32u, 64u})
-        for (uint32_t segc : {16u, 64u})
-            for (uint32_t cwg : {256u, 512u})
-                for (uint32_t cwpc : {4u, 8u, 16u})
-                    for (uint32_t ov : {0u, 1u})
-                        for (uint32_t xw : {1u, 2u}) {
-                            if (!ov && xw != 1) continue;
-                            devirt_config k = base;
-                            k.group = group;
-                            k.seg_chunks = segc;
-                            k.copy_wg = cwg;
-                            k.copy_wgs_per_cu = cwpc;
-                            k.overlap = ov;
-                            k.xlat_wgs_per_cu = ov ? xw : 8;
-                            cand.push_back(k);
-                        }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    double best_t = 1e300;
-    devirt_config best_c = base;
     const int prof = c->profiling;
     c->profiling = 0;
-    int rc = 0;
-    for (const auto &k : cand) {
-        c->cfg = k;
-        c->cfg_version++;
-        // warm-up (also captures the graph)
-        if ((rc = devirt_submit_batch(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, nullptr, stream))) break;
-        std::vector<double> ts;
-        for (uint32_t r = 0; r < reps; ++r) {
-            hipEventRecord(e0, s);
-            if ((rc = devirt_submit_batch(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, nullptr, stream)))
-                break;
-            hipEventRecord(e1, s);
-            hipEventSynchronize(e1);
-            float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
-            ts.push_back(ms);
-        }
+    devirt_config cur = base;
+    double cur_ms = 0;
+    c->cfg_version++;
+    int rc = time_batch(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, stream, reps, e0, e1, &cur_ms);
+    typedef void (*Setter)(devirt_config &, uint32_t);
+    struct Knob {
+        Setter set;
+        std::vector<uint32_t> values;
+    };
+    const std::vector<Knob> knobs = {
+        {[](devirt_config &k, uint32_t v) { k.group = v; }, {8, 16, 32, 64}},
+        {[](devirt_config &k, uint32_t v) {
+             k.overlap = v ? 1 : 0;
+             k.xlat_wgs_per_cu = v ? v : 8;
+         },
+         {0, 1, 2}},
+        {[](devirt_config &k, uint32_t v) { k.copy_wg = v; }, {256, 512, 1024}},
+        {[](devirt_config &k, uint32_t v) { k.copy_wgs_per_cu = v; }, {2, 4, 8, 16}},
+        {[](devirt_config &k, uint32_t v) { k.seg_chunks = v; }, {4, 16, 64}},
+    };
+    for (const auto &kn : knobs) {
         if (rc) break;
-        std::sort(ts.begin(), ts.end());
-        double med = ts[ts.size() / 2];
-        if (med < best_t) {
-            best_t = med;
-            best_c = k;
+        devirt_config keep = cur;
+        for (uint32_t v : kn.values) {
+            devirt_config k = keep;
+            kn.set(k, v);
+            if (memcmp(&k, &keep, sizeof k) == 0) continue;
+            if (check_config(k)) continue;
+            c->cfg = k;
+            c->cfg_version++;
+            double ms = 0;
+            if ((rc = time_batch(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, stream, reps, e0, e1, &ms)))
+                break;
+            if (ms < cur_ms) {
+                cur_ms = ms;
+                cur = k;
+            }
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     c->profiling = prof;
-    c->cfg = rc ? base : best_c;
+    c->cfg = rc ? base : cur;
     c->cfg_version++;
     if (rc) return rc;
-    if (best) *best = best_c;
-    if (best_ms) *best_ms = best_t;
+    if (best) *best = cur;
+    if (best_ms) *best_ms = cur_ms;
     return 0;
 }

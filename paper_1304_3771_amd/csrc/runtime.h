@@ -31,8 +31,10 @@ struct GraphEntry {
 // and the captured graphs that reference them.
 struct Workspace {
     hipStream_t stream = nullptr;
-    dv::DSeg *segs = nullptr;
+    dv::DSeg *segs = nullptr;    // long-segment queue
     uint64_t seg_cap = 0;
+    dv::DSeg *shorts = nullptr;  // short-segment queue, same capacity
+    uint64_t short_cap = 0;
     dv::DEpochCtr *ctr = nullptr;
     uint64_t ctr_cap = 0;
     uint32_t *pending = nullptr;
