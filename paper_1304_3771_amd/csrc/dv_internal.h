@@ -64,14 +64,25 @@ struct DSeg {
 // 16-lane group moves 4 x 16 x 16 B = 1 KiB.
 constexpr uint32_t kShortRun = 1024;
 
-// Per-epoch device counters (16 B each).  A count may exceed the queue's
-// capacity; segments past it were copied by the translating wavefront.
+// Same-address atomics serialise: with one shared counter of queued
+// segments the reservation atomics dominated the translate time.  So each
+// segment queue is split into kQParts equal parts with a counter each, every
+// counter on a 128-byte line of its own, and a translating wavefront appends
+// to part (its global index mod kQParts).
+constexpr uint32_t kQParts = 32;
+constexpr uint32_t kLineWords = 32;
+
+// Per-epoch device counters (word 0 of each line is used).  A segment count
+// may exceed its part's capacity; segments past it were copied by the
+// translating wavefront.
 struct DEpochCtr {
-    uint32_t group_cursor;  // next request group to translate
-    uint32_t nseg;          // long segments queued
-    uint32_t nshort;        // short segments queued
-    uint32_t pad;
+    uint32_t group_cursor;  // groups claimed beyond each wavefront's first
+    uint32_t pad[kLineWords - 1];
+    // segments in part p of the long queue (q[p]) and of the short queue
+    // (q[kQParts + p])
+    uint32_t q[2 * kQParts][kLineWords];
 };
+static_assert(2 * kQParts == 64, "one counter per lane of a wavefront");
 
 // Device counters gathered while profiling.
 struct DCounters {
@@ -91,7 +102,7 @@ struct DBatch {
     uint32_t *pending;        // per request, queued segments not yet copied (t_done only)
     DSeg *segs;               // long segments
     DSeg *shorts;             // short segments (len <= kShortRun)
-    uint64_t seg_cap;         // capacity of each of the two queues
+    uint64_t seg_cap;         // capacity of each of the two queues (kQParts parts each)
     DEpochCtr *ctr;           // per epoch
     DCounters *counters;      // null unless profiling
     uint64_t *t0;             // device wall clock at batch start

@@ -341,6 +341,9 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                               const devirt_request &preq, uint32_t epoch, CEnt *cache, uint32_t *owner,
                               bool coop_all, DEpochCtr *ctr, GroupOut &st) {
     const int lane = lane_id();
+    // this wavefront's part of the segment queues
+    const uint32_t qpart = kPlain ? 0u : (uint32_t)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kQParts);
+    const uint64_t pcap = B.seg_cap / kQParts;
     // ---- load and validate the group's requests (lane k owns request k)
     uint64_t gva = 0, host = 0, cr3 = 0;
     uint32_t len = 0, asid = 0, dir = 0, vm = 0, levels = 4, code0 = 0, nch = 0;
@@ -665,22 +668,22 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         if (lmask | smask) {
             uint32_t lbase = 0, sbase = 0;
             if (lane == 0) {
-                if (lmask) lbase = atomicAdd(&ctr[epoch].nseg, (uint32_t)__popcll(lmask));
-                if (smask) sbase = atomicAdd(&ctr[epoch].nshort, (uint32_t)__popcll(smask));
+                if (lmask) lbase = atomicAdd(&ctr[epoch].q[qpart][0], (uint32_t)__popcll(lmask));
+                if (smask) sbase = atomicAdd(&ctr[epoch].q[kQParts + qpart][0], (uint32_t)__popcll(smask));
             }
             lbase = shfl32(lbase, 0);
             sbase = shfl32(sbase, 0);
             if (want_q) {
                 const uint64_t qm = is_short ? smask : lmask;
                 const uint64_t pos = (uint64_t)(is_short ? sbase : lbase) + (uint64_t)__popcll(qm & mask_lt(lane));
-                if (pos < B.seg_cap) {
+                if (pos < pcap) {
                     DSeg sg;
                     sg.src = src;
                     sg.dst = dst;
                     sg.len = run;
                     sg.req = (uint32_t)(r0 + (uint64_t)j);
                     sg.pad = 0;
-                    gp<DV_GLOBAL DSeg>(is_short ? B.shorts : B.segs)[pos] = sg;
+                    gp<DV_GLOBAL DSeg>(is_short ? B.shorts : B.segs)[qpart * pcap + pos] = sg;
                     q_ok = 1;
                 } else {
                     coop = true;  // queue full: the wavefront copies it below
@@ -741,11 +744,13 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
 __global__ void k_reset(DBatch b, uint32_t n_epochs) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *b.t0 = wall_clock64();
-    for (; i < n_epochs; i += gridDim.x * blockDim.x) {
-        b.ctr[i].group_cursor = 0;
-        b.ctr[i].nseg = 0;
-        b.ctr[i].nshort = 0;
-        b.ctr[i].pad = 0;
+    constexpr uint32_t per = 1 + 2 * kQParts;  // counters per epoch
+    for (; i < n_epochs * per; i += gridDim.x * blockDim.x) {
+        const uint32_t e = i / per, k = i % per;
+        if (k == 0)
+            b.ctr[e].group_cursor = 0;
+        else
+            b.ctr[e].q[k - 1][0] = 0;
     }
 }
 
@@ -783,14 +788,19 @@ __global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uin
     const uint64_t ngroups = (n + G - 1) / G;
     GroupOut st = {0, 0, 0, 0, 0, 0};
     devirt_request dummy = {};
-    for (;;) {
+    // Each wavefront takes group (its global index) first, without an atomic;
+    // further groups come from the cursor, numbered after those first ones.
+    // The next claim is issued before the current group is translated, so its
+    // round trip overlaps the group's own loads.
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    uint64_t gi = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (uint64_t)wave;
+    while (gi < ngroups) {
         uint32_t g = 0;
         if (lane_id() == 0) g = atomicAdd(&b.ctr[epoch].group_cursor, 1u);
-        g = uniform_u32(shfl32(g, 0));
-        if ((uint64_t)g >= ngroups) break;
-        const uint64_t gs = r0 + (uint64_t)g * G;
+        const uint64_t gs = r0 + gi * G;
         const uint32_t gn = (uint32_t)((r1 - gs) < G ? (r1 - gs) : G);
         process_group<false>(v, b, gs, gn, dummy, epoch, cache, owner, false, b.ctr, st);
+        gi = nwaves + uniform_u32(shfl32(g, 0));
     }
     flush_counters(b.counters, st);
 }
@@ -800,32 +810,63 @@ __global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uin
 // SIMD holds) stay resident, and short segments a 16-lane quarter each, so
 // that a wavefront keeps up to four of them in flight.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_copy(DBatch b, uint32_t epoch) {
-    const uint32_t nl = b.ctr[epoch].nseg, ns = b.ctr[epoch].nshort;
-    const uint64_t nlong = nl < b.seg_cap ? nl : b.seg_cap;
-    const uint64_t nshort = ns < b.seg_cap ? ns : b.seg_cap;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t w0 = uniform_u64((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const bool nt = b.nontemporal != 0;
     const int lane = lane_id();
+    const uint64_t pcap = b.seg_cap / kQParts;
+    // lane p < 32: part p of the long queue; lane 32 + p: part p of the short
+    // queue.  Exclusive scan of the part counts within each half.
+    uint32_t cnt = b.ctr[epoch].q[lane][0];
+    if (cnt > pcap) cnt = (uint32_t)pcap;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const uint32_t t = shfl32(incl, (lane & 31) >= d ? lane - d : lane);
+        if ((lane & 31) >= d) incl += t;
+    }
+    const uint32_t excl = incl - cnt;
+    const uint32_t nlong = uniform_u32(shfl32(incl, 31));
+    const uint32_t nshort = uniform_u32(shfl32(incl, 63));
+    const bool lo_half = lane < 32;
+    // queue index s lies in the last part whose exclusive start is <= s
+    // (parts are in lane order, so those lanes form a prefix of the half)
+
     // long segments: one per wavefront
     const DV_GLOBAL DSeg *segs = gp<const DV_GLOBAL DSeg>(b.segs);
     for (uint64_t s = w0; s < nlong; s += waves) {
-        const DSeg sg = segs[s];
+        const int p = 63 - __clzll(__ballot(lo_half && excl <= (uint32_t)s));
+        const uint64_t i = (uint64_t)p * pcap + (s - (uint32_t)__builtin_amdgcn_readlane((int)excl, p));
+        const DSeg sg = segs[i];
         copy_wave((uint8_t *)uniform_u64(sg.dst), (const uint8_t *)uniform_u64(sg.src), uniform_u32(sg.len), nt);
         if (b.t_done && lane == 0) {
             uint32_t old = atomicSub(&b.pending[sg.req], 1u);
             if (old == 1) b.t_done[sg.req] = now_ns(b);
         }
     }
-    // short segments: one per 16-lane quarter
+    // short segments: one per 16-lane quarter, four per wavefront per round
     const DV_GLOBAL DSeg *sh = gp<const DV_GLOBAL DSeg>(b.shorts);
-    const int l = lane & 15;
-    for (uint64_t s = 4 * w0 + (uint64_t)(lane >> 4); s < nshort; s += 4 * waves) {
-        const uint64_t src = sh[s].src, dst = sh[s].dst;
-        const uint32_t len = sh[s].len;
+    const int q = lane >> 4, l = lane & 15;
+    for (uint64_t s0 = 4 * w0; s0 < nshort; s0 += 4 * waves) {
+        uint64_t i = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t sk = (uint32_t)s0 + (uint32_t)k;
+            const int p = 63 - __clzll(__ballot(!lo_half && excl <= sk) >> 32);
+            const uint64_t ik = (uint64_t)p * pcap + (sk - (uint32_t)__builtin_amdgcn_readlane((int)excl, 32 + p));
+            if (q == k) i = ik;
+        }
+        const bool mine = s0 + (uint64_t)q < nshort;
+        uint64_t src = 0, dst = 0;
+        uint32_t len = 0, req = 0;
+        if (mine) {
+            src = sh[i].src;
+            dst = sh[i].dst;
+            len = sh[i].len;
+            req = sh[i].req;
+        }
         copy_span<16>((uint8_t *)dst, (const uint8_t *)src, len, nt, l);
-        if (b.t_done && l == 0) {
-            const uint32_t req = sh[s].req;
+        if (mine && b.t_done && l == 0) {
             uint32_t old = atomicSub(&b.pending[req], 1u);
             if (old == 1) b.t_done[req] = now_ns(b);
         }
@@ -837,8 +878,7 @@ __global__ void __launch_bounds__(64) k_plain(DView v, DBatch b, devirt_request 
     __shared__ uint32_t owner[kCacheWays];
     if (threadIdx.x < kCacheWays) cache[threadIdx.x].key = ~0ull;
     if (threadIdx.x == 0) {
-        b.ctr[0].nseg = 0;
-        b.ctr[0].nshort = 0;
+        for (uint32_t k = 0; k < 2 * kQParts; ++k) b.ctr[0].q[k][0] = 0;
         *b.t0 = wall_clock64();
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
