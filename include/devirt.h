@@ -204,8 +204,6 @@ typedef struct {
                                  translating lane itself                            */
     uint32_t use_graph;       /* 1: capture each distinct batch shape as a HIP graph
                                  and replay it                                     */
-    uint32_t fused;           /* 1: run all epochs of a batch in one persistent
-                                 launch with device-side epoch barriers             */
     uint32_t overlap;         /* 1: translate epoch e+1 on a second stream while
                                  epoch e is being copied                          */
 } devirt_config;

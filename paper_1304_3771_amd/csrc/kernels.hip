@@ -691,7 +691,7 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
             }
         }
         st.segs += __popcll(__ballot(q_ok != 0));
-        st.inl += __popcll(__ballot(small));
+        st.inl += __popcll(__ballot(small || coop));  // inline and queue-overflow copies
         // per-request count of queued segments (for completion times)
         {
             const uint64_t okm = __ballot(q_ok != 0);

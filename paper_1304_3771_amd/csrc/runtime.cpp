@@ -50,7 +50,6 @@ static devirt_config default_config() {
     c.nontemporal = 0;
     c.inline_bytes = 0;
     c.use_graph = 1;
-    c.fused = 0;
     c.overlap = 1;
     return c;
 }
@@ -64,7 +63,7 @@ static int check_config(const devirt_config &c) {
     if (c.copy_wgs_per_cu < 1 || c.copy_wgs_per_cu > 64) return dv_fail(-EINVAL, "copy_wgs_per_cu must be 1..64");
     if (c.nontemporal > 1 || c.use_graph > 1) return dv_fail(-EINVAL, "nontemporal/use_graph must be 0 or 1");
     if (c.inline_bytes > 256) return dv_fail(-EINVAL, "inline_bytes must be <= 256");
-    if (c.fused > 1 || c.overlap > 1) return dv_fail(-EINVAL, "fused/overlap must be 0 or 1");
+    if (c.overlap > 1) return dv_fail(-EINVAL, "overlap must be 0 or 1");
     return 0;
 }
 
@@ -355,7 +354,7 @@ static uint64_t default_seg_cap() {
         unsigned long long v = strtoull(e, nullptr, 10);
         if (v >= 64) return v;
     }
-    return 4ull << 20;  // 4 Mi segments (128 MiB)
+    return 8ull << 20;  // 8 Mi segments per queue (256 MiB)
 }
 
 Workspace *get_ws(devirt_ctx *c, hipStream_t s) {
@@ -760,7 +759,6 @@ extern "C" int devirt_set_config(devirt_ctx *c, const devirt_config *cfg) {
     if (!c || !cfg) return dv_fail(-EINVAL, "NULL argument");
     int rc = check_config(*cfg);
     if (rc) return rc;
-    if (cfg->fused) return dv_fail(-EINVAL, "the fused persistent batch launch is not available in this build");
     c->cfg = *cfg;
     c->cfg_version++;
     return 0;
@@ -812,16 +810,19 @@ extern "C" int devirt_autotune(devirt_ctx *c, const devirt_request *reqs, uint64
         Setter set;
         std::vector<uint32_t> values;
     };
+    // Overlap first: the best group size depends on whether translation
+    // shares the GPU with the copies.  Without overlap the translate grid is
+    // the 3 workgroups of 256 per CU that its registers allow.
     const std::vector<Knob> knobs = {
-        {[](devirt_config &k, uint32_t v) { k.group = v; }, {8, 16, 32, 64}},
         {[](devirt_config &k, uint32_t v) {
              k.overlap = v ? 1 : 0;
-             k.xlat_wgs_per_cu = v ? v : 8;
+             k.xlat_wgs_per_cu = v ? v : 3;
          },
          {0, 1, 2}},
+        {[](devirt_config &k, uint32_t v) { k.group = v; }, {8, 16, 32, 64}},
         {[](devirt_config &k, uint32_t v) { k.copy_wg = v; }, {256, 512, 1024}},
-        {[](devirt_config &k, uint32_t v) { k.copy_wgs_per_cu = v; }, {2, 4, 8, 16}},
-        {[](devirt_config &k, uint32_t v) { k.seg_chunks = v; }, {4, 16, 64}},
+        {[](devirt_config &k, uint32_t v) { k.copy_wgs_per_cu = v; }, {4, 8, 16}},
+        {[](devirt_config &k, uint32_t v) { k.seg_chunks = v; }, {1, 2, 4, 16, 64}},
     };
     for (const auto &kn : knobs) {
         if (rc) break;
