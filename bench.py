@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GB/s copied + Mreq/s translated; p50/p99 latency, batched vs per-request"
 HBM_PEAK_GBS = 8000.0
+ROOF_STEPS = 3  # profiled steps the roofline is measured over
 WORKLOADS = {
     "C2": "one guest, 4 GiB guest memory, 4-level paging, 70/30 4KiB/2MiB pages, 16 memslots, "
           "5% not-present, 1e6 requests log-uniform 64B-64KiB, 50/50 direction",
@@ -282,11 +283,43 @@ def main():
     def step():
         ctx.submit_batch(dw.reqs, n, res, wl.epoch_end, faults, nf)
 
+    def profiled_steps(k):
+        """k steps with HIP events around every kernel launch (no graphs); summed stats."""
+        tot = None
+        for _ in range(k):
+            reset()
+            ctx.set_profiling(True)
+            ctx.reset_stats()
+            step()
+            ctx.sync()
+            st = ctx.get_stats()
+            ctx.set_profiling(False)
+            tot = st if tot is None else {key: tot[key] + st[key] for key in st}
+        return tot
+
     for i in range(args.warmup):
         reset()
         step()
         ctx.sync()
     log(f"warmup done ({args.warmup})")
+    if args.profile_only:
+        # the steps the roofline is measured on, for rocprofv3 to trace
+        st = profiled_steps(args.steps)
+        r = res.cpu().numpy().view(dv.RESULT_DTYPE)
+        copied = int(r["bytes_done"].sum())
+        # a plain copy-like kernel of known size (1 GiB read + 1 GiB written) to scale HBM counters
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        for _ in range(3):
+            torch.add(a, 1, out=b)
+        torch.cuda.synchronize()
+        avg = st["copy_ms"] / max(1, st["copy_launches"])
+        log(f"profiled steps: copy kernel {st['copy_launches']} launches, average {avg:.4f} ms (HIP events)")
+        print(json.dumps({"workload": args.workload, "steps": args.steps,
+                          "copy_launches": st["copy_launches"], "copy_avg_ms_hip_events": avg,
+                          "copy_launches_per_step": int(len(wl.epoch_end)),
+                          "alg_copy_bytes_per_step": 2 * copied, "calibration_bytes_each_way": 1 << 30}))
+        return
     times = []
     for i in range(args.steps):
         reset()
@@ -301,29 +334,13 @@ def main():
     ms_step = 1e3 * float(np.mean(times))
     gbs = copied / (ms_step * 1e-3) / 1e9
     log(f"batched: {ms_step:.3f} ms/step, {gbs:.1f} GB/s copied, {int(nf.item())} faults")
-    if args.profile_only:
-        # a plain copy-like kernel of known size (1 GiB read + 1 GiB written) to scale HBM counters
-        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        b = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        for _ in range(3):
-            torch.add(a, 1, out=b)
-        torch.cuda.synchronize()
-        print(json.dumps({"workload": args.workload, "ms_per_step": ms_step, "gbs": gbs,
-                          "copy_launches_per_step": int(len(wl.epoch_end)),
-                          "alg_copy_bytes_per_step": 2 * copied, "calibration_bytes_each_way": 1 << 30}))
-        return
 
-    # ---- roofline of the dominant kernel (copy), HIP events around each launch
-    reset()
-    ctx.set_profiling(True)
-    ctx.reset_stats()
-    step()
-    ctx.sync()
-    st = ctx.get_stats()
-    ctx.set_profiling(False)
+    # ---- roofline of the dominant kernel (copy): HIP events around each
+    # launch on its stream, over ROOF_STEPS steps of the same batch and config
+    st = profiled_steps(ROOF_STEPS)
     copy_ms = st["copy_ms"]
     copy_launches = max(1, st["copy_launches"])
-    alg_copy = 2 * copied  # every copied byte is read once and written once
+    alg_copy = 2 * copied * ROOF_STEPS  # every copied byte is read once and written once
     achieved = (alg_copy / copy_launches) / (copy_ms / copy_launches * 1e-3) / 1e9 if copy_ms > 0 else None
     traffic = measured_traffic(args.workload)
     roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
@@ -331,11 +348,23 @@ def main():
             "kernel": "k_copy", "launches": copy_launches,
             "avg_launch_ms": round(copy_ms / copy_launches, 4),
             "alg_bytes_per_launch": alg_copy // copy_launches}
-    log(f"copy kernel: {copy_launches} launches, {copy_ms:.3f} ms, {achieved:.1f} GB/s algorithmic; "
-        f"translate kernel: {st['xlat_launches']} launches, {st['xlat_ms']:.3f} ms; pages {st['pages_walked']}, "
-        f"cache hits {st['cache_hits']} misses {st['cache_misses']}, segments {st['segments']}, "
-        f"A/D ORs {st['ad_atomics']}")
-    path_alg = 2 * copied + 56 * n + 8 * st["pages_walked"] + 24 * int(nf.item())
+    # the same measurement with translation not overlapped: the copy kernel alone on the GPU
+    tuned = ctx.get_config()
+    ctx.set_config(**{**tuned, "overlap": 0, "xlat_wgs_per_cu": 3})
+    st_alone = profiled_steps(ROOF_STEPS)
+    ctx.set_config(**tuned)
+    alone_ms = st_alone["copy_ms"] / max(1, st_alone["copy_launches"])
+    alone = (alg_copy / copy_launches) / (alone_ms * 1e-3) / 1e9 if alone_ms > 0 else None
+    roof_alone = {"bound": "hbm", "achieved": round(alone, 1) if alone else None, "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(alone / HBM_PEAK_GBS, 4) if alone else None,
+                  "kernel": "k_copy", "avg_launch_ms": round(alone_ms, 4), "config": "overlap off"}
+    log(f"copy kernel alone (no overlap): {alone_ms:.4f} ms/launch, {alone:.1f} GB/s algorithmic")
+    ps = {k: v // ROOF_STEPS if isinstance(v, int) else v / ROOF_STEPS for k, v in st.items()}  # per step
+    log(f"copy kernel: {ps['copy_launches']} launches/step, {ps['copy_ms']:.3f} ms/step, {achieved:.1f} GB/s "
+        f"algorithmic; translate kernel: {ps['xlat_launches']} launches/step, {ps['xlat_ms']:.3f} ms/step; "
+        f"per step: pages {ps['pages_walked']}, cache hits {ps['cache_hits']} misses {ps['cache_misses']}, "
+        f"segments {ps['segments']}, A/D ORs {ps['ad_atomics']}")
+    path_alg = 2 * copied + 56 * n + 8 * ps["pages_walked"] + 24 * int(nf.item())
     path_frac = path_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
     # ---- batched per-request completion latency (device clock)
@@ -429,6 +458,7 @@ def main():
         "per_request": {**{k: round(v, 3) for k, v in plain.items()}, "latency_us": lat_plain,
                         "latency_clock": "host, launch to stream sync"},
         "roofline": roof,
+        "roofline_copy_alone": roof_alone,
         "path_roofline_frac": round(path_frac, 4),
         "cpu_baseline": cpu,
     }

@@ -431,8 +431,10 @@ int prof_begin(devirt_ctx *c, hipStream_t s, int kind, ProfEv **out) {
     if (!c->profiling) return 0;
     ProfEv e;
     e.kind = kind;
-    HIPCHK(hipEventCreate(&e.a));
-    HIPCHK(hipEventCreate(&e.b));
+    // timing only: no system-scope fence (a cache writeback and invalidate
+    // that would be counted in the bracketed kernel's time)
+    HIPCHK(hipEventCreateWithFlags(&e.a, hipEventDisableSystemFence));
+    HIPCHK(hipEventCreateWithFlags(&e.b, hipEventDisableSystemFence));
     HIPCHK(hipEventRecord(e.a, s));
     c->prof.push_back(e);
     *out = &c->prof.back();
