@@ -155,19 +155,26 @@ def serving(args):
         t0 = time.monotonic_ns()
         i = 0
         polls = 0
+        t_sub = t_poll = 0
+        arrival = tr.arrival_ns.astype(np.int64)  # same dtype as `now`: no per-call cast of the whole array
         try:
             while i < n_ops:
-                now = time.monotonic_ns() - t0
-                j = int(np.searchsorted(tr.arrival_ns, now, side="right"))
+                now = np.int64(time.monotonic_ns() - t0)
+                j = int(np.searchsorted(arrival, now, side="right"))
                 if j > i:
+                    ta = time.monotonic_ns()
                     srv.submit(reqs[i:j])
+                    t_sub += time.monotonic_ns() - ta
                     i = j
                 polls += 1
                 if polls % 16 == 0:
+                    ta = time.monotonic_ns()
                     c = srv.poll(1 << 14, pbuf)
+                    t_poll += time.monotonic_ns() - ta
                     if len(c):
                         comps.append(c)
             srv.drain()
+            sst = srv.stats()
             while True:
                 c = srv.poll(1 << 20)
                 if not len(c):
@@ -180,10 +187,29 @@ def serving(args):
         lat = (c["t_done_ns"].astype(np.int64) - (t0 + tr.arrival_ns.astype(np.int64))) / 1e3
         span = (c["t_done_ns"].max() - t0) / 1e9
         nbytes = int(c["bytes_done"].sum())
+        wait = (c["t_admit_ns"].astype(np.int64) - (t0 + tr.arrival_ns.astype(np.int64))) / 1e3
+        lag = (c["t_submit_ns"].astype(np.int64) - (t0 + tr.arrival_ns.astype(np.int64))) / 1e3
+        run = (c["t_done_ns"].astype(np.int64) - c["t_admit_ns"].astype(np.int64)) / 1e3
+        launches = len(np.unique(c["t_admit_ns"]))  # operations admitted together share the stamp
         rec = {"rate_mreq_s": lam / 1e6, "ops": n_ops, "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
-               "throughput_mreq_s": n_ops / span / 1e6, "gbs": nbytes / span / 1e9}
+               "throughput_mreq_s": n_ops / span / 1e6, "gbs": nbytes / span / 1e9,
+               "submit_lag_us": {"p50": pct(lag, 50), "p99": pct(lag, 99)},
+               "admission_wait_us": {"p50": pct(wait, 50), "p99": pct(wait, 99)},
+               "in_flight_us": {"p50": pct(run, 50), "p99": pct(run, 99)},
+               "launches": launches, "ops_per_launch": round(n_ops / max(1, launches), 1),
+               "server_thread": sst}
+        log(f"  driver: {polls} iterations, {t_sub / 1e9:.3f} s in submit, {t_poll / 1e9:.3f} s in poll")
+        log(f"  server thread over {span:.2f} s: inbox {sst['ns_inbox'] / 1e9:.3f} s, completions "
+            f"{sst['ns_complete'] / 1e9:.3f} s, admission {sst['ns_admit'] / 1e9:.3f} s, launches "
+            f"{sst['ns_launch'] / 1e9:.3f} s ({sst['launches']} launches, {sst['loops']} loops)")
         # the plain per-request path at the same arrival rate (bounded sample)
         m = min(n_ops, args.serve_plain_ops)
+        if m == 0:
+            out_rates.append(rec)
+            log(f"lambda {lam / 1e6:.2f} M/s: served p50 {rec['p50_us']:.0f} us p99 {rec['p99_us']:.0f} us "
+                f"(submit lag p50 {pct(lag, 50):.0f}, wait p50 {pct(wait, 50):.0f}, in flight p50 {pct(run, 50):.0f} p99 {pct(run, 99):.0f}; "
+                f"{launches} launches, {rec['ops_per_launch']} ops each), {rec['throughput_mreq_s']:.3f} Mreq/s")
+            continue
         stream = torch.cuda.current_stream()
         res = torch.zeros(m * 24, dtype=torch.uint8, device="cuda")
         done = np.zeros(m, np.int64)
@@ -199,7 +225,9 @@ def serving(args):
         plat = (done - (t0p + tr.arrival_ns[:m].astype(np.int64))) / 1e3
         rec["per_request"] = {"ops": m, "p50_us": pct(plat, 50), "p99_us": pct(plat, 99),
                               "throughput_mreq_s": m / ((done[-1] - t0p) / 1e9) / 1e6}
-        log(f"lambda {lam / 1e6:.2f} M/s: served p50 {rec['p50_us']:.0f} us p99 {rec['p99_us']:.0f} us, "
+        log(f"lambda {lam / 1e6:.2f} M/s: served p50 {rec['p50_us']:.0f} us p99 {rec['p99_us']:.0f} us "
+            f"(submit lag p50 {pct(lag, 50):.0f}, wait p50 {pct(wait, 50):.0f}, in flight p50 {pct(run, 50):.0f} p99 {pct(run, 99):.0f}; "
+            f"{launches} launches, {rec['ops_per_launch']} ops each), "
             f"{rec['throughput_mreq_s']:.3f} Mreq/s, {rec['gbs']:.1f} GB/s; per-request p50 "
             f"{rec['per_request']['p50_us']:.0f} us p99 {rec['per_request']['p99_us']:.0f} us")
         out_rates.append(rec)

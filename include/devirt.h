@@ -288,6 +288,20 @@ int devirt_server_drain(devirt_server *srv);
 /* Stop the thread (after draining) and free the server. */
 int devirt_server_stop(devirt_server *srv);
 
+/* Where the server thread's time goes (cumulative since start; host clock). */
+typedef struct {
+    uint64_t loops;        /* iterations of the server loop                         */
+    uint64_t launches;     /* batches launched                                      */
+    uint64_t ops;          /* operations completed                                  */
+    uint64_t ns_inbox;     /* moving submitted operations into guest-thread FIFOs   */
+    uint64_t ns_complete;  /* polling slot events and turning results into
+                              completions                                          */
+    uint64_t ns_admit;     /* admission and writing descriptors                     */
+    uint64_t ns_launch;    /* enqueueing the kernels of a batch                     */
+} devirt_server_stats;
+/* Read the counters (any thread; values may be a few iterations old). */
+int devirt_server_get_stats(devirt_server *srv, devirt_server_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

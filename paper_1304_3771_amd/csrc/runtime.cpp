@@ -624,7 +624,11 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
         hipEvent_t t_done = overlap ? w->events[2 * e] : nullptr;
         hipEvent_t c_done = overlap ? w->events[2 * e + 1] : nullptr;
         if (r1 > r0) {
-            const uint64_t groups = (r1 - r0 + c->cfg.group - 1) / c->cfg.group;
+            // A small epoch gets smaller groups, so that it still spreads over
+            // about 4 wavefronts per CU (results do not depend on the group).
+            const uint64_t spread = (r1 - r0 + 4ull * c->cus - 1) / (4ull * c->cus);
+            be.group = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(c->cfg.group, spread));
+            const uint64_t groups = (r1 - r0 + be.group - 1) / be.group;
             if (overlap && e >= 2) HIPCHK(hipStreamWaitEvent(side, w->events[2 * (e - 2) + 1], 0));
             ProfEv *pe;
             if ((rc = prof_begin(c, side, 1, &pe))) return rc;

@@ -22,6 +22,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <mutex>
 #include <thread>
@@ -42,6 +43,14 @@ struct Op {
     uint64_t ticket;
     devirt_request r;
     uint64_t t_submit;
+    uint32_t th;  // index of its guest thread (set by the loop)
+};
+
+// A guest thread (asid, tag): its waiting operations and whether one of its
+// operations is in flight.
+struct GThread {
+    std::deque<Op> q;
+    bool busy = false;
 };
 
 // A launch slot: its own stream and workspace, and pinned host buffers that
@@ -68,18 +77,24 @@ struct devirt_server {
     std::string err_msg;
 
     std::mutex mu;  // guards inbox and done
+    std::condition_variable wake;  // submit -> idle loop
     std::deque<Op> inbox;
     std::deque<devirt_completion> done;
     uint64_t next_ticket = 0;
     std::atomic<uint64_t> submitted{0}, completed{0};
 
-    // owned by the loop thread
-    std::unordered_map<uint64_t, std::deque<Op>> fifo;
-    std::unordered_map<uint64_t, bool> busy;
-    std::deque<uint64_t> ready;
+    // owned by the loop thread: guest threads by index (one hash lookup per
+    // operation, at intake), indices of ready threads
+    std::unordered_map<uint64_t, uint32_t> tindex;
+    std::vector<GThread> threads;
+    std::deque<uint32_t> ready;
+    std::vector<devirt_completion> outbuf;
     uint64_t inflight_ops = 0, inflight_bytes = 0;
     std::vector<Slot> slots;
     uint64_t launches = 0;
+    // time accounting (written by the loop thread, read by any)
+    std::atomic<uint64_t> st_loops{0}, st_launches{0}, st_ops{0};
+    std::atomic<uint64_t> ns_inbox{0}, ns_complete{0}, ns_admit{0}, ns_launch{0};
 };
 
 static thread_local bool tl_server_thread = false;
@@ -90,11 +105,14 @@ static uint64_t thread_key(const devirt_request &r) { return ((uint64_t)r.asid <
 static int launch_slot(devirt_server *s, Slot &sl) {
     const uint32_t n = (uint32_t)sl.ops.size();
     for (uint32_t i = 0; i < n; ++i) sl.h_reqs[i] = sl.ops[i].r;
+    const uint64_t t0 = now_ns();
     int rc = dv_submit(s->ctx, sl.h_reqs, n, nullptr, 0, sl.h_res, nullptr, nullptr, nullptr, sl.stream, false);
     if (rc) return rc;
     if (hipEventRecord(sl.ev, sl.stream) != hipSuccess) return dv_fail(-EIO, "server: event record failed");
+    s->ns_launch += now_ns() - t0;
     sl.busy = true;
     s->launches++;
+    s->st_launches++;
     return 0;
 }
 
@@ -103,20 +121,33 @@ static void server_loop(devirt_server *s) {
     hipSetDevice(s->ctx->device);
     std::deque<Op> in;
     const uint32_t max_batch = s->cfg.max_batch ? s->cfg.max_batch : s->cfg.max_inflight;
+    uint64_t taken = 0;  // operations moved out of the inbox so far
     for (;;) {
         bool progress = false;
-        {
+        const uint64_t t_a = now_ns();
+        s->st_loops++;
+        // the lock is taken only when something was submitted: a loop that
+        // spins on the mutex would keep submitters waiting for it
+        if (s->submitted.load(std::memory_order_acquire) != taken) {
             std::lock_guard<std::mutex> g(s->mu);
             in.swap(s->inbox);
+            taken += in.size();
         }
         for (auto &op : in) {
-            const uint64_t k = thread_key(op.r);
-            auto &q = s->fifo[k];
-            if (q.empty() && !s->busy[k]) s->ready.push_back(k);
-            q.push_back(op);
+            auto it = s->tindex.find(thread_key(op.r));
+            if (it == s->tindex.end()) {
+                it = s->tindex.emplace(thread_key(op.r), (uint32_t)s->threads.size()).first;
+                s->threads.emplace_back();
+            }
+            op.th = it->second;
+            GThread &g = s->threads[op.th];
+            if (g.q.empty() && !g.busy) s->ready.push_back(op.th);
+            g.q.push_back(op);
             progress = true;
         }
         in.clear();
+        const uint64_t t_b = now_ns();
+        s->ns_inbox += t_b - t_a;
         // completions
         for (auto &sl : s->slots) {
             if (!sl.busy) continue;
@@ -129,7 +160,8 @@ static void server_loop(devirt_server *s) {
                 continue;
             }
             const uint64_t t = now_ns();
-            std::vector<devirt_completion> out(sl.ops.size());
+            std::vector<devirt_completion> &out = s->outbuf;
+            out.resize(sl.ops.size());
             for (size_t i = 0; i < sl.ops.size(); ++i) {
                 const Op &op = sl.ops[i];
                 out[i].ticket = op.ticket;
@@ -137,39 +169,42 @@ static void server_loop(devirt_server *s) {
                 out[i].t_submit_ns = op.t_submit;
                 out[i].t_admit_ns = sl.t_admit[i];
                 out[i].t_done_ns = t;
-                const uint64_t k = thread_key(op.r);
-                s->busy[k] = false;
-                if (!s->fifo[k].empty()) s->ready.push_back(k);
+                GThread &g = s->threads[op.th];
+                g.busy = false;
+                if (!g.q.empty()) s->ready.push_back(op.th);
                 s->inflight_ops--;
                 s->inflight_bytes -= op.r.len;
             }
             {
                 std::lock_guard<std::mutex> g(s->mu);
-                for (auto &c : out) s->done.push_back(c);
+                s->done.insert(s->done.end(), out.begin(), out.end());
             }
             s->completed += sl.ops.size();
+            s->st_ops += sl.ops.size();
             sl.ops.clear();
             sl.t_admit.clear();
             sl.busy = false;
             progress = true;
         }
+        const uint64_t t_c = now_ns();
+        s->ns_complete += t_c - t_b;
         // admission into free slots
+        const uint64_t launch_before = s->ns_launch.load();
         if (!s->err) {
             for (auto &sl : s->slots) {
                 if (sl.busy || s->ready.empty()) continue;
                 const uint64_t t = now_ns();
                 while (!s->ready.empty() && sl.ops.size() < max_batch && s->inflight_ops < s->cfg.max_inflight) {
-                    const uint64_t k = s->ready.front();
-                    auto &q = s->fifo[k];
-                    const Op &op = q.front();
+                    GThread &g = s->threads[s->ready.front()];
+                    const Op &op = g.q.front();
                     if (s->inflight_ops > 0 && s->inflight_bytes + op.r.len > s->cfg.pool_bytes) break;
                     s->ready.pop_front();
                     sl.ops.push_back(op);
                     sl.t_admit.push_back(t);
                     s->inflight_ops++;
                     s->inflight_bytes += op.r.len;
-                    s->busy[k] = true;
-                    q.pop_front();
+                    g.busy = true;
+                    g.q.pop_front();
                 }
                 if (sl.ops.empty()) break;
                 int rc = launch_slot(s, sl);
@@ -181,9 +216,24 @@ static void server_loop(devirt_server *s) {
                 progress = true;
             }
         }
+        s->ns_admit += (now_ns() - t_c) - (s->ns_launch.load() - launch_before);
         if (s->stop.load() && s->completed.load() == s->submitted.load()) break;
         if (s->stop.load() && s->err) break;
-        if (!progress) std::this_thread::yield();
+        if (!progress) {
+            bool inflight = false;
+            for (auto &sl : s->slots) inflight = inflight || sl.busy;
+            if (inflight || !s->ready.empty()) {
+                // batches on the GPU: poll again soon, without hogging the core
+                for (int k = 0; k < 64; ++k) __builtin_ia32_pause();
+                std::this_thread::yield();
+            } else {
+                // nothing to do until something is submitted (or stop)
+                std::unique_lock<std::mutex> g(s->mu);
+                s->wake.wait_for(g, std::chrono::milliseconds(1), [&] {
+                    return s->stop.load() || s->submitted.load(std::memory_order_acquire) != taken;
+                });
+            }
+        }
     }
     tl_server_thread = false;
 }
@@ -253,8 +303,9 @@ extern "C" int devirt_server_submit(devirt_server *s, const devirt_request *reqs
     const size_t cap = 1u << 24;
     std::lock_guard<std::mutex> g(s->mu);
     uint32_t k = 0;
-    for (; k < n && s->inbox.size() < cap; ++k) s->inbox.push_back(Op{s->next_ticket++, reqs[k], t});
+    for (; k < n && s->inbox.size() < cap; ++k) s->inbox.push_back(Op{s->next_ticket++, reqs[k], t, 0});
     s->submitted += k;
+    if (k) s->wake.notify_one();
     if (n_queued) *n_queued = k;
     if (k < n) return dv_fail(-EBUSY, "server inbox full");
     return 0;
@@ -284,11 +335,27 @@ extern "C" int devirt_server_drain(devirt_server *s) {
 
 extern "C" int devirt_server_stop(devirt_server *s) {
     if (!s) return dv_fail(-EINVAL, "NULL argument");
-    s->stop = true;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->wake.notify_one();
     if (s->th.joinable()) s->th.join();
     const int err = s->err;
     std::string msg = s->err_msg;
     free_server(s);
     if (err) return dv_fail(err, "server failed: %s", msg.c_str());
+    return 0;
+}
+
+extern "C" int devirt_server_get_stats(devirt_server *s, devirt_server_stats *out) {
+    if (!s || !out) return dv_fail(-EINVAL, "NULL argument");
+    out->loops = s->st_loops.load();
+    out->launches = s->st_launches.load();
+    out->ops = s->st_ops.load();
+    out->ns_inbox = s->ns_inbox.load();
+    out->ns_complete = s->ns_complete.load();
+    out->ns_admit = s->ns_admit.load();
+    out->ns_launch = s->ns_launch.load();
     return 0;
 }

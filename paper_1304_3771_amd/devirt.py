@@ -65,6 +65,14 @@ class ServerCfg(ctypes.Structure):
                 ("streams", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "loops", "launches", "ops", "ns_inbox", "ns_complete", "ns_admit", "ns_launch")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class Result(ctypes.Structure):
     _fields_ = [("bytes_done", ctypes.c_uint64), ("fault_gva", ctypes.c_uint64), ("code", ctypes.c_uint32),
                 ("level", ctypes.c_uint16), ("pad", ctypes.c_uint16)]
@@ -108,6 +116,7 @@ _SIGS = {
     "devirt_server_poll": ([vp, vp, u32, ctypes.POINTER(u32)]),
     "devirt_server_drain": ([vp]),
     "devirt_server_stop": ([vp]),
+    "devirt_server_get_stats": ([vp, ctypes.POINTER(ServerStats)]),
 }
 
 
@@ -308,6 +317,11 @@ class Server:
 
     def drain(self):
         _check("devirt_server_drain", lib().devirt_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check("devirt_server_get_stats", lib().devirt_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
 
     def stop(self):
         if self._h:
