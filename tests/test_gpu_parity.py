@@ -144,6 +144,72 @@ def test_batch_matches_oracle(name):
     assert compare(name, got, exp) == []
 
 
+# Lengths on both sides of every split in the copy: 16-byte blocks, the 1 KiB
+# bound between 16-lane and whole-wavefront segments, and page crossings.
+ALIGN_LENS = [1, 2, 15, 16, 17, 31, 100, 255, 256, 257, 511, 1000, 1007, 1008, 1009, 1023, 1024, 1025,
+              1100, 2047, 4095, 4096, 4097, 6000]
+
+
+def _alignment_workload():
+    """mix2m's tables with requests at every (guest address mod 16, host address
+    mod 16) pair for every length above, alternating direction: one epoch,
+    disjoint guest and host ranges laid out through the process's VMAs."""
+    import dataclasses
+    w = wl("mix2m")
+    p = w.procs[0]
+    vmas = [(int(b), int(z)) for b, z in p.vmas]
+    R = np.zeros(16 * 16 * len(ALIGN_LENS), gen.REQ_DTYPE)
+    v, g, h, k = 0, vmas[0][0], 0, 0
+    for L in ALIGN_LENS:
+        for a in range(16):
+            for b in range(16):
+                gva = (g + 15) // 16 * 16 + a
+                if gva + L > vmas[v][0] + vmas[v][1]:
+                    v += 1
+                    gva = (vmas[v][0] + 15) // 16 * 16 + a
+                host = (h + 15) // 16 * 16 + b
+                R[k] = (gva, host, L, p.asid, k % 2, (0, 0, 0), 0)
+                g, h, k = gva + L + 48, host + L + 48, k + 1
+    return dataclasses.replace(w, requests=R, epoch_end=np.array([k], np.uint64), pool_bytes=h + 64,
+                               req_vma=None)
+
+
+@pytest.mark.parametrize("path", ["batch", "batch_group1", "plain"])
+def test_copy_alignments(path):
+    """Every source/destination alignment pair and length class, bit-exact."""
+    import torch
+    import paper_1304_3771_amd as dv
+    from oracle import Oracle
+    w = _alignment_workload()
+    log(f"alignments {path}: {w.n_requests} requests")
+    assert Oracle.from_workload(w).check_conflicts(w.requests, w.epoch_end) is None  # one valid epoch
+    if path == "plain":
+        ctx = new_ctx()
+        try:
+            dw = device.load(ctx, w)
+            n = dw.n
+            res = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+            for i, r in enumerate(dw.reqs_host):
+                f = ctx.copy_to_guest if int(r["dir"]) == 1 else ctx.copy_from_guest
+                f(int(r["asid"]), int(r["gva"]), int(r["host"]), int(r["len"]), res.data_ptr() + 24 * i)
+            ctx.sync()
+            got_r = res.cpu().numpy().view(dv.RESULT_DTYPE)
+            arenas = device.read_arenas(ctx, dw)
+            pool = dw.pool.cpu().numpy()
+        finally:
+            ctx.close()
+        fidx = np.nonzero(got_r["code"] != 0)[0]
+        gf = np.zeros(len(fidx), dv.FAULT_DTYPE)
+        gf["req_index"], gf["fault_gva"], gf["code"], gf["level"] = fidx, got_r["fault_gva"][fidx], \
+            got_r["code"][fidx], got_r["level"][fidx]
+        got = (got_r, gf, arenas, pool)
+    else:
+        got = gpu_batch(w, cfg=dict(group=1) if path == "batch_group1" else None)
+    exp = oracle_batch(w)
+    assert compare(f"alignments {path}", got, exp) == []
+    assert int(np.count_nonzero(exp[0]["bytes_done"])) > w.n_requests // 2  # most requests copy bytes
+
+
 @pytest.mark.parametrize("cfg", [
     dict(group=1, seg_chunks=1),
     dict(group=64, seg_chunks=64, nontemporal=1),
