@@ -311,12 +311,13 @@ def main():
     def step():
         ctx.submit_batch(dw.reqs, n, res, wl.epoch_end, faults, nf)
 
-    def profiled_steps(k):
-        """k steps with HIP events around every kernel launch (no graphs); summed stats."""
+    def profiled_steps(k, counters=False):
+        """k steps with HIP events around every kernel launch (no graphs); summed stats.
+        Device counters (which add atomics of their own) only when asked for."""
         tot = None
         for _ in range(k):
             reset()
-            ctx.set_profiling(True)
+            ctx.set_profiling(True, counters=counters)
             ctx.reset_stats()
             step()
             ctx.sync()
@@ -387,9 +388,9 @@ def main():
                   "unit": "GB/s", "frac": round(alone / HBM_PEAK_GBS, 4) if alone else None,
                   "kernel": "k_copy", "avg_launch_ms": round(alone_ms, 4), "config": "overlap off"}
     log(f"copy kernel alone (no overlap): {alone_ms:.4f} ms/launch, {alone:.1f} GB/s algorithmic")
-    ps = {k: v // ROOF_STEPS if isinstance(v, int) else v / ROOF_STEPS for k, v in st.items()}  # per step
-    log(f"copy kernel: {ps['copy_launches']} launches/step, {ps['copy_ms']:.3f} ms/step, {achieved:.1f} GB/s "
-        f"algorithmic; translate kernel: {ps['xlat_launches']} launches/step, {ps['xlat_ms']:.3f} ms/step; "
+    ps = profiled_steps(1, counters=True)  # one more step for the device counters
+    log(f"copy kernel: {copy_launches // ROOF_STEPS} launches/step, {copy_ms / ROOF_STEPS:.3f} ms/step, "
+        f"{achieved:.1f} GB/s algorithmic; translate kernel: {st['xlat_ms'] / ROOF_STEPS:.3f} ms/step; "
         f"per step: pages {ps['pages_walked']}, cache hits {ps['cache_hits']} misses {ps['cache_misses']}, "
         f"segments {ps['segments']}, A/D ORs {ps['ad_atomics']}")
     path_alg = 2 * copied + 56 * n + 8 * ps["pages_walked"] + 24 * int(nf.item())

@@ -228,7 +228,7 @@ typedef struct {
     uint64_t epochs;         /* epochs launched                                    */
     uint64_t plain_calls;    /* devirt_copy_* calls                                */
     uint64_t graph_replays;  /* batches served by replaying a captured graph       */
-    /* the following are filled only while profiling is on */
+    /* the following are filled only while profiling (timing, then counters) */
     uint64_t copy_launches;  /* copy-kernel launches timed                         */
     double copy_ms;          /* summed copy-kernel time (HIP events)               */
     uint64_t xlat_launches;  /* translate-kernel launches timed                    */
@@ -241,10 +241,17 @@ typedef struct {
     uint64_t ad_atomics;     /* A/D atomic ORs issued                              */
 } devirt_stats;
 
-/* With profiling on, data-path calls run without graphs, each kernel launch
- * is bracketed by HIP events on the call's stream, and device counters are
- * gathered; devirt_get_stats synchronises to read them. */
-int devirt_set_profiling(devirt_ctx *ctx, int on);
+/* Profiling flags.  While any is set, data-path calls run without graphs.
+ *  DEVIRT_PROF_TIMING:   each kernel launch is bracketed by HIP events on the
+ *                        call's stream (copy_ms, xlat_ms and launch counts);
+ *  DEVIRT_PROF_COUNTERS: the kernels also gather device counters (pages,
+ *                        cache hits, segments, A/D ORs).  Gathering them costs
+ *                        atomics on shared addresses, so kernel times taken
+ *                        with this flag are pessimistic.
+ * devirt_get_stats synchronises to read them.  -EINVAL for unknown flags. */
+#define DEVIRT_PROF_TIMING 1
+#define DEVIRT_PROF_COUNTERS 2
+int devirt_set_profiling(devirt_ctx *ctx, int flags);
 int devirt_get_stats(devirt_ctx *ctx, devirt_stats *out);
 int devirt_reset_stats(devirt_ctx *ctx);
 

@@ -415,7 +415,7 @@ DBatch make_batch(devirt_ctx *c, Workspace *w) {
     b.ctr = w->ctr;
     b.pending = w->pending;
     b.t0 = w->t0;
-    b.counters = c->profiling ? c->d_counters : nullptr;
+    b.counters = (c->profiling & DEVIRT_PROF_COUNTERS) ? c->d_counters : nullptr;
     b.ns_num = 1000000ull;
     b.ns_den = c->wall_khz;
     b.group = c->cfg.group;
@@ -428,7 +428,7 @@ DBatch make_batch(devirt_ctx *c, Workspace *w) {
 // ------------------------------------------------------------- profiling
 int prof_begin(devirt_ctx *c, hipStream_t s, int kind, ProfEv **out) {
     *out = nullptr;
-    if (!c->profiling) return 0;
+    if (!(c->profiling & DEVIRT_PROF_TIMING)) return 0;
     ProfEv e;
     e.kind = kind;
     // timing only: no system-scope fence (a cache writeback and invalidate
@@ -467,9 +467,10 @@ static int prof_collect(devirt_ctx *c) {
     return 0;
 }
 
-extern "C" int devirt_set_profiling(devirt_ctx *c, int on) {
+extern "C" int devirt_set_profiling(devirt_ctx *c, int flags) {
     if (!c) return dv_fail(-EINVAL, "ctx is NULL");
-    c->profiling = on ? 1 : 0;
+    if (flags & ~(DEVIRT_PROF_TIMING | DEVIRT_PROF_COUNTERS)) return dv_fail(-EINVAL, "unknown profiling flags");
+    c->profiling = flags;
     return 0;
 }
 
@@ -527,7 +528,7 @@ extern "C" int devirt_translate(devirt_ctx *c, uint32_t asid, const uint64_t *gv
     int rc = prof_begin(c, s, 1, &pe);
     if (rc) return rc;
     HIPCHK(launch_xlat(s, grid, block, view_of(c), asid, gva_dev, n, flags, out_dev,
-                       c->profiling ? c->d_counters : nullptr));
+                       (c->profiling & DEVIRT_PROF_COUNTERS) ? c->d_counters : nullptr));
     return prof_end(c, s, pe);
 }
 

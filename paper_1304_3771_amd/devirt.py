@@ -40,6 +40,9 @@ class DevirtError(RuntimeError):
         self.rc = rc
 
 
+PROF_TIMING, PROF_COUNTERS = 1, 2  # devirt_set_profiling flags
+
+
 class Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "group", "seg_chunks", "xlat_wg", "xlat_wgs_per_cu", "copy_wg", "copy_wgs_per_cu", "nontemporal",
@@ -278,8 +281,10 @@ class Context:
             _ptr(n_faults), _stream(stream), reps, ctypes.byref(best), ctypes.byref(ms)))
         return best.as_dict(), ms.value
 
-    def set_profiling(self, on: bool):
-        _check("devirt_set_profiling", lib().devirt_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on=True, counters: bool = True):
+        """Timing events (and, unless counters=False, device counters); off when on is False."""
+        flags = (PROF_TIMING | (PROF_COUNTERS if counters else 0)) if on else 0
+        _check("devirt_set_profiling", lib().devirt_set_profiling(self._h, flags))
 
     def get_stats(self) -> dict:
         s = Stats()
