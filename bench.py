@@ -120,8 +120,9 @@ def cpu_baseline(wl, seconds, name, max_vms=8):
         i += len(part)
         if dt < 0.2:
             chunk *= 2
-    sample = (f"{done} requests of {name} in index order" + (f" (the {len(reqs)} requests of VMs 0-{nvm - 1})"
-              if nvm < len(wl.vms) else "") + f", sequential, {tot_t:.1f} s on one of {os.cpu_count()} host cores")
+    sample = (f"{done} requests: {name}'s " + (f"{len(reqs)} requests of VMs 0-{nvm - 1}" if nvm < len(wl.vms)
+              else f"{len(reqs)} requests") + f" in index order, {done / len(reqs):.2f} passes, sequential, "
+              f"{tot_t:.1f} s on one of {os.cpu_count()} host cores")
     return {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle", "sample": sample,
             "mreq_s": round(done / tot_t / 1e6, 4)}
 
