@@ -150,7 +150,7 @@ def serving(args):
         reqs = tr.requests.copy()
         reqs["host"] += np.uint64(pool.data_ptr())
         srv = ctx.server_start(max_inflight=args.max_inflight, pool_bytes=args.pool_gib << 30,
-                               max_batch=args.max_batch, streams=args.streams)
+                               max_batch=args.max_batch, streams=args.streams, completion=args.completion)
         comps = []
         pbuf = np.empty(1 << 14, dv.COMPLETION_DTYPE)
         t0 = time.monotonic_ns()
@@ -238,7 +238,8 @@ def serving(args):
                       "config": {"workload": "C4: 8 VMs x 4 GiB, 4 processes x 64 guest threads each, Poisson "
                                              "arrivals, 60% 24B / 25% 4KiB / 14% 16-256KiB / 1% 4147200B",
                                  "max_inflight": args.max_inflight, "pool_gib": args.pool_gib,
-                                 "max_batch": args.max_batch, "streams": args.streams},
+                                 "max_batch": args.max_batch, "streams": args.streams,
+                                 "completion": args.completion},
                       "rates": out_rates}))
 
 
@@ -265,6 +266,8 @@ def main():
     ap.add_argument("--pool-gib", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=4096)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--completion", default="poll", choices=["poll", "notify", "blocking"],
+                    help="how the serving loop learns that a batch finished")
     args = ap.parse_args()
 
     if args.gpus != 1:

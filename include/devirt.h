@@ -263,14 +263,27 @@ int devirt_reset_stats(devirt_ctx *ctx);
  * descriptor slot is free and (c) the bytes of all operations in flight stay
  * within pool_bytes.  Admitted operations are batched continuously: while
  * earlier batches run on the GPU, newly admitted ones are launched on further
- * streams, and completions are polled (section 7.4 finds polling faster than
- * interrupts).  Page tables stay resident in the context. */
+ * streams.  Page tables stay resident in the context.
+ *
+ * How the server learns that a batch has finished (flags):
+ *  DEVIRT_SERVE_POLL     the server thread polls each batch's event (section
+ *                        7.4 finds polling faster than interrupts);
+ *  DEVIRT_SERVE_NOTIFY   a host function enqueued after each batch marks it
+ *                        done and wakes the server thread, which sleeps while
+ *                        batches run (the interrupt-style completion);
+ *  DEVIRT_SERVE_BLOCKING the server waits for each batch before it admits
+ *                        anything else: one batch at a time, no overlap (the
+ *                        blocking mode of section 5).
+ * Results do not depend on the mode. */
+#define DEVIRT_SERVE_POLL 0u
+#define DEVIRT_SERVE_NOTIFY 1u
+#define DEVIRT_SERVE_BLOCKING 2u
 typedef struct {
     uint32_t max_inflight; /* descriptor slots (operations admitted, not yet done)  */
     uint64_t pool_bytes;   /* byte budget of operations in flight                   */
     uint32_t max_batch;    /* operations per launch (0: max_inflight)               */
     uint32_t streams;      /* launches in flight at once, 1..8                      */
-    uint32_t flags;        /* reserved, 0                                           */
+    uint32_t flags;        /* completion mode: one DEVIRT_SERVE_* value             */
 } devirt_server_cfg;
 
 typedef struct {

@@ -59,6 +59,8 @@ struct GThread {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
+    devirt_server *srv = nullptr;  // for the completion host function
+    uint32_t idx = 0;
     devirt_request *h_reqs = nullptr;  // pinned, device-visible
     devirt_result *h_res = nullptr;    // pinned, device-visible
     std::vector<Op> ops;
@@ -77,7 +79,8 @@ struct devirt_server {
     std::string err_msg;
 
     std::mutex mu;  // guards inbox and done
-    std::condition_variable wake;  // submit -> idle loop
+    std::condition_variable wake;  // submit or a finished batch -> sleeping loop
+    std::atomic<uint32_t> done_bits{0};  // DEVIRT_SERVE_NOTIFY: slots whose batch finished
     std::deque<Op> inbox;
     std::deque<devirt_completion> done;
     uint64_t next_ticket = 0;
@@ -102,6 +105,18 @@ bool dv_in_server_thread() { return tl_server_thread; }
 
 static uint64_t thread_key(const devirt_request &r) { return ((uint64_t)r.asid << 32) | r.tag; }
 
+// Host function run by the HIP runtime once a batch has finished
+// (DEVIRT_SERVE_NOTIFY).  It makes no HIP call.
+static void on_batch_done(void *arg) {
+    Slot *sl = (Slot *)arg;
+    devirt_server *s = sl->srv;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->done_bits.fetch_or(1u << sl->idx, std::memory_order_release);
+    }
+    s->wake.notify_one();
+}
+
 static int launch_slot(devirt_server *s, Slot &sl) {
     const uint32_t n = (uint32_t)sl.ops.size();
     for (uint32_t i = 0; i < n; ++i) sl.h_reqs[i] = sl.ops[i].r;
@@ -109,6 +124,11 @@ static int launch_slot(devirt_server *s, Slot &sl) {
     int rc = dv_submit(s->ctx, sl.h_reqs, n, nullptr, 0, sl.h_res, nullptr, nullptr, nullptr, sl.stream, false);
     if (rc) return rc;
     if (hipEventRecord(sl.ev, sl.stream) != hipSuccess) return dv_fail(-EIO, "server: event record failed");
+    if (s->cfg.flags == DEVIRT_SERVE_NOTIFY &&
+        hipLaunchHostFunc(sl.stream, on_batch_done, &sl) != hipSuccess)
+        return dv_fail(-EIO, "server: cannot enqueue the completion function");
+    if (s->cfg.flags == DEVIRT_SERVE_BLOCKING && hipStreamSynchronize(sl.stream) != hipSuccess)
+        return dv_fail(-EIO, "server: batch failed");
     s->ns_launch += now_ns() - t0;
     sl.busy = true;
     s->launches++;
@@ -151,6 +171,11 @@ static void server_loop(devirt_server *s) {
         // completions
         for (auto &sl : s->slots) {
             if (!sl.busy) continue;
+            if (s->cfg.flags == DEVIRT_SERVE_NOTIFY) {
+                const uint32_t bit = 1u << sl.idx;
+                if (!(s->done_bits.load(std::memory_order_acquire) & bit)) continue;
+                s->done_bits.fetch_and(~bit, std::memory_order_relaxed);
+            }
             hipError_t q = hipEventQuery(sl.ev);
             if (q == hipErrorNotReady) continue;
             if (q != hipSuccess) {
@@ -222,15 +247,17 @@ static void server_loop(devirt_server *s) {
         if (!progress) {
             bool inflight = false;
             for (auto &sl : s->slots) inflight = inflight || sl.busy;
-            if (inflight || !s->ready.empty()) {
+            if ((inflight && s->cfg.flags != DEVIRT_SERVE_NOTIFY) || !s->ready.empty()) {
                 // batches on the GPU: poll again soon, without hogging the core
                 for (int k = 0; k < 64; ++k) __builtin_ia32_pause();
                 std::this_thread::yield();
             } else {
-                // nothing to do until something is submitted (or stop)
+                // nothing to do until something is submitted, a batch reports
+                // back (DEVIRT_SERVE_NOTIFY) or stop
                 std::unique_lock<std::mutex> g(s->mu);
                 s->wake.wait_for(g, std::chrono::milliseconds(1), [&] {
-                    return s->stop.load() || s->submitted.load(std::memory_order_acquire) != taken;
+                    return s->stop.load() || s->submitted.load(std::memory_order_acquire) != taken ||
+                           s->done_bits.load(std::memory_order_acquire) != 0;
                 });
             }
         }
@@ -263,15 +290,17 @@ extern "C" int devirt_server_start(devirt_ctx *c, const devirt_server_cfg *cfg, 
     if (c->server) return dv_fail(-EBUSY, "a server is already running on this context");
     if (cfg->max_inflight == 0 || cfg->pool_bytes == 0) return dv_fail(-EINVAL, "max_inflight and pool_bytes must be > 0");
     if (cfg->streams < 1 || cfg->streams > 8) return dv_fail(-EINVAL, "streams must be 1..8");
-    if (cfg->flags != 0) return dv_fail(-EINVAL, "flags must be 0");
+    if (cfg->flags > DEVIRT_SERVE_BLOCKING) return dv_fail(-EINVAL, "flags must be one DEVIRT_SERVE_* mode");
     if (hipSetDevice(c->device) != hipSuccess) return dv_fail(-EIO, "hipSetDevice");
     devirt_server *s = new devirt_server();
     s->ctx = c;
     s->cfg = *cfg;
     c->server = s;
     const uint32_t max_batch = cfg->max_batch ? cfg->max_batch : cfg->max_inflight;
-    s->slots.resize(cfg->streams);
+    s->slots.resize(cfg->streams);  // never resized again: host functions keep slot addresses
     for (auto &sl : s->slots) {
+        sl.srv = s;
+        sl.idx = (uint32_t)(&sl - s->slots.data());
         bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess &&
                   hipHostMalloc(&sl.h_reqs, (size_t)max_batch * sizeof(devirt_request),

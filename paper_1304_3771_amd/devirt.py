@@ -41,6 +41,7 @@ class DevirtError(RuntimeError):
 
 
 PROF_TIMING, PROF_COUNTERS = 1, 2  # devirt_set_profiling flags
+SERVE_MODES = {"poll": 0, "notify": 1, "blocking": 2}  # devirt_server_cfg.flags
 
 
 class Config(ctypes.Structure):
@@ -295,8 +296,9 @@ class Context:
         _check("devirt_reset_stats", lib().devirt_reset_stats(self._h))
 
     # ---- serving
-    def server_start(self, max_inflight=4096, pool_bytes=1 << 30, max_batch=0, streams=2):
-        cfg = ServerCfg(max_inflight, pool_bytes, max_batch, streams, 0)
+    def server_start(self, max_inflight=4096, pool_bytes=1 << 30, max_batch=0, streams=2, completion="poll"):
+        """completion: "poll", "notify" or "blocking" (the DEVIRT_SERVE_* modes)."""
+        cfg = ServerCfg(max_inflight, pool_bytes, max_batch, streams, SERVE_MODES[completion])
         h = vp()
         _check("devirt_server_start", lib().devirt_server_start(self._h, ctypes.byref(cfg), ctypes.byref(h)))
         return Server(h)

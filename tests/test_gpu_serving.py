@@ -1,7 +1,7 @@
 """Serving loop: every operation's result, and all memory, are the same alone
 (one operation at a time through the plain per-request path) and in the mix
-(continuous batching over several streams), and both equal the oracle.
-Tolerance: none (bit-exact)."""
+(continuous batching over several streams, each completion mode), and both
+equal the oracle.  Tolerance: none (bit-exact)."""
 import time
 
 import numpy as np
@@ -38,12 +38,14 @@ def _load(ctx, wl, tr):
     return dw, pool, reqs
 
 
-def test_alone_vs_mix(trace):
+@pytest.fixture(scope="module")
+def alone(trace):
+    """Every operation alone: one at a time, in submission order, through the
+    plain per-request path."""
     import torch
     import paper_1304_3771_amd as dv
     wl, tr = trace
     n = len(tr.requests)
-    # alone: one operation at a time, in submission order
     log("serving: alone")
     ctx = new_ctx()
     try:
@@ -54,17 +56,24 @@ def test_alone_vs_mix(trace):
             f = ctx.copy_to_guest if int(r["dir"]) == 1 else ctx.copy_from_guest
             f(int(r["asid"]), int(r["gva"]), int(r["host"]), int(r["len"]), res.data_ptr() + 24 * i, stream)
             stream.synchronize()
-        alone_res = res.cpu().numpy().view(dv.RESULT_DTYPE).copy()
-        alone_arenas = device.read_arenas(ctx, dw)
-        alone_pool = pool.cpu().numpy()
+        return (res.cpu().numpy().view(dv.RESULT_DTYPE).copy(), device.read_arenas(ctx, dw),
+                pool.cpu().numpy())
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("completion", ["poll", "notify", "blocking"])
+def test_alone_vs_mix(trace, alone, completion):
+    wl, tr = trace
+    n = len(tr.requests)
+    alone_res, alone_arenas, alone_pool = alone
     # in the mix: Poisson arrivals replayed in bursts into the serving loop
-    log("serving: mix")
+    log(f"serving: mix, completion by {completion}")
     ctx = new_ctx()
     try:
         dw, pool, reqs = _load(ctx, wl, tr)
-        srv = ctx.server_start(max_inflight=256, pool_bytes=4 * MiB, max_batch=64, streams=3)
+        srv = ctx.server_start(max_inflight=256, pool_bytes=4 * MiB, max_batch=64, streams=3,
+                               completion=completion)
         comps = []
         try:
             t0 = time.monotonic_ns()
@@ -124,6 +133,10 @@ def test_server_refuses_misuse(trace):
     try:
         with pytest.raises(dv.DevirtError):
             ctx.server_start(max_inflight=0)
+        import ctypes
+        bad = dv.devirt.ServerCfg(16, MiB, 0, 2, 3)  # no such completion mode
+        h = ctypes.c_void_p()
+        assert dv.lib().devirt_server_start(ctx._h, ctypes.byref(bad), ctypes.byref(h)) == -22
         srv = ctx.server_start(max_inflight=16, pool_bytes=MiB, streams=2)
         try:
             with pytest.raises(dv.DevirtError):   # the server owns the context
