@@ -18,12 +18,18 @@
  *     can be re-executed (section 6.6), so a copy stops at its first faulting
  *     page and reports how many bytes it moved.
  *
- * The page-table format is x86-64 (4-level, and 5-level with 57-bit linear
- * addresses), which replaces the paper's 32-bit PAE host (section 6.2).
+ * Page-table formats: x86-64 4-level and 5-level (48- and 57-bit linear
+ * addresses), and the paper's own 32-bit PAE format (section 6.2; levels =
+ * 3): CR3 bits 31:5 locate a 4-entry page-directory-pointer table indexed by
+ * address bits 31:30, whose entries hold no permission or accessed bits;
+ * below it the page directory and page table are the x86-64 ones.
  * Every point the paper leaves open follows the readings listed with the
  * design notes; the ones that shape this code are:
- *   - entry address bits are 51:12; bits 62:52, XD, G, PWT, PCD, PAT, the
- *     available bits and CR3's low 12 bits are ignored;
+ *   - entry address bits are 51:12; XD, G, PWT, PCD, PAT and the available
+ *     bits are ignored; bits 62:52 are ignored with 4/5 levels and reserved
+ *     in PAE entries; CR3's low 12 bits are ignored (PAE: its low 5);
+ *   - a PAE page-directory-pointer entry has bits 2:1, 8:5 and 63:52
+ *     reserved, and is never given an accessed bit;
  *   - PS set in a level-4 or level-5 entry is reserved; a 2 MiB / 1 GiB leaf
  *     with any of bits [shift-1:13] set is reserved;
  *   - user-mode access: U/S must be 1 at every level, and R/W at every level
@@ -33,8 +39,9 @@
  *   - A (bit 5) is OR-ed into every entry of the walk of each page copied,
  *     and D (bit 6) into the leaf when the copy writes the guest; a walk that
  *     faults changes nothing;
- *   - the whole range must be user-canonical and must not wrap, else nothing
- *     happens; a zero-length copy does nothing and succeeds.
+ *   - the whole range must be user-canonical (below 2^47, 2^56 with 5
+ *     levels, 2^32 with PAE) and must not wrap, else nothing happens; a
+ *     zero-length copy does nothing and succeeds.
  *
  * Memory model: each VM owns one byte arena (host memory standing in for
  * the guest's RAM); a memslot maps [gpa, gpa+bytes) to [arena_off, ...).
@@ -199,13 +206,42 @@ typedef struct {
 
 /* Software walk of the guest page tables for one linear address
  * (section 4.2).  Precondition: the address is user-canonical. */
+#define ORC_PAE_PDPTE_RSVD 0xFFF00000000001E6ull   /* bits 63:52, 8:5, 2:1 */
+#define ORC_PAE_RSVD 0x7FF0000000000000ull         /* bits 62:52 of a PAE PDE/PTE */
+
 static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write, walk_t *w) {
     const orc_vm *v = &s->vms[p->vm];
     uint64_t table = p->cr3 & ORC_ADDR_MASK;
     int user_ok = 1, write_ok = 1;
     uint64_t frame = 0;
+    int top = (int)p->levels;
+    const int pae = p->levels == 3;
     memset(w, 0, sizeof(*w));
-    for (int lvl = (int)p->levels; lvl >= 1; lvl--) {
+    if (pae) {
+        /* the 4-entry table at CR3 bits 31:5; its entry is not part of the
+         * accessed-bit path and grants every permission */
+        uint64_t pdpt = p->cr3 & 0xFFFFFFE0ull;
+        uint64_t thpa;
+        if (!slot_lookup(v, pdpt, &thpa)) {
+            w->code = ORC_NO_MEMSLOT;
+            w->level = 3;
+            return;
+        }
+        uint64_t e = load64(v->arena + thpa + 8 * ((gva >> 30) & 3));
+        if (!(e & ORC_P)) {
+            w->code = ORC_NOT_PRESENT;
+            w->level = 3;
+            return;
+        }
+        if (e & ORC_PAE_PDPTE_RSVD) {
+            w->code = ORC_RESERVED;
+            w->level = 3;
+            return;
+        }
+        table = e & ORC_ADDR_MASK;
+        top = 2;
+    }
+    for (int lvl = top; lvl >= 1; lvl--) {
         uint32_t shift = 12 + 9 * (uint32_t)(lvl - 1);
         uint64_t idx = (gva >> shift) & 511;
         uint64_t thpa;
@@ -219,6 +255,11 @@ static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write,
         w->path[w->npath++] = eoff;
         if (!(e & ORC_P)) {
             w->code = ORC_NOT_PRESENT;
+            w->level = (uint32_t)lvl;
+            return;
+        }
+        if (pae && (e & ORC_PAE_RSVD)) {
+            w->code = ORC_RESERVED;
             w->level = (uint32_t)lvl;
             return;
         }
@@ -282,7 +323,9 @@ static void set_ad(orc_state *s, const orc_proc *p, const walk_t *w, int write) 
     }
 }
 
-static uint64_t user_limit(uint32_t levels) { return levels == 5 ? (1ull << 56) : (1ull << 47); }
+static uint64_t user_limit(uint32_t levels) {
+    return levels == 5 ? (1ull << 56) : levels == 3 ? (1ull << 32) : (1ull << 47);
+}
 
 /* ------------------------------------------------------------ translate -- */
 #define ORC_XLAT_WRITE 1u

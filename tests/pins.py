@@ -182,7 +182,7 @@ def check_roundtrip(wl, lib_path=None, per_proc=20000, seed=5):
                 np.any(x["level"][npres] != p.leaf_level[sel][npres]):
             fails.append(f"asid {p.asid}: not-present leaves not reported at their own level")
         # unmapped addresses: random user addresses that no leaf covers
-        lim = 1 << (47 if p.levels == 4 else 56)
+        lim = 1 << {3: 32, 4: 47, 5: 56}[p.levels]
         cand = rng.integers(0, lim, 4000, dtype=np.uint64)
         # plus addresses just past each VMA (share upper tables with mapped ones)
         cand = np.concatenate([cand, p.vmas[:, 0] + p.vmas[:, 1], p.vmas[:, 0] - np.uint64(4096)])
@@ -247,7 +247,9 @@ def check_bruteforce(wl, lib_path=None, max_requests=None):
 def identity_world(n_pages=96, levels=4, seed=9):
     """Identity-mapped user pages [base, base + n_pages*4K) with one memslot at
     arena offset 0, built by a tiny recursive encoder independent of the
-    generator (tables allocated top-down from the end of guest memory)."""
+    generator (tables allocated top-down from the end of guest memory).
+    levels 3 is PAE: the root is a 4-entry table of P-only entries at byte
+    0x40 of its frame, indexed by address bits 31:30."""
     rng = np.random.default_rng(seed)
     base = 0x40_0000  # 4 MiB
     mem = 16 << 20
@@ -263,6 +265,8 @@ def identity_world(n_pages=96, levels=4, seed=9):
         return f
 
     root = alloc()
+    if levels == 3:
+        root += 0x40  # the PAE root table is 32-byte aligned, not page aligned
 
     def put(table, idx, val):
         arena[table + 8 * idx: table + 8 * idx + 8] = np.frombuffer(int(val).to_bytes(8, "little"), np.uint8)
@@ -276,12 +280,14 @@ def identity_world(n_pages=96, levels=4, seed=9):
         table = root
         for lvl in range(levels, 1, -1):
             idx = (va >> (12 + 9 * (lvl - 1))) & 511
+            if levels == 3 and lvl == 3:
+                idx = (va >> 30) & 3
             e = get(table, idx)
             if e & 1:
                 table = e & 0x000FFFFFFFFFF000
             else:
                 t = alloc()
-                put(table, idx, t | 0x7)
+                put(table, idx, t | (0x1 if (levels == 3 and lvl == 3) else 0x7))
                 table = t
         put(table, (va >> 12) & 511, (va | 0x7) if present[k] else 0)
     slots = np.zeros(1, SLOT_DTYPE)
@@ -291,7 +297,7 @@ def identity_world(n_pages=96, levels=4, seed=9):
 
 def check_identity(lib_path=None, seed=9):
     fails = []
-    for levels in (4, 5):
+    for levels in (3, 4, 5):
         arena, slots, root, base, present = identity_world(levels=levels, seed=seed)
         pool = np.zeros(1 << 20, np.uint8)
         gen.fill_bytes(pool, seed, 2)
@@ -358,7 +364,8 @@ def expected_ad(wl, reqs, res):
 
         lv = p.leaf_level[li]
         orbits(p.leaf_table_gfn[li], p.leaf_index[li], A | (D if int(r["dir"]) == 1 else np.uint64(0)))
-        for L in range(2, p.levels + 1):
+        # A on every upper entry of the path; a PAE root entry has no A bit
+        for L in range(2, (2 if p.levels == 3 else p.levels) + 1):
             m = lv < L
             if not m.any():
                 continue
@@ -486,4 +493,8 @@ def small_specs():
                             n_requests=200, len_hi=100000, seed=15),
         "prot": gen.spec("C2", mem_bytes=16 * MiB, n_requests=300, p_readonly=0.1, p_supervisor=0.05,
                          p_upper_np=0.05, len_hi=20000, seed=16),
+        # the paper's 32-bit PAE platform: 4 KiB and 2 MiB pages under a 4-entry root table
+        "pae": gen.spec("C2", levels=3, mem_bytes=64 * MiB, n_requests=400, n_slots=6, len_hi=40000, seed=17),
+        "pae_prot": gen.spec("C2", levels=3, mem_bytes=16 * MiB, n_requests=300, p_readonly=0.1,
+                             p_supervisor=0.05, p_upper_np=0.1, len_hi=20000, seed=18),
     }

@@ -36,8 +36,18 @@ MUTANTS = {
     "slot_end_inclusive": ("if (gpa >= sl->gpa && gpa - sl->gpa < sl->bytes) {",
                            "if (gpa >= sl->gpa && gpa - sl->gpa <= sl->bytes) {"),
     "slot_offset_dropped": ("*hpa = sl->arena_off + (gpa - sl->gpa);", "*hpa = sl->arena_off + gpa;"),
-    "canonical_limit_48": ("return levels == 5 ? (1ull << 56) : (1ull << 47);",
-                           "return levels == 5 ? (1ull << 56) : (1ull << 48);"),
+    "canonical_limit_48": ("levels == 3 ? (1ull << 32) : (1ull << 47);", "levels == 3 ? (1ull << 32) : (1ull << 48);"),
+    # PAE (the paper's 32-bit platform)
+    "pae_root_page_aligned": ("uint64_t pdpt = p->cr3 & 0xFFFFFFE0ull;", "uint64_t pdpt = p->cr3 & 0xFFFFF000ull;"),
+    "pae_root_index_bits": ("8 * ((gva >> 30) & 3)", "8 * ((gva >> 29) & 3)"),
+    "pae_root_reserved_unchecked": ("if (e & ORC_PAE_PDPTE_RSVD) {", "if (0) {"),
+    "pae_high_bits_ignored": ("if (pae && (e & ORC_PAE_RSVD)) {", "if (0) {"),
+    "pae_root_gets_accessed": ("        table = e & ORC_ADDR_MASK;\n        top = 2;",
+                               "        w->path[w->npath++] = thpa + 8 * ((gva >> 30) & 3);\n"
+                               "        table = e & ORC_ADDR_MASK;\n        top = 2;"),
+    "pae_root_user_bit": ("        table = e & ORC_ADDR_MASK;\n        top = 2;",
+                          "        user_ok &= (int)((e >> 2) & 1);\n        table = e & ORC_ADDR_MASK;\n        top = 2;"),
+    "pae_limit_47": ("levels == 3 ? (1ull << 32)", "levels == 3 ? (1ull << 47)"),
     "copy_direction_swapped": ("        if (to_guest)\n            memcpy(g, h, hi - lo);",
                                "        if (!to_guest)\n            memcpy(g, h, hi - lo);"),
     "ad_before_fault_check": ("        if (w.code != ORC_OK) {\n            res->bytes_done",
@@ -77,6 +87,8 @@ def test_pins_catch_mutant(tmp_path, name):
         lambda: pins.check_roundtrip(_small("lvl5_1g"), lib, per_proc=3000),
         lambda: pins.check_bruteforce(_small("prot"), lib, max_requests=60),
         lambda: pins.check_ad_closed_form(_small("c1"), lib),
+        lambda: pins.check_roundtrip(_small("pae"), lib, per_proc=3000),
+        lambda: pins.check_ad_closed_form(_small("pae"), lib),
     ]
     for c in checks:
         if c():

@@ -19,12 +19,13 @@ def test_golden_walks_ad_and_copies():
     assert pins.check_golden() == []
 
 
-@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g"])
+@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "pae"])
 def test_encode_decode_roundtrip(name):
     assert pins.check_roundtrip(wl(name)) == []
 
 
-@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "prot"])
+@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "prot", "pae",
+                                  "pae_prot"])
 def test_per_byte_bruteforce(name):
     assert pins.check_bruteforce(wl(name), max_requests=120) == []
 
@@ -33,17 +34,17 @@ def test_identity_tables_equal_memcpy():
     assert pins.check_identity() == []
 
 
-@pytest.mark.parametrize("name", ["c1", "mix2m", "multi_vm", "lvl5", "prot"])
+@pytest.mark.parametrize("name", ["c1", "mix2m", "multi_vm", "lvl5", "prot", "pae", "pae_prot"])
 def test_ad_closed_form(name):
     assert pins.check_ad_closed_form(wl(name)) == []
 
 
-@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5"])
+@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "pae"])
 def test_invariants(name):
     assert pins.check_invariants(wl(name)) == []
 
 
-@pytest.mark.parametrize("name", ["c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g"])
+@pytest.mark.parametrize("name", ["c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "pae"])
 def test_generated_batches_are_conflict_free(name):
     from oracle import Oracle
     w = wl(name)
@@ -72,7 +73,7 @@ def test_conflict_checker_finds_planted_overlap():
         assert o.check_conflicts(r, [len(r)]) is not None
 
 
-@pytest.mark.parametrize("name", ["c1", "multi_vm", "lvl5_1g", "prot"])
+@pytest.mark.parametrize("name", ["c1", "multi_vm", "lvl5_1g", "prot", "pae_prot"])
 def test_results_only_mode_matches_full_batch(name):
     """Results do not depend on bytes or A/D: the results-only walk equals the full batch."""
     import numpy as np

@@ -63,6 +63,13 @@ _IGN_PTE = np.uint64(0x0F98) | _HI_IGN    # PWT PCD PAT G AVL(11:9)
 _IGN_LARGE = np.uint64(0x1F18) | _HI_IGN  # PWT PCD G AVL PAT(12)
 _IGN_TABLE = np.uint64(0x0F18) | _HI_IGN  # PWT PCD G AVL
 _ADDR = np.uint64(0x000FFFFFFFFFF000)
+# PAE (levels 3): bits 62:52 are reserved in every entry, XD (63) is accepted;
+# a page-directory-pointer entry has only P, PWT, PCD and the AVL bits 11:9
+_XD = np.uint64(1 << 63)
+_IGN_PTE_PAE = np.uint64(0x0F98) | _XD
+_IGN_LARGE_PAE = np.uint64(0x1F18) | _XD
+_IGN_TABLE_PAE = np.uint64(0x0F18) | _XD
+_IGN_PDPTE = np.uint64(0x0E18)
 
 POOL_KEY = 0xFFFF
 
@@ -346,11 +353,21 @@ def _layout_process(rng, sp: Spec, n1: int, n2: int, n4: int):
         groups.append(np.zeros(0, np.int64))
     g1 = rng.integers(0, k, n1) if n1 else np.zeros(0, np.int64)
     sizes = np.array([int((g1 == j).sum()) * GiB + len(groups[j]) * 2 * MiB for j in range(k)], np.int64)
-    span = int(max(1, -(-int(sizes.max()) // GiB)))  # in GiB
-    limit = 1 << (47 if sp.levels == 4 else 56)
-    ncell = (limit - 2 * GiB) // ((span + 1) * GiB)
-    cells = rng.choice(ncell, k, replace=False)
-    bases = np.uint64(GiB) + cells.astype(np.uint64) * np.uint64((span + 1) * GiB)
+    if sp.levels == 3:
+        # PAE: 32-bit addresses; VMAs in [4 MiB, 3 GiB), cells of whole 2 MiB units
+        if n1:
+            raise ValueError("PAE paging has no 1 GiB pages")
+        unit = 2 * MiB
+        span = int(max(1, -(-int(sizes.max()) // unit)))
+        ncell = (3 * GiB - 4 * MiB) // ((span + 1) * unit)
+        cells = rng.choice(ncell, k, replace=False)
+        bases = np.uint64(4 * MiB) + cells.astype(np.uint64) * np.uint64((span + 1) * unit)
+    else:
+        span = int(max(1, -(-int(sizes.max()) // GiB)))  # in GiB
+        limit = 1 << (47 if sp.levels == 4 else 56)
+        ncell = (limit - 2 * GiB) // ((span + 1) * GiB)
+        cells = rng.choice(ncell, k, replace=False)
+        bases = np.uint64(GiB) + cells.astype(np.uint64) * np.uint64((span + 1) * GiB)
     va_l, lvl_l = [], []
     blk4_idx = np.cumsum(kinds == 1) - 1
     vmas = []
@@ -455,23 +472,34 @@ def make_workload(sp: Spec, requests: bool = True) -> Workload:
                 gfns[L] = ptf[o:o + len(per[L])]
                 o += len(per[L])
             data = {L: np.zeros((len(per[L]), 512), np.uint64) for L in per}
+            pae = sp.levels == 3
+            # PAE: the 4-entry page-directory-pointer table sits at a random
+            # 32-byte slot of its frame, which CR3 bits 11:5 name
+            pdpt_slot = int(rng.integers(0, 128)) if pae else 0
             # upper-level entries: child table at level L-1 referenced from level L
             for L in range(2, sp.levels + 1):
                 child = per[L - 1]
                 if len(child) == 0:
                     continue
                 parent_pos = np.searchsorted(per[L], child >> np.uint64(9))
-                e = (gfns[L - 1] << np.uint64(12)) | np.uint64(_P | _RW | _US) | (_rand_u64(rng, len(child)) & _IGN_TABLE)
+                if pae and L == 3:
+                    e = (gfns[L - 1] << np.uint64(12)) | np.uint64(_P) | (_rand_u64(rng, len(child)) & _IGN_PDPTE)
+                else:
+                    ign = _IGN_TABLE_PAE if pae else _IGN_TABLE
+                    e = (gfns[L - 1] << np.uint64(12)) | np.uint64(_P | _RW | _US) | (_rand_u64(rng, len(child)) & ign)
                 if sp.p_upper_np > 0:
                     np_m = rng.random(len(child)) < sp.p_upper_np
                     e = np.where(np_m, _rand_u64(rng, len(child)) & ~np.uint64(1), e)
-                data[L][parent_pos, (child & np.uint64(511)).astype(np.int64)] = e
+                slot = (child & np.uint64(511)).astype(np.int64)
+                if pae and L == 3:
+                    slot = slot + 4 * pdpt_slot
+                data[L][parent_pos, slot] = e
             # leaves
             n = len(va)
             present = rng.random(n) >= sp.p_np
             rnd = _rand_u64(rng, n)
-            ent = np.where(lvl == 1, (frames[p] | np.uint64(_P | _RW | _US)) | (rnd & _IGN_PTE),
-                           (frames[p] | np.uint64(_P | _RW | _US | _PS)) | (rnd & _IGN_LARGE))
+            ent = np.where(lvl == 1, (frames[p] | np.uint64(_P | _RW | _US)) | (rnd & (_IGN_PTE_PAE if pae else _IGN_PTE)),
+                           (frames[p] | np.uint64(_P | _RW | _US | _PS)) | (rnd & (_IGN_LARGE_PAE if pae else _IGN_LARGE)))
             if sp.p_readonly > 0:
                 ro = rng.random(n) < sp.p_readonly
                 ent = np.where(ro, ent & ~np.uint64(_RW), ent)
@@ -495,7 +523,10 @@ def make_workload(sp: Spec, requests: bool = True) -> Workload:
                 pt_gfn_all.append(gfns[L])
                 pt_data_all.append(data[L])
             root = int(gfns[sp.levels][0])
-            cr3 = (root << 12) | int(rng.integers(0, 4096))   # low 12 bits ignored by the walk
+            if pae:
+                cr3 = (root << 12) | (pdpt_slot << 5) | int(rng.integers(0, 32))  # bits 4:0 ignored
+            else:
+                cr3 = (root << 12) | int(rng.integers(0, 4096))   # low 12 bits ignored by the walk
             procs.append(ProcTruth(asid, vm, sp.levels, cr3, va, lvl, frames[p], present, ent, t_gfn, t_idx,
                                    {L: (per[L], gfns[L]) for L in per}, vmas))
         vms.append(VMImage(vm, sp.mem_bytes, slots, arena_bytes,
