@@ -149,9 +149,13 @@ int devirt_vm_read(devirt_ctx *ctx, uint32_t vm, uint64_t off, void *dst, uint64
 int devirt_memslot_set(devirt_ctx *ctx, uint32_t vm, uint32_t slot, uint64_t gpa, uint64_t bytes,
                        uint64_t arena_off);
 
-/* Register a guest process by its page-table root (CR3; low 12 bits
- * ignored) and paging depth (4 or 5), captured once as the backend does when
- * a thread first makes a call (section 6.3).  Returns ids 0, 1, 2, ... */
+/* Register a guest process by its page-table root (CR3) and paging mode,
+ * captured once as the backend does when a thread first makes a call
+ * (section 6.3).  levels 4 or 5: x86-64 4-level (48-bit) or 5-level (57-bit)
+ * paging, CR3 low 12 bits ignored.  levels 3: 32-bit PAE paging, the paper's
+ * own platform (section 6.2): CR3 bits 31:5 locate a 4-entry root table,
+ * addresses stop at 2^32.  -EINVAL for any other depth.
+ * Returns ids 0, 1, 2, ... */
 int devirt_process_create(devirt_ctx *ctx, uint32_t vm, uint64_t cr3_gpa, uint32_t levels, uint32_t *asid);
 
 /* ---------------------------------------------------------------- data path */

@@ -10,6 +10,10 @@ namespace dv {
 // x86-64 entry bits (section 4.2 walks the guest's own tables).
 constexpr uint64_t kAddrMask = 0x000FFFFFFFFFF000ull;  // address bits 51:12
 constexpr uint64_t kP = 1ull, kRW = 2ull, kUS = 4ull, kA = 0x20ull, kD = 0x40ull, kPS = 0x80ull;
+// PAE (section 6.2): reserved bits of a root (page-directory-pointer) entry,
+// bits 63:52, 8:5 and 2:1, and of a PDE or PTE, bits 62:52.
+constexpr uint64_t kPaeRootRsvd = 0xFFF00000000001E6ull;
+constexpr uint64_t kPaeRsvd = 0x7FF0000000000000ull;
 
 // A memslot as the device sees it: sorted by gpa, end = gpa + bytes.
 struct DSlot {

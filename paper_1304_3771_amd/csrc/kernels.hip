@@ -191,11 +191,41 @@ __device__ __forceinline__ void walk_upper_t(const DVm &v, uint64_t cr3, uint64_
     c.info = DEVIRT_OK | (u << 9) | (w << 10) | ((LEVELS - 2) << 11) | (abits << 13);
 }
 
+// PAE, the paper's 32-bit platform (section 6.2): one read of the 4-entry
+// root table at CR3 bits 31:5, indexed by address bits 31:30.  Its entries
+// grant every permission and take no accessed bit, so the cached path is
+// empty; bits 2:1, 8:5 and 63:52 are reserved.
+__device__ __forceinline__ void walk_upper_pae(const DVm &v, uint64_t cr3, uint64_t gva, CEnt &c) {
+    c.path[0] = c.path[1] = c.path[2] = 0;
+    uint64_t th;
+    if (!slot_lookup(v, cr3 & 0xFFFFFFE0ull, th)) {
+        c.info = DEVIRT_NO_MEMSLOT | (3u << 4);
+        return;
+    }
+    const uint64_t e = load_entry(v.arena, th + 8 * ((gva >> 30) & 3));
+    if (!(e & kP)) {
+        c.info = DEVIRT_NOT_PRESENT | (3u << 4);
+        return;
+    }
+    if (e & kPaeRootRsvd) {
+        c.info = DEVIRT_RESERVED | (3u << 4);
+        return;
+    }
+    c.base = e & kAddrMask;
+    c.info = DEVIRT_OK | (1u << 9) | (1u << 10);  // u = w = 1, no path entries
+}
+
 __device__ __forceinline__ void walk_upper(const DVm &v, uint64_t cr3, uint32_t levels, uint64_t gva, CEnt &c) {
     if (levels == 5)
         walk_upper_t<5>(v, cr3, gva, c);
+    else if (levels == 3)
+        walk_upper_pae(v, cr3, gva, c);
     else
         walk_upper_t<4>(v, cr3, gva, c);
+}
+
+__device__ __forceinline__ uint64_t user_limit(uint32_t levels) {
+    return levels == 5 ? (1ull << 56) : levels == 3 ? (1ull << 32) : (1ull << 47);
 }
 
 __device__ __forceinline__ uint32_t cache_slot(uint64_t key) {
@@ -373,7 +403,7 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
             levels = p.levels;
             cr3 = p.cr3;
             if (len != 0) {
-                uint64_t lim = levels == 5 ? (1ull << 56) : (1ull << 47);
+                uint64_t lim = user_limit(levels);
                 if (gva >= lim || (uint64_t)len > lim - gva)
                     code0 = DEVIRT_NONCANONICAL;
                 else
@@ -474,6 +504,9 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                         if (!(e & kP)) {
                             rcode = DEVIRT_NOT_PRESENT;
                             rlevel = 2;
+                        } else if (j_levels == 3 && (e & kPaeRsvd)) {
+                            rcode = DEVIRT_RESERVED;
+                            rlevel = 2;
                         } else {
                             ru &= (uint32_t)(e >> 2) & 1u;
                             rw &= (uint32_t)(e >> 1) & 1u;
@@ -523,6 +556,9 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                     leaf_e = load_entry(vmv.arena, leaf_off);
                     if (!(leaf_e & kP)) {
                         code = DEVIRT_NOT_PRESENT;
+                        level = 1;
+                    } else if (j_levels == 3 && (leaf_e & kPaeRsvd)) {
+                        code = DEVIRT_RESERVED;
                         level = 1;
                     } else {
                         u &= (uint32_t)(leaf_e >> 2) & 1u;
@@ -906,7 +942,7 @@ __global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint
         p = gp<const DV_GLOBAL DProc>(v.procs)[asid];
         vmv = gp<const DV_GLOBAL DVm>(v.vms)[p.vm];
     }
-    const uint64_t lim = p.levels == 5 ? (1ull << 56) : (1ull << 47);
+    const uint64_t lim = user_limit(p.levels);
     const bool write = (flags & DEVIRT_XLAT_WRITE) != 0;
     const bool set_ad = (flags & DEVIRT_XLAT_SET_AD) != 0;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -960,6 +996,9 @@ __global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint
                         if (!(e2 & kP)) {
                             code = DEVIRT_NOT_PRESENT;
                             level = 2;
+                        } else if (p.levels == 3 && (e2 & kPaeRsvd)) {
+                            code = DEVIRT_RESERVED;
+                            level = 2;
                         } else {
                             u &= (uint32_t)(e2 >> 2) & 1u;
                             w &= (uint32_t)(e2 >> 1) & 1u;
@@ -982,6 +1021,9 @@ __global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint
                                     e1 = load_entry(vmv.arena, pte_off);
                                     if (!(e1 & kP)) {
                                         code = DEVIRT_NOT_PRESENT;
+                                        level = 1;
+                                    } else if (p.levels == 3 && (e1 & kPaeRsvd)) {
+                                        code = DEVIRT_RESERVED;
                                         level = 1;
                                     } else {
                                         u &= (uint32_t)(e1 >> 2) & 1u;

@@ -323,7 +323,7 @@ extern "C" int devirt_memslot_set(devirt_ctx *c, uint32_t vm, uint32_t slot, uin
 extern "C" int devirt_process_create(devirt_ctx *c, uint32_t vm, uint64_t cr3_gpa, uint32_t levels, uint32_t *asid) {
     if (!c || !asid) return dv_fail(-EINVAL, "NULL argument");
     if (vm >= c->vms.size()) return dv_fail(-ENOENT, "no VM %u", vm);
-    if (levels != 4 && levels != 5) return dv_fail(-EINVAL, "levels must be 4 or 5");
+    if (levels < 3 || levels > 5) return dv_fail(-EINVAL, "levels must be 3 (PAE), 4 or 5");
     if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
     if (c->procs.size() >= 0x7FFFFFFF) return dv_fail(-EINVAL, "too many processes");
     if (set_dev(c)) return -EIO;

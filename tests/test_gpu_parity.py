@@ -48,7 +48,7 @@ def _golden_ctx(world):
     return ctx, vm, o, arena, pool, dpool, dv
 
 
-@pytest.mark.parametrize("widx", [0, 1])
+@pytest.mark.parametrize("widx", [0, 1, 2, 3])  # 4-level, 5-level, PAE, PAE
 def test_golden_translate(widx):
     import torch
     world = pins.golden_worlds()[widx]
@@ -80,9 +80,10 @@ def test_golden_translate(widx):
         ctx.close()
 
 
-def test_golden_set_ad():
+@pytest.mark.parametrize("widx", [0, 2, 3])  # the worlds with an A/D expectation
+def test_golden_set_ad(widx):
     import torch
-    world = pins.golden_worlds()[0]
+    world = pins.golden_worlds()[widx]
     ad = world["ad_after_set_ad_write"]
     ctx, vm, o, arena, pool, dpool, dv = _golden_ctx(world)
     try:
@@ -101,10 +102,11 @@ def test_golden_set_ad():
         ctx.close()
 
 
+@pytest.mark.parametrize("widx", [0, 2, 3])  # the worlds with copies
 @pytest.mark.parametrize("path", ["plain", "batch"])
-def test_golden_copies(path):
+def test_golden_copies(path, widx):
     import torch
-    world = pins.golden_worlds()[0]
+    world = pins.golden_worlds()[widx]
     for c in world["copies"]:
         log(f"golden copy {path} {c['gva']} dir {c['dir']}")
         ctx, vm, o, arena, pool, dpool, dv = _golden_ctx(world)
@@ -135,7 +137,8 @@ def test_golden_copies(path):
 
 
 # ------------------------------------------------------------ batches
-@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "prot"])
+@pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "prot", "pae",
+                                  "pae_prot"])
 def test_batch_matches_oracle(name):
     w = wl(name)
     log(f"batch {name}: {w.n_requests} requests, {len(w.epoch_end)} epochs")
@@ -263,7 +266,7 @@ def test_translate_matches_oracle():
     import torch
     import paper_1304_3771_amd as dv
     from oracle import Oracle
-    for name in ("mix2m", "lvl5_1g", "prot", "multi_vm"):
+    for name in ("mix2m", "lvl5_1g", "prot", "multi_vm", "pae_prot"):
         w = wl(name)
         log(f"translate {name}")
         rng = np.random.default_rng(3)
