@@ -35,7 +35,16 @@ WORKLOADS = {
     "C1": "one guest, 64 MiB, 8192 4KiB pages, 10% not-present, 4 memslots, 256 requests uniform 8-4096B",
     "C3": "16 VMs x 4 processes, 2 GiB each, 80/20 4KiB/2MiB, 4e6 requests log-uniform 16B-4MiB",
     "C5": "64 VMs x 2 GiB, 5-level paging, 60/35/5 4KiB/2MiB/1GiB, 3% not-present, 1e7 requests 16B-1MiB",
+    "C2-PAE": "C2 under 32-bit PAE paging (4-entry root table, 32-bit addresses): one guest, 4 GiB, "
+              "70/30 4KiB/2MiB, 16 memslots, 5% not-present, 1e6 requests log-uniform 64B-64KiB",
 }
+
+
+def workload_spec(name):
+    from workload import gen
+    if name == "C2-PAE":
+        return gen.spec("C2", levels=3, seed=1006)
+    return gen.spec(name)
 
 
 def log(msg):
@@ -287,7 +296,7 @@ def main():
         return serving(args)
 
     t_gen = time.time()
-    sp = gen.spec(args.workload)
+    sp = workload_spec(args.workload)
     log(f"generating {args.workload}")
     wl = gen.make_workload(sp)
     n = wl.n_requests
@@ -447,7 +456,8 @@ def main():
     sel = rng.integers(0, len(p0.leaf_va), k_map)
     size = np.uint64(1) << (np.uint64(12) + np.uint64(9) * (p0.leaf_level[sel].astype(np.uint64) - np.uint64(1)))
     g = p0.leaf_va[sel] + rng.integers(0, 1 << 62, k_map, dtype=np.uint64) % size
-    g = np.concatenate([g, rng.integers(0, 1 << 47, args.xlat_n - k_map, dtype=np.uint64)])
+    user_limit = {3: 1 << 32, 4: 1 << 47, 5: 1 << 56}[p0.levels]
+    g = np.concatenate([g, rng.integers(0, user_limit, args.xlat_n - k_map, dtype=np.uint64)])
     rng.shuffle(g)
     dg = torch.from_numpy(g.view(np.int64)).cuda()
     xo = torch.empty(args.xlat_n * 24, dtype=torch.uint8, device="cuda")
