@@ -1,20 +1,21 @@
 // gfx950 kernels of the guest-memory translate-and-copy path.
 //
 // The operation (section 4.2 of the paper): a buffer at a guest virtual
-// address is translated page by page -- a software walk of the guest's
-// x86-64 page tables to a guest-physical address, then the VM's memslots to
-// the host address (KVM style) -- and its bytes are copied between the guest
-// memory image ("arena") and a host buffer.  A fault ends the operation with
-// everything before the faulting byte copied, so the operation can be
+// address is translated page by page -- a software walk of the guest's page
+// tables (x86-64 4- or 5-level, or the 32-bit PAE format of the paper's
+// prototype, section 6.2) to a guest-physical address, then the VM's memslots
+// to the host address (KVM style) -- and its bytes are copied between the
+// guest memory image ("arena") and a host buffer.  A fault ends the operation
+// with everything before the faulting byte copied, so the operation can be
 // re-executed (section 6.6).
 //
 // Work decomposition (wave64 throughout):
-//   translate  one wavefront owns a group of up to 64 consecutive requests.
-//              A wave prefix sum over their page counts flattens the group's
-//              pages; each pass gives every lane one page.  Lanes that start a
-//              2 MiB region ("heads") resolve the upper levels -- levels 5..3
-//              through a per-wavefront LDS cache of 1 GiB regions, level 2 by
-//              a load -- and hand the result to the rest of the region with
+//   translate  one wavefront owns a group of consecutive requests.  A wave
+//              prefix sum over their page counts flattens the group's pages;
+//              each pass gives every lane one page.  Lanes that start a 2 MiB
+//              region ("heads") resolve the upper levels -- the levels above
+//              2 through a per-wavefront LDS cache of 1 GiB regions, level 2
+//              by a load -- and hand the result to the rest of the region with
 //              cross-lane shuffles; every lane then reads its own leaf entry,
 //              so neighbouring lanes read neighbouring PTEs in one cache line.
 //              Because a group's pages are walked in order, the first fault
@@ -22,11 +23,12 @@
 //              side effect: A/D bits are OR-ed only into entries on the paths
 //              of pages that will be copied.  Copy segments (runs of pages
 //              whose guest side is contiguous in the arena) are appended to a
-//              queue with one wave-aggregated atomic per pass.
-//   copy       every wavefront takes segments and moves them with 16-byte
-//              aligned stores; the source misalignment is absorbed with
-//              cross-lane shuffles and byte funnel shifts, never with a
-//              read-modify-write of bytes outside the segment.
+//              long or a short queue, each split into parts with a counter of
+//              their own, with one wave-aggregated atomic per pass and queue.
+//   copy       a wavefront takes each long segment, a 16-lane quarter each
+//              short one; stores are 16-byte aligned, the source misalignment
+//              is absorbed with one neighbour dword and a byte funnel shift,
+//              never with a read-modify-write of bytes outside the segment.
 //   faults     the ordered fault list is a tile count, a single-workgroup
 //              scan and a ballot/mbcnt scatter.
 #include "dv_internal.h"
