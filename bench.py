@@ -211,7 +211,8 @@ def serving(args):
         log(f"  driver: {polls} iterations, {t_sub / 1e9:.3f} s in submit, {t_poll / 1e9:.3f} s in poll")
         log(f"  server thread over {span:.2f} s: inbox {sst['ns_inbox'] / 1e9:.3f} s, completions "
             f"{sst['ns_complete'] / 1e9:.3f} s, admission {sst['ns_admit'] / 1e9:.3f} s, launches "
-            f"{sst['ns_launch'] / 1e9:.3f} s ({sst['launches']} launches, {sst['loops']} loops)")
+            f"{sst['ns_launch'] / 1e9:.3f} s ({sst['launches']} launches, {sst['direct_launches']} direct, "
+            f"{sst['loops']} loops)")
         # the plain per-request path at the same arrival rate (bounded sample)
         m = min(n_ops, args.serve_plain_ops)
         if m == 0:

@@ -322,6 +322,8 @@ typedef struct {
                               completions                                          */
     uint64_t ns_admit;     /* admission and writing descriptors                     */
     uint64_t ns_launch;    /* enqueueing the kernels of a batch                     */
+    uint64_t direct_launches; /* small batches run as one kernel that translates and
+                                 copies (at most 64 operations, 256 KiB, 64 KiB each) */
 } devirt_server_stats;
 /* Read the counters (any thread; values may be a few iterations old). */
 int devirt_server_get_stats(devirt_server *srv, devirt_server_stats *out);

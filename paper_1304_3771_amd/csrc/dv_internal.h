@@ -121,7 +121,7 @@ struct DBatch {
 // ---- launchers (kernels.hip) ------------------------------------------------
 hipError_t launch_reset(hipStream_t s, DBatch b, uint32_t n_epochs);
 hipError_t launch_translate_groups(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0,
-                                   uint64_t r1, uint32_t epoch);
+                                   uint64_t r1, uint32_t epoch, int direct);
 hipError_t launch_copy(hipStream_t s, int grid, int block, DBatch b, uint32_t epoch);
 hipError_t launch_plain(hipStream_t s, DView v, DBatch b, devirt_request req, int inline_copy);
 hipError_t launch_xlat(hipStream_t s, int grid, int block, DView v, uint32_t asid, const uint64_t *gva,

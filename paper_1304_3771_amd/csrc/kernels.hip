@@ -812,8 +812,10 @@ __device__ __forceinline__ void flush_counters(DCounters *c, const GroupOut &st)
     }
 }
 
+// direct != 0: the translating wavefronts copy their runs themselves and
+// nothing is queued (one launch for a small batch).
 __global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uint64_t r0, uint64_t r1,
-                                                           uint32_t epoch) {
+                                                           uint32_t epoch, int direct) {
     extern __shared__ uint8_t smem[];
     const int wave = threadIdx.x >> 6;
     CEnt *cache = (CEnt *)smem + wave * kCacheWays;
@@ -829,15 +831,18 @@ __global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uin
     // Each wavefront takes group (its global index) first, without an atomic;
     // further groups come from the cursor, numbered after those first ones.
     // The next claim is issued before the current group is translated, so its
-    // round trip overlaps the group's own loads.
+    // round trip overlaps the group's own loads.  When every group is some
+    // wavefront's first, no claim is made at all (and the cursor is not read).
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const bool claim = ngroups > nwaves;
     uint64_t gi = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (uint64_t)wave;
     while (gi < ngroups) {
         uint32_t g = 0;
-        if (lane_id() == 0) g = atomicAdd(&b.ctr[epoch].group_cursor, 1u);
+        if (claim && lane_id() == 0) g = atomicAdd(&b.ctr[epoch].group_cursor, 1u);
         const uint64_t gs = r0 + gi * G;
         const uint32_t gn = (uint32_t)((r1 - gs) < G ? (r1 - gs) : G);
-        process_group<false>(v, b, gs, gn, dummy, epoch, cache, owner, false, b.ctr, st);
+        process_group<false>(v, b, gs, gn, dummy, epoch, cache, owner, direct != 0, b.ctr, st);
+        if (!claim) break;
         gi = nwaves + uniform_u32(shfl32(g, 0));
     }
     flush_counters(b.counters, st);
@@ -1193,8 +1198,8 @@ hipError_t launch_reset(hipStream_t s, DBatch b, uint32_t n_epochs) {
 }
 
 hipError_t launch_translate_groups(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0, uint64_t r1,
-                                   uint32_t epoch) {
-    hipLaunchKernelGGL(k_translate_groups, dim3(grid), dim3(block), wave_lds(block), s, v, b, r0, r1, epoch);
+                                   uint32_t epoch, int direct) {
+    hipLaunchKernelGGL(k_translate_groups, dim3(grid), dim3(block), wave_lds(block), s, v, b, r0, r1, epoch, direct);
     return hipGetLastError();
 }
 

@@ -598,6 +598,20 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
     b.t_done = a.t_done;
     const DView v = view_of(c);
     const size_t ne = a.epochs.size();
+    if (a.direct) {
+        // one epoch, every group the first of some wavefront (no claims, so no
+        // counter reset), copies by the translating wavefronts: one launch
+        b.group = 1;
+        HIPCHK(launch_translate_groups(s, grid_for(c, a.n, c->cfg.xlat_wg, 1u << 20), (int)c->cfg.xlat_wg, v, b, 0,
+                                       a.n, 0, 1));
+        if (a.faults || a.n_faults) {
+            uint64_t tiles = (a.n + kFaultTile - 1) / kFaultTile;
+            HIPCHK(launch_fault_count(s, a.res, a.n, w->tiles));
+            HIPCHK(launch_fault_scan(s, w->tiles, tiles, a.n_faults));
+            if (a.faults) HIPCHK(launch_fault_scatter(s, a.res, a.n, w->tiles, a.faults));
+        }
+        return 0;
+    }
     HIPCHK(launch_reset(s, b, (uint32_t)ne));
     const bool overlap = ne > 1 && c->cfg.overlap;
     hipStream_t side = s;
@@ -634,7 +648,7 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
             ProfEv *pe;
             if ((rc = prof_begin(c, side, 1, &pe))) return rc;
             HIPCHK(launch_translate_groups(side, grid_for(c, groups, c->cfg.xlat_wg, c->cfg.xlat_wgs_per_cu),
-                                           (int)c->cfg.xlat_wg, v, be, r0, r1, (uint32_t)e));
+                                           (int)c->cfg.xlat_wg, v, be, r0, r1, (uint32_t)e, 0));
             if ((rc = prof_end(c, side, pe))) return rc;
             if (overlap) {
                 HIPCHK(hipEventRecord(t_done, side));
@@ -676,9 +690,12 @@ extern "C" int devirt_submit_batch(devirt_ctx *c, const devirt_request *reqs, ui
     return dv_submit(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, t_done, (hipStream_t)stream, true);
 }
 
+// Batches of at most this many requests may run as one direct launch.
+static constexpr uint64_t kDirectMaxReqs = 64;
+
 int dv_submit(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint64_t *epoch_end, uint32_t n_epochs,
               devirt_result *res, devirt_fault *faults, uint64_t *n_faults, uint64_t *t_done, hipStream_t s,
-              bool allow_graph) {
+              bool allow_graph, bool allow_direct) {
     if (n && (!reqs || !res)) return dv_fail(-EINVAL, "NULL request or result buffer");
     if (((uintptr_t)reqs & 15) || ((uintptr_t)res & 7)) return dv_fail(-EINVAL, "reqs must be 16-byte aligned");
     BatchArgs a;
@@ -706,6 +723,11 @@ int dv_submit(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint6
     if (rc) return rc;
     c->stats.batches++;
     c->stats.epochs += a.epochs.size();
+    // the direct launch: one epoch of at most kDirectMaxReqs requests, one
+    // request per wavefront, no completion times
+    a.direct = allow_direct && a.epochs.size() == 1 && n > 0 && n <= kDirectMaxReqs && !t_done &&
+               (uint64_t)grid_for(c, n, c->cfg.xlat_wg, 1u << 20) * (c->cfg.xlat_wg / 64) >= n;
+    if (a.direct) return enqueue_batch(c, w, a, s);
     if (!allow_graph || !c->cfg.use_graph || c->profiling || n == 0 || stream_capturing(s))
         return enqueue_batch(c, w, a, s);
     // graph cache: key = every argument that ends up in a kernel parameter

@@ -84,6 +84,7 @@ struct BatchArgs {
     uint64_t *n_faults = nullptr;
     uint64_t *t_done = nullptr;
     std::vector<uint64_t> epochs;
+    bool direct = false;  // one translate launch that also copies (small batches)
 };
 
 int dv_fail(int code, const char *fmt, ...);
@@ -93,5 +94,5 @@ int ensure_ws(devirt_ctx *c, Workspace *w, uint64_t n_req, uint64_t n_epochs, bo
 dv::DBatch make_batch(devirt_ctx *c, Workspace *w);
 int dv_submit(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint64_t *epoch_end, uint32_t n_epochs,
               devirt_result *res, devirt_fault *faults, uint64_t *n_faults, uint64_t *t_done, hipStream_t s,
-              bool allow_graph);
+              bool allow_graph, bool allow_direct = false);
 bool dv_in_server_thread();

@@ -20,6 +20,7 @@
 #include <errno.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -96,7 +97,7 @@ struct devirt_server {
     std::vector<Slot> slots;
     uint64_t launches = 0;
     // time accounting (written by the loop thread, read by any)
-    std::atomic<uint64_t> st_loops{0}, st_launches{0}, st_ops{0};
+    std::atomic<uint64_t> st_loops{0}, st_launches{0}, st_ops{0}, st_direct{0};
     std::atomic<uint64_t> ns_inbox{0}, ns_complete{0}, ns_admit{0}, ns_launch{0};
 };
 
@@ -117,12 +118,26 @@ static void on_batch_done(void *arg) {
     s->wake.notify_one();
 }
 
+// A launch this small (operations, bytes, largest operation) may run as one
+// kernel whose translating wavefronts also copy: fewer launches, less latency.
+// Larger operations go through the copy queue, where every wavefront helps.
+static constexpr uint32_t kDirectOps = 64;
+static constexpr uint64_t kDirectBytes = 256 << 10, kDirectMaxOp = 64 << 10;
+
 static int launch_slot(devirt_server *s, Slot &sl) {
     const uint32_t n = (uint32_t)sl.ops.size();
-    for (uint32_t i = 0; i < n; ++i) sl.h_reqs[i] = sl.ops[i].r;
+    uint64_t total = 0, largest = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        sl.h_reqs[i] = sl.ops[i].r;
+        total += sl.ops[i].r.len;
+        largest = std::max<uint64_t>(largest, sl.ops[i].r.len);
+    }
+    const bool direct = n <= kDirectOps && total <= kDirectBytes && largest <= kDirectMaxOp;
     const uint64_t t0 = now_ns();
-    int rc = dv_submit(s->ctx, sl.h_reqs, n, nullptr, 0, sl.h_res, nullptr, nullptr, nullptr, sl.stream, false);
+    int rc = dv_submit(s->ctx, sl.h_reqs, n, nullptr, 0, sl.h_res, nullptr, nullptr, nullptr, sl.stream, false,
+                       direct);
     if (rc) return rc;
+    if (direct) s->st_direct++;
     if (hipEventRecord(sl.ev, sl.stream) != hipSuccess) return dv_fail(-EIO, "server: event record failed");
     if (s->cfg.flags == DEVIRT_SERVE_NOTIFY &&
         hipLaunchHostFunc(sl.stream, on_batch_done, &sl) != hipSuccess)
@@ -386,5 +401,6 @@ extern "C" int devirt_server_get_stats(devirt_server *s, devirt_server_stats *ou
     out->ns_complete = s->ns_complete.load();
     out->ns_admit = s->ns_admit.load();
     out->ns_launch = s->ns_launch.load();
+    out->direct_launches = s->st_direct.load();
     return 0;
 }

@@ -71,7 +71,7 @@ class ServerCfg(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
-        "loops", "launches", "ops", "ns_inbox", "ns_complete", "ns_admit", "ns_launch")]
+        "loops", "launches", "ops", "ns_inbox", "ns_complete", "ns_admit", "ns_launch", "direct_launches")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -87,8 +87,11 @@ def test_alone_vs_mix(trace, alone, completion):
                 comps.append(srv.poll())
             srv.drain()
             comps.append(srv.poll(n))
+            st = srv.stats()
         finally:
             srv.stop()
+        # both launch kinds ran: small batches as one direct kernel, the rest queued
+        assert 0 < st["direct_launches"] < st["launches"], st
         c = np.concatenate(comps)
         assert len(c) == n and np.array_equal(np.sort(c["ticket"]), np.arange(n))
         c = c[np.argsort(c["ticket"])]
