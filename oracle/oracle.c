@@ -62,6 +62,7 @@ enum {
     ORC_NO_MEMSLOT = 5,
     ORC_NONCANONICAL = 6,
     ORC_INVALID = 7,
+    ORC_NO_POOL = 8,
 };
 
 #define ORC_ADDR_MASK 0x000FFFFFFFFFF000ull
@@ -532,4 +533,185 @@ int orc_check_conflicts(orc_state *s, const orc_req *reqs, uint64_t n, const uin
         if (n_epochs == 0) break;
     }
     return 0;
+}
+
+/* ------------------------------------------------------------ map pages -- */
+/* The second kind of routine of the software hybrid address space (section
+ * 4.2): map a page into the process address space by writing the guest's own
+ * page tables, taking new table pages from guest-physical frames the
+ * frontend handed over.  Batched, with this definition:
+ *   - map i puts the 4 KiB page at gva (aligned, user range) on the frame at
+ *     gpa (aligned, below 2^52): leaf = gpa | P | U/S, plus R/W when
+ *     flags & 1; when two maps name one page, the later one wins;
+ *   - every walk runs on the tables as they were before the call.  A present
+ *     large leaf or reserved bits on the path fail the map (RESERVED), so does
+ *     an existing table outside every memslot (NO_MEMSLOT);
+ *   - the tables the successful maps lack are created once each, in order of
+ *     level from the top down and ascending index within a level, on the pool
+ *     frames in order; each is zeroed and linked from its parent entry with P,
+ *     R/W and U/S (a PAE root entry: P only);
+ *   - if the pool is too small nothing is written and every map that would
+ *     have succeeded reports NO_POOL.
+ * Returns the number of pool frames used; -1 if a pool frame is unaligned or
+ * outside every memslot. */
+typedef struct {
+    uint64_t gva, gpa;
+    uint32_t flags, pad;
+} orc_map;
+
+static int cmp_u64(const void *a, const void *b) {
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+static uint64_t map_key(uint32_t level, uint64_t gva) {
+    return ((uint64_t)(8 - level) << 56) | (gva >> (12 + 9 * level));
+}
+
+/* Walk for a map (no A/D).  On success *missing is the highest level whose
+ * entry is not present (the tables below it are lacking), 0 if none is. */
+static uint32_t map_walk(const orc_state *s, const orc_proc *p, uint64_t gva, uint32_t *level,
+                         uint32_t *missing) {
+    const orc_vm *v = &s->vms[p->vm];
+    const int pae = p->levels == 3;
+    uint64_t table = pae ? (p->cr3 & 0xFFFFFFE0ull) : (p->cr3 & ORC_ADDR_MASK);
+    *missing = 0;
+    for (int lvl = (int)p->levels; lvl >= 2; lvl--) {
+        uint64_t thpa;
+        if (!slot_lookup(v, table, &thpa)) {
+            *level = (uint32_t)lvl;
+            return ORC_NO_MEMSLOT;
+        }
+        uint64_t idx = (pae && lvl == 3) ? ((gva >> 30) & 3) : ((gva >> (12 + 9 * (lvl - 1))) & 511);
+        uint64_t e = load64(v->arena + thpa + 8 * idx);
+        if (!(e & ORC_P)) {
+            *missing = (uint32_t)lvl;
+            return ORC_OK;
+        }
+        int rsvd = pae ? (lvl == 3 ? (e & ORC_PAE_PDPTE_RSVD) != 0 : (e & ORC_PAE_RSVD) != 0) : 0;
+        if (rsvd || (!(pae && lvl == 3) && (e & ORC_PS))) {  /* reserved, or a large leaf on the path */
+            *level = (uint32_t)lvl;
+            return ORC_RESERVED;
+        }
+        table = e & ORC_ADDR_MASK;
+    }
+    uint64_t thpa;
+    if (!slot_lookup(v, table, &thpa)) {   /* the page table itself */
+        *level = 1;
+        return ORC_NO_MEMSLOT;
+    }
+    return ORC_OK;
+}
+
+/* Arena offset of the existing table at `level` on gva's path (the walk to it
+ * is known to succeed), or of the PAE root table when level is the top. */
+static uint64_t existing_table(const orc_state *s, const orc_proc *p, uint64_t gva, uint32_t level) {
+    const orc_vm *v = &s->vms[p->vm];
+    const int pae = p->levels == 3;
+    uint64_t table = pae ? (p->cr3 & 0xFFFFFFE0ull) : (p->cr3 & ORC_ADDR_MASK);
+    uint64_t hpa = 0;
+    for (int lvl = (int)p->levels; lvl > (int)level; lvl--) {
+        slot_lookup(v, table, &hpa);
+        uint64_t idx = (pae && lvl == 3) ? ((gva >> 30) & 3) : ((gva >> (12 + 9 * (lvl - 1))) & 511);
+        table = load64(v->arena + hpa + 8 * idx) & ORC_ADDR_MASK;
+    }
+    slot_lookup(v, table, &hpa);
+    return hpa;
+}
+
+static void store64(uint8_t *p, uint64_t v) {
+    for (int i = 0; i < 8; i++) p[i] = (uint8_t)(v >> (8 * i));
+}
+
+int64_t orc_map_pages(orc_state *s, uint32_t asid, const orc_map *maps, uint64_t n, const uint64_t *pool,
+                      uint64_t n_pool, orc_result *res) {
+    if (asid >= s->nproc) {
+        for (uint64_t i = 0; i < n; i++) {
+            memset(&res[i], 0, sizeof(res[i]));
+            res[i].code = ORC_INVALID;
+            res[i].fault_gva = maps[i].gva;
+        }
+        return 0;
+    }
+    const orc_proc *p = &s->procs[asid];
+    orc_vm *v = &s->vms[p->vm];
+    const int pae = p->levels == 3;
+    uint64_t *pool_hpa = (uint64_t *)malloc((n_pool ? n_pool : 1) * sizeof(uint64_t));
+    for (uint64_t k = 0; k < n_pool; k++)
+        if ((pool[k] & 0xFFF) || !slot_lookup(v, pool[k], &pool_hpa[k])) {
+            free(pool_hpa);
+            return -1;
+        }
+    /* 1. walk every map on the initial tables; gather the lacking tables */
+    uint64_t *keys = (uint64_t *)malloc((4 * n + 1) * sizeof(uint64_t));
+    uint64_t nk = 0;
+    const uint64_t lim = user_limit(p->levels);
+    for (uint64_t i = 0; i < n; i++) {
+        const orc_map *m = &maps[i];
+        orc_result *r = &res[i];
+        memset(r, 0, sizeof(*r));
+        if ((m->gva & 0xFFF) || m->gva >= lim || (m->gpa & 0xFFF) || m->gpa >= (1ull << 52)) {
+            r->code = ORC_NONCANONICAL;
+            r->fault_gva = m->gva;
+            continue;
+        }
+        uint32_t level = 0, missing = 0;
+        uint32_t code = map_walk(s, p, m->gva, &level, &missing);
+        if (code != ORC_OK) {
+            r->code = code;
+            r->level = (uint16_t)level;
+            r->fault_gva = m->gva;
+            continue;
+        }
+        r->bytes_done = 4096;
+        for (uint32_t l = missing ? missing - 1 : 0; l >= 1; l--) keys[nk++] = map_key(l, m->gva);
+    }
+    qsort(keys, nk, sizeof(uint64_t), cmp_u64);
+    uint64_t nt = 0;
+    for (uint64_t k = 0; k < nk; k++)
+        if (nt == 0 || keys[nt - 1] != keys[k]) keys[nt++] = keys[k];
+    if (nt > n_pool) {   /* 2. not enough frames: nothing is written */
+        for (uint64_t i = 0; i < n; i++)
+            if (res[i].code == ORC_OK) {
+                res[i].code = ORC_NO_POOL;
+                res[i].bytes_done = 0;
+                res[i].fault_gva = maps[i].gva;
+            }
+        free(keys);
+        free(pool_hpa);
+        return 0;
+    }
+    /* 3. new tables: zeroed, then linked from their parents */
+    for (uint64_t k = 0; k < nt; k++) memset(v->arena + pool_hpa[k], 0, 4096);
+    for (uint64_t k = 0; k < nt; k++) {
+        uint32_t l = 8 - (uint32_t)(keys[k] >> 56);
+        uint64_t id = keys[k] & ((1ull << 56) - 1);
+        uint64_t va = id << (12 + 9 * l);
+        uint64_t parent_key = map_key(l + 1, va), phpa;
+        /* the parent is new unless it is the root table */
+        uint64_t *hit = l + 1 < (uint32_t)p->levels
+                            ? (uint64_t *)bsearch(&parent_key, keys, nt, sizeof(uint64_t), cmp_u64)
+                            : NULL;
+        if (hit)
+            phpa = pool_hpa[hit - keys];
+        else
+            phpa = existing_table(s, p, va, l + 1);
+        int root_pae = pae && l + 1 == 3;
+        uint64_t idx = root_pae ? ((va >> 30) & 3) : (id & 511);
+        uint64_t e = pool[k] | (root_pae ? ORC_P : (ORC_P | ORC_RW | ORC_US));
+        store64(v->arena + phpa + 8 * idx, e);
+    }
+    /* 4. leaves, in index order */
+    for (uint64_t i = 0; i < n; i++) {
+        if (res[i].code != ORC_OK) continue;
+        const orc_map *m = &maps[i];
+        uint64_t key = map_key(1, m->gva), pt;
+        uint64_t *hit = nt ? (uint64_t *)bsearch(&key, keys, nt, sizeof(uint64_t), cmp_u64) : NULL;
+        pt = hit ? pool_hpa[hit - keys] : existing_table(s, p, m->gva, 1);
+        uint64_t e = m->gpa | ORC_P | ORC_US | ((m->flags & 1) ? ORC_RW : 0);
+        store64(v->arena + pt + 8 * ((m->gva >> 12) & 511), e);
+    }
+    free(keys);
+    free(pool_hpa);
+    return (int64_t)nt;
 }

@@ -17,7 +17,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 CODES = {
     "OK": 0, "NOT_PRESENT": 1, "RESERVED": 2, "PROT_USER": 3, "PROT_WRITE": 4,
-    "NO_MEMSLOT": 5, "NONCANONICAL": 6, "INVALID": 7,
+    "NO_MEMSLOT": 5, "NONCANONICAL": 6, "INVALID": 7, "NO_POOL": 8,
 }
 RESULT_DTYPE = np.dtype([("bytes_done", "<u8"), ("fault_gva", "<u8"), ("code", "<u4"), ("level", "<u2"),
                          ("pad", "<u2")])
@@ -26,6 +26,7 @@ FAULT_DTYPE = np.dtype([("req_index", "<u8"), ("fault_gva", "<u8"), ("code", "<u
 XLAT_DTYPE = np.dtype([("gpa", "<u8"), ("hpa", "<u8"), ("code", "<u4"), ("level", "u1"), ("page_shift", "u1"),
                        ("vm", "<u2")])
 SLOT_DTYPE = np.dtype([("gpa", "<u8"), ("bytes", "<u8"), ("arena_off", "<u8")])
+MAP_DTYPE = np.dtype([("gva", "<u8"), ("gpa", "<u8"), ("flags", "<u4"), ("pad", "<u4")])
 XLAT_WRITE = 1
 XLAT_SET_AD = 2
 
@@ -66,6 +67,8 @@ def _load(path: str | None = None):
         lib.orc_batch_results.restype = ctypes.c_int64
         lib.orc_check_conflicts.argtypes = [vp, vp, u64, vp, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         lib.orc_check_conflicts.restype = ctypes.c_int
+        lib.orc_map_pages.argtypes = [vp, u32, vp, u64, vp, u64, vp]
+        lib.orc_map_pages.restype = ctypes.c_int64
         _libs[key] = lib
     return _libs[key]
 
@@ -146,6 +149,18 @@ class Oracle:
         faults = np.zeros(n, FAULT_DTYPE)
         nf = self._lib.orc_batch_results(self._h, r.ctypes.data, n, res.ctypes.data, faults.ctypes.data)
         return res, faults[:nf].copy()
+
+    def map_pages(self, asid: int, maps, pool_gpa):
+        """Map pages by writing the guest tables (see orc_map_pages); returns
+        (per-map results, pool frames used)."""
+        m = np.ascontiguousarray(maps, dtype=MAP_DTYPE)
+        pool = np.ascontiguousarray(np.asarray(pool_gpa, np.uint64).reshape(-1))
+        res = np.zeros(len(m), RESULT_DTYPE)
+        used = self._lib.orc_map_pages(self._h, asid, m.ctypes.data, len(m), pool.ctypes.data if len(pool) else None,
+                                       len(pool), res.ctypes.data)
+        if used < 0:
+            raise ValueError("a pool frame is unaligned or outside every memslot")
+        return res, int(used)
 
     def check_conflicts(self, reqs, epoch_end=None):
         """Return None if every epoch is conflict-free, else the offending (i, j)."""

@@ -109,6 +109,153 @@ def check_golden(lib_path=None):
     return fails
 
 
+def check_golden_maps(lib_path=None):
+    """The hand-derived map batches: per-map results, frames used, every entry
+    written, new tables zeroed, and no other arena byte changed."""
+    from oracle.oracle import MAP_DTYPE
+    fails = []
+    for w in golden_worlds():
+        if "maps" not in w:
+            continue
+        gm = w["maps"]
+        o, arena, pool = build_golden(w, lib_path)
+        a0 = arena.copy()
+        m = np.zeros(len(gm["batch"]), MAP_DTYPE)
+        for i, b in enumerate(gm["batch"]):
+            m[i] = (H(b["gva"]), H(b["gpa"]), b["flags"], 0)
+        res, used = o.map_pages(0, m, [H(x) for x in gm["pool"]])
+        if used != gm["used"]:
+            fails.append(f"{w['name']} maps: {used} pool frames used, expected {gm['used']}")
+        for i, b in enumerate(gm["batch"]):
+            got = (int(res[i]["code"]), int(res[i]["level"]), int(res[i]["bytes_done"]))
+            exp = (b["code"], b["level"], 4096 if b["code"] == 0 else 0)
+            if got != exp:
+                fails.append(f"{w['name']} map {b['gva']}: got {got} expected {exp} ({b['why']})")
+        a_exp = a0.copy()
+        for z in gm["zeroed"]:
+            a_exp[H(z):H(z) + 4096] = 0
+        for e in gm["expect"]:
+            a_exp[H(e["arena_off"]):H(e["arena_off"]) + 8] = np.frombuffer(H(e["value"]).to_bytes(8, "little"), np.uint8)
+        if not np.array_equal(arena, a_exp):
+            bad = np.nonzero(arena != a_exp)[0]
+            fails.append(f"{w['name']} maps: {len(bad)} arena bytes differ, first {hex(int(bad[0]))}")
+    return fails
+
+
+def free_frames(wl, vm, count, rng):
+    """Guest frames no table and no data page of the encoded map uses."""
+    v = wl.vms[vm]
+    used = set(int(x) for x in v.pt_gfn)
+    for p in wl.procs:
+        if p.vm != vm:
+            continue
+        for lv, fr in zip(p.leaf_level, p.leaf_frame):
+            n = 1 << (9 * (int(lv) - 1))
+            base = int(fr) >> 12
+            used.update(range(base, base + n)) if n <= 512 else used.update((base, base + n - 1))
+    nfr = v.mem_bytes >> 12
+    cand = np.setdiff1d(np.arange(nfr, dtype=np.int64), np.fromiter(used, np.int64))
+    return (rng.choice(cand, count, replace=False).astype(np.uint64) << np.uint64(12))
+
+
+def map_batch(wl, rng, n=600):
+    """Maps for process 0: remaps of mapped 4 KiB pages, pages in mapped and in
+    empty regions, pages inside large leaves, out-of-range pages, duplicates."""
+    from oracle.oracle import MAP_DTYPE
+    p = wl.procs[0]
+    lim = {3: 1 << 32, 4: 1 << 47, 5: 1 << 56}[p.levels]
+    lvl = p.leaf_level
+    g = []
+    k = n // 6
+    g += list(p.leaf_va[lvl == 1][rng.integers(0, max(1, int((lvl == 1).sum())), k)])        # remaps
+    big = np.nonzero(lvl >= 2)[0]
+    if len(big):                                                                            # inside large leaves
+        j = big[rng.integers(0, len(big), k)]
+        g += list(p.leaf_va[j] + (rng.integers(0, 512, k).astype(np.uint64) << np.uint64(12)))
+    vb = p.vmas[rng.integers(0, len(p.vmas), k)]                                            # around the VMAs
+    g += list(vb[:, 0] + vb[:, 1] + (rng.integers(0, 4096, k).astype(np.uint64) << np.uint64(12)))
+    g += list((rng.integers(1, lim >> 12, k, dtype=np.uint64) << np.uint64(12)))            # anywhere
+    g += [np.uint64(lim), np.uint64(lim + 4096)]                                            # out of range
+    g = np.array(g, np.uint64)
+    g = np.concatenate([g, g[rng.integers(0, len(g), k)]])                                  # duplicates
+    rng.shuffle(g)
+    m = np.zeros(len(g), MAP_DTYPE)
+    m["gva"] = g
+    m["gpa"] = rng.integers(0, wl.vms[p.vm].mem_bytes >> 12, len(g)).astype(np.uint64) << np.uint64(12)
+    m["flags"] = rng.integers(0, 2, len(g))
+    return m
+
+
+def expected_new_tables(wl, m):
+    """Tables the maps need and the encoded map lacks, counted from the
+    generator's table sets (no walk), and the expected per-map codes."""
+    p = wl.procs[0]
+    lim = {3: 1 << 32, 4: 1 << 47, 5: 1 << 56}[p.levels]
+    tabs = _leaf_lookup(p)
+    li = find_leaf(p, tabs, m["gva"])
+    code = np.zeros(len(m), np.int64)
+    code[m["gva"] >= np.uint64(lim)] = CODES["NONCANONICAL"]
+    inside_large = (li >= 0) & (p.leaf_level[np.maximum(li, 0)] >= 2) & (code == 0)
+    code[inside_large] = CODES["RESERVED"]
+    new = set()
+    for gva in m["gva"][code == 0]:
+        for L in range(1, p.levels):
+            ids = p.tables[L][0]
+            t = int(gva) >> (12 + 9 * L)
+            pos = np.searchsorted(ids, np.uint64(t))
+            if not (pos < len(ids) and int(ids[pos]) == t):
+                new.add((L, t))
+    return code, len(new)
+
+
+def check_map_properties(wl, lib_path=None, seed=3):
+    """Map a batch with the oracle, then check it against the encoded map.
+    Needs a world whose encoded tables are all reachable (p_upper_np = 0)."""
+    assert wl.spec.p_upper_np == 0
+    fails = []
+    rng = np.random.default_rng(seed)
+    p = wl.procs[0]
+    m = map_batch(wl, rng)
+    code, n_new = expected_new_tables(wl, m)
+    pool = free_frames(wl, p.vm, n_new + 5, rng)
+    # too small a pool: nothing is written
+    o = Oracle.from_workload(wl, lib_path=lib_path)
+    a0 = [a.copy() for a in o.arenas]
+    if n_new:
+        res, used = o.map_pages(0, m, pool[:n_new - 1])
+        if used != 0 or not all(np.array_equal(a, b) for a, b in zip(a0, o.arenas)):
+            fails.append("short pool: something was written")
+        if np.any(res["code"][code == 0] != CODES["NO_POOL"]):
+            fails.append("short pool: a map did not report NO_POOL")
+    res, used = o.map_pages(0, m, pool)
+    if not np.array_equal(res["code"].astype(np.int64), code):
+        i = int(np.nonzero(res["code"].astype(np.int64) != code)[0][0])
+        fails.append(f"map {hex(int(m['gva'][i]))}: code {int(res['code'][i])} expected {int(code[i])}")
+    if used != n_new:
+        fails.append(f"{used} new tables, the encoded map lacks {n_new}")
+    ok = np.nonzero(code == 0)[0]
+    last = {}
+    for i in ok:
+        last[int(m["gva"][i])] = i
+    idx = np.array(sorted(last.values()), np.int64)
+    x = o.translate(0, m["gva"][idx])
+    if np.any(x["code"] != 0) or np.any(x["gpa"] != m["gpa"][idx]) or np.any(x["page_shift"] != 12):
+        fails.append("a mapped page does not translate to its (last) frame")
+    wrote = o.translate(0, m["gva"][idx], XLAT_WRITE)
+    if np.any((wrote["code"] == CODES["PROT_WRITE"]) != (m["flags"][idx] & 1 == 0)):
+        fails.append("R/W of a mapped page does not follow its flags")
+    # pages the batch left alone translate as before
+    mapped = set(last)
+    keep = np.array([i for i in range(len(p.leaf_va)) if p.leaf_present[i] and p.leaf_level[i] == 1
+                     and int(p.leaf_va[i]) not in mapped][:3000], np.int64)
+    if len(keep):
+        before = Oracle.from_workload(wl, lib_path=lib_path).translate(0, p.leaf_va[keep])
+        after = o.translate(0, p.leaf_va[keep])
+        if not np.array_equal(before, after):
+            fails.append("a page outside the batch changed its translation")
+    return fails
+
+
 # ------------------------------------------------------- encode -> decode --
 def _leaf_lookup(p):
     """Map page-granular keys to leaf indices using the encoder's own map."""

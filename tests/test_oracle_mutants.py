@@ -48,6 +48,18 @@ MUTANTS = {
     "pae_root_user_bit": ("        table = e & ORC_ADDR_MASK;\n        top = 2;",
                           "        user_ok &= (int)((e >> 2) & 1);\n        table = e & ORC_ADDR_MASK;\n        top = 2;"),
     "pae_limit_47": ("levels == 3 ? (1ull << 32)", "levels == 3 ? (1ull << 47)"),
+    # mapping pages (the guest-table writer)
+    "map_link_without_user": ("(root_pae ? ORC_P : (ORC_P | ORC_RW | ORC_US))", "(root_pae ? ORC_P : (ORC_P | ORC_RW))"),
+    "map_leaf_always_writable": ("((m->flags & 1) ? ORC_RW : 0)", "ORC_RW"),
+    "map_tables_bottom_up": ("return ((uint64_t)(8 - level) << 56)", "return ((uint64_t)level << 56)"),
+    "map_earlier_wins": ("    for (uint64_t i = 0; i < n; i++) {\n        if (res[i].code != ORC_OK) continue;\n"
+                         "        const orc_map *m = &maps[i];",
+                         "    for (uint64_t j = n; j-- > 0;) {\n        uint64_t i = j;\n"
+                         "        if (res[i].code != ORC_OK) continue;\n        const orc_map *m = &maps[i];"),
+    "map_short_pool_unreported": ("                res[i].code = ORC_NO_POOL;", "                res[i].code = ORC_OK;"),
+    "map_new_table_not_zeroed": ("    for (uint64_t k = 0; k < nt; k++) memset(v->arena + pool_hpa[k], 0, 4096);\n", ""),
+    "map_pae_root_full_bits": ("(root_pae ? ORC_P :", "(root_pae ? (ORC_P | ORC_RW | ORC_US) :"),
+    "map_large_leaf_ignored": ("if (rsvd || (!(pae && lvl == 3) && (e & ORC_PS))) {", "if (rsvd) {"),
     "copy_direction_swapped": ("        if (to_guest)\n            memcpy(g, h, hi - lo);",
                                "        if (!to_guest)\n            memcpy(g, h, hi - lo);"),
     "ad_before_fault_check": ("        if (w.code != ORC_OK) {\n            res->bytes_done",
@@ -89,6 +101,9 @@ def test_pins_catch_mutant(tmp_path, name):
         lambda: pins.check_ad_closed_form(_small("c1"), lib),
         lambda: pins.check_roundtrip(_small("pae"), lib, per_proc=3000),
         lambda: pins.check_ad_closed_form(_small("pae"), lib),
+        lambda: pins.check_golden_maps(lib),
+        lambda: pins.check_map_properties(_small("mix2m"), lib),
+        lambda: pins.check_map_properties(_small("pae"), lib),
     ]
     for c in checks:
         if c():

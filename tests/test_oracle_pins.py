@@ -19,6 +19,16 @@ def test_golden_walks_ad_and_copies():
     assert pins.check_golden() == []
 
 
+def test_golden_maps():
+    assert pins.check_golden_maps() == []
+
+
+# worlds whose encoded tables are all reachable (no not-present upper entries)
+@pytest.mark.parametrize("name", ["c1", "mix2m", "lvl5", "lvl5_1g", "pae"])
+def test_map_properties(name):
+    assert pins.check_map_properties(wl(name)) == []
+
+
 @pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "pae"])
 def test_encode_decode_roundtrip(name):
     assert pins.check_roundtrip(wl(name)) == []
