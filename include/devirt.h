@@ -79,6 +79,8 @@ typedef struct {
                                   has no memslot                                  */
 #define DEVIRT_NONCANONICAL 6u /* range not inside user canonical space, or wraps */
 #define DEVIRT_INVALID 7u      /* unknown asid                                    */
+#define DEVIRT_NO_POOL 8u      /* devirt_map_pages: too few pool frames for the
+                                  tables the batch needs (nothing written)        */
 
 /* Per-operation result (24 bytes), the analogue of the per-guest-thread
  * result page (section 5).  Copies have prefix semantics: every byte before
@@ -174,6 +176,41 @@ int devirt_copy_from_guest(devirt_ctx *ctx, uint32_t asid, uint64_t gva, void *d
                            devirt_result *res_dev, void *hip_stream);
 int devirt_copy_to_guest(devirt_ctx *ctx, uint32_t asid, uint64_t gva, const void *src_dev, uint64_t len,
                          devirt_result *res_dev, void *hip_stream);
+
+/* Map guest virtual pages by writing the guest's own page tables: the
+ * second kind of routine of the software hybrid address space (section 4.2;
+ * insert_pfn and kin), where the backend maps a page into the process
+ * address space and takes the page-table pages it needs from guest-physical
+ * frames the frontend handed over.
+ *
+ * maps_dev: n devirt_map (n <= 2^19).  Map i puts the 4 KiB page at gva
+ * (aligned, in the user range) on the frame gpa (aligned, below 2^52): leaf
+ * = gpa | P | U/S, plus R/W with DEVIRT_MAP_WRITE, A = D = 0.  When two maps
+ * name one page, the later one wins.  Every walk sees the tables as they were
+ * before the call.  Per map, res_dev (n devirt_result): OK with bytes_done =
+ * 4096; NONCANONICAL (unaligned or out of range); RESERVED (a large leaf or
+ * reserved bits on the path; `level` names it); NO_MEMSLOT (an existing table
+ * outside every memslot); INVALID (unknown asid); NO_POOL.
+ * New tables: each table the successful maps need and the process lacks is
+ * created once, in order of level from the top down and ascending index
+ * within a level, on pool_gpa_host[0], [1], ...: zeroed, then linked from its
+ * parent entry with P, R/W and U/S (a PAE root entry: P only).  If n_pool is
+ * too small, nothing is written and every map that would have succeeded
+ * reports NO_POOL.  *n_used_dev (one uint64_t) receives the frames used.
+ * pool_gpa_host: n_pool distinct, 4 KiB aligned frames inside memslots that
+ * nothing else uses (-EINVAL otherwise); read before the call returns.
+ * Asynchronous on hip_stream; no other call may touch the process's tables
+ * meanwhile. */
+typedef struct {
+    uint64_t gva;
+    uint64_t gpa;
+    uint32_t flags; /* DEVIRT_MAP_WRITE */
+    uint32_t pad;
+} devirt_map;
+#define DEVIRT_MAP_WRITE 1u
+int devirt_map_pages(devirt_ctx *ctx, uint32_t asid, const devirt_map *maps_dev, uint64_t n,
+                     const uint64_t *pool_gpa_host, uint64_t n_pool, devirt_result *res_dev, uint64_t *n_used_dev,
+                     void *hip_stream);
 
 /* Many operations from many guests in one submission.  Results equal
  * applying the requests one after another in index order, provided that

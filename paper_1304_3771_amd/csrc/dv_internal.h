@@ -132,4 +132,23 @@ hipError_t launch_fault_scatter(hipStream_t s, const devirt_result *res, uint64_
                                 devirt_fault *faults);
 constexpr int kFaultTile = 1024;
 
+// devirt_map_pages: device buffers and arguments of one call.
+constexpr int kMapIdxBits = 19;  // map index bits in a (page, index) sort key: n <= 2^19
+struct MapArgs {
+    DView v;
+    uint32_t asid;
+    const devirt_map *maps;
+    uint64_t n;
+    devirt_result *res;
+    uint64_t *n_used;
+    uint64_t n_pool;
+    const uint64_t *pool_gpa, *pool_hpa;  // device, n_pool each
+    uint64_t *keys, *keys_sorted, *uniq;  // 4n each
+    uint64_t *mkeys, *mkeys_sorted;       // n each
+    uint64_t *sc;                         // 3 scalars
+    void *temp;                           // sort / unique scratch
+    size_t *temp_query;                   // non-null: only report the scratch size needed
+};
+hipError_t launch_map(hipStream_t s, const MapArgs &a);
+
 }  // namespace dv

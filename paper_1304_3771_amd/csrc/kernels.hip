@@ -31,6 +31,10 @@
 //              never with a read-modify-write of bytes outside the segment.
 //   faults     the ordered fault list is a tile count, a single-workgroup
 //              scan and a ballot/mbcnt scatter.
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_select.hpp>
+
 #include "dv_internal.h"
 
 namespace dv {
@@ -1236,6 +1240,240 @@ hipError_t launch_fault_scatter(hipStream_t s, const devirt_result *res, uint64_
     uint64_t tiles = (n + kFaultTile - 1) / kFaultTile;
     if (tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fault_scatter, dim3((unsigned)tiles), dim3(256), 0, s, res, n, tile_off, faults);
+    return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------- map pages
+// Mapping pages by writing the guest's own tables (section 4.2, the second
+// kind of routine).  Keys name tables: (8 - level) in bits 63:56, the table's
+// index (gva >> (12 + 9 level)) below, so ascending keys run from the top
+// level down and by index within a level.
+__device__ __forceinline__ uint64_t map_key(uint32_t level, uint64_t gva) {
+    return ((uint64_t)(8 - level) << 56) | (gva >> (12 + 9 * level));
+}
+
+// Index of gva's entry in its table at `level` (a PAE root table has 4).
+__device__ __forceinline__ uint64_t entry_index(uint32_t levels, uint32_t level, uint64_t gva) {
+    return (levels == 3 && level == 3) ? ((gva >> 30) & 3) : ((gva >> (12 + 9 * (level - 1))) & 511);
+}
+
+__device__ __forceinline__ uint64_t root_table(const DProc &p) {
+    return p.levels == 3 ? (p.cr3 & 0xFFFFFFE0ull) : (p.cr3 & kAddrMask);
+}
+
+__device__ __forceinline__ void store_entry(uint8_t *arena, uint64_t off, uint64_t v) { *gp<g_u64>(arena + off) = v; }
+
+// Walk for a map on the tables as they are (no A/D).  On success `missing` is
+// the highest level whose entry is not present (its child tables are lacking),
+// 0 when the whole path exists.
+__device__ uint32_t map_walk(const DVm &v, const DProc &p, uint64_t gva, uint32_t &level, uint32_t &missing) {
+    const bool pae = p.levels == 3;
+    uint64_t table = root_table(p);
+    missing = 0;
+    for (int lvl = (int)p.levels; lvl >= 2; --lvl) {
+        uint64_t th;
+        if (!slot_lookup(v, table, th)) {
+            level = (uint32_t)lvl;
+            return DEVIRT_NO_MEMSLOT;
+        }
+        const uint64_t e = load_entry(v.arena, th + 8 * entry_index(p.levels, (uint32_t)lvl, gva));
+        if (!(e & kP)) {
+            missing = (uint32_t)lvl;
+            return DEVIRT_OK;
+        }
+        const bool root = pae && lvl == 3;
+        const bool rsvd = pae && (e & (root ? kPaeRootRsvd : kPaeRsvd)) != 0;
+        if (rsvd || (!root && (e & kPS))) {  // reserved bits, or a large leaf on the path
+            level = (uint32_t)lvl;
+            return DEVIRT_RESERVED;
+        }
+        table = e & kAddrMask;
+    }
+    uint64_t th;
+    if (!slot_lookup(v, table, th)) {  // the page table itself
+        level = 1;
+        return DEVIRT_NO_MEMSLOT;
+    }
+    return DEVIRT_OK;
+}
+
+// Arena offset of the existing table at `level` on gva's path (the path to it
+// is known to be present); level == top gives the root table.  False if a
+// table on the way has no memslot (then nothing may be written).
+__device__ bool existing_table(const DVm &v, const DProc &p, uint64_t gva, uint32_t level, uint64_t &th) {
+    uint64_t table = root_table(p);
+    for (int lvl = (int)p.levels; lvl > (int)level; --lvl) {
+        if (!slot_lookup(v, table, th)) return false;
+        table = load_entry(v.arena, th + 8 * entry_index(p.levels, (uint32_t)lvl, gva)) & kAddrMask;
+    }
+    return slot_lookup(v, table, th);
+}
+
+// Position of key in the sorted keys[0, n), or -1.
+__device__ __forceinline__ int64_t find_key(const uint64_t *keys, uint64_t n, uint64_t key) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (lo < n && keys[lo] == key) ? (int64_t)lo : -1;
+}
+
+// One lane per map: its result, the keys of the tables it lacks (4 slots,
+// unused ones ~0) and its (page, index) key (~0 unless it succeeds).
+__global__ void __launch_bounds__(256) k_map_walk(DView V, uint32_t asid, const devirt_map *maps, uint64_t n,
+                                                   devirt_result *res, uint64_t *keys, uint64_t *mkeys) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const devirt_map m = maps[i];
+    devirt_result r;
+    r.bytes_done = 0;
+    r.fault_gva = m.gva;
+    r.code = DEVIRT_OK;
+    r.level = 0;
+    r.pad = 0;
+    uint64_t k[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+    uint64_t mk = ~0ull;
+    if (asid >= V.nproc) {
+        r.code = DEVIRT_INVALID;
+    } else {
+        const DProc p = V.procs[asid];
+        const DVm vm = V.vms[p.vm];
+        if ((m.gva & 0xFFFull) || m.gva >= user_limit(p.levels) || (m.gpa & 0xFFFull) || m.gpa >= (1ull << 52)) {
+            r.code = DEVIRT_NONCANONICAL;
+        } else {
+            uint32_t level = 0, missing = 0;
+            r.code = map_walk(vm, p, m.gva, level, missing);
+            r.level = (uint16_t)level;
+            if (r.code == DEVIRT_OK) {
+                r.bytes_done = 4096;
+                r.fault_gva = 0;
+                int j = 0;
+                for (uint32_t l = missing ? missing - 1 : 0; l >= 1 && j < 4; --l) k[j++] = map_key(l, m.gva);
+                mk = ((m.gva >> 12) << kMapIdxBits) | i;
+            }
+        }
+    }
+    res[i] = r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) keys[4 * i + j] = k[j];
+    mkeys[i] = mk;
+}
+
+// sc[0] = unique keys (from the unique step), sc[1] = new tables, sc[2] = 1 if
+// the pool is too small.
+__global__ void k_map_check(const uint64_t *uniq, uint64_t *sc, uint64_t n_pool, uint64_t *n_used) {
+    if (blockIdx.x || threadIdx.x) return;
+    const uint64_t nu = sc[0];
+    const uint64_t nt = (nu && uniq[nu - 1] == ~0ull) ? nu - 1 : nu;
+    const bool fail = nt > n_pool;
+    sc[1] = fail ? 0 : nt;
+    sc[2] = fail ? 1 : 0;
+    *n_used = fail ? 0 : nt;
+}
+
+__global__ void __launch_bounds__(256) k_map_fail(const devirt_map *maps, uint64_t n, devirt_result *res,
+                                                   const uint64_t *sc) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !sc[2] || res[i].code != DEVIRT_OK) return;
+    res[i].code = DEVIRT_NO_POOL;
+    res[i].bytes_done = 0;
+    res[i].fault_gva = maps[i].gva;
+}
+
+// Zero the new tables: 256 lanes x 16 bytes per table.
+__global__ void __launch_bounds__(256) k_map_zero(DView V, uint32_t asid, const uint64_t *pool_hpa,
+                                                   const uint64_t *sc) {
+    const uint64_t nt = sc[1];
+    if (!nt || asid >= V.nproc) return;
+    uint8_t *arena = V.vms[V.procs[asid].vm].arena;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt * 256; t += stride)
+        *gp<g_u32x4>(arena + pool_hpa[t >> 8] + 16 * (t & 255)) = (u32x4){0u, 0u, 0u, 0u};
+}
+
+// Link each new table from its parent entry (a new table or an existing one).
+__global__ void __launch_bounds__(256) k_map_link(DView V, uint32_t asid, const uint64_t *uniq, const uint64_t *sc,
+                                                   const uint64_t *pool_gpa, const uint64_t *pool_hpa) {
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nt = sc[1];
+    if (k >= nt || asid >= V.nproc) return;
+    const DProc p = V.procs[asid];
+    const DVm vm = V.vms[p.vm];
+    const uint64_t key = uniq[k];
+    const uint32_t l = 8u - (uint32_t)(key >> 56);
+    const uint64_t id = key & ((1ull << 56) - 1);
+    const uint64_t va = id << (12 + 9 * l);
+    int64_t j = -1;
+    if (l + 1 < p.levels) j = find_key(uniq, nt, map_key(l + 1, va));
+    uint64_t phpa = 0;
+    if (j >= 0)
+        phpa = pool_hpa[j];
+    else if (!existing_table(vm, p, va, l + 1, phpa))
+        return;
+    const bool root_pae = p.levels == 3 && l + 1 == 3;
+    const uint64_t idx = root_pae ? ((va >> 30) & 3) : (id & 511);
+    store_entry(vm.arena, phpa + 8 * idx, pool_gpa[k] | (root_pae ? kP : (kP | kRW | kUS)));
+}
+
+// Leaves: maps sorted by (page, index); the last map of each page writes.
+__global__ void __launch_bounds__(256) k_map_leaf(DView V, uint32_t asid, const devirt_map *maps, uint64_t n,
+                                                   const uint64_t *mk, const uint64_t *uniq, const uint64_t *sc,
+                                                   const uint64_t *pool_hpa) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n || sc[2] || asid >= V.nproc) return;
+    const uint64_t key = mk[t];
+    if (key == ~0ull) return;
+    if (t + 1 < n && mk[t + 1] != ~0ull && (mk[t + 1] >> kMapIdxBits) == (key >> kMapIdxBits)) return;
+    const devirt_map m = maps[key & ((1ull << kMapIdxBits) - 1)];
+    const DProc p = V.procs[asid];
+    const DVm vm = V.vms[p.vm];
+    const int64_t j = find_key(uniq, sc[1], map_key(1, m.gva));
+    uint64_t pt = 0;
+    if (j >= 0)
+        pt = pool_hpa[j];
+    else if (!existing_table(vm, p, m.gva, 1, pt))
+        return;
+    store_entry(vm.arena, pt + 8 * ((m.gva >> 12) & 511),
+                m.gpa | kP | kUS | ((m.flags & DEVIRT_MAP_WRITE) ? kRW : 0ull));
+}
+
+static unsigned blocks_for(uint64_t n) { return (unsigned)((n + 255) / 256 ? (n + 255) / 256 : 1); }
+
+hipError_t launch_map(hipStream_t s, const MapArgs &a) {
+    size_t t1 = 0, t2 = 0, t3 = 0;
+    hipError_t e;
+    const uint64_t nk = 4 * a.n;
+    if ((e = rocprim::radix_sort_keys(nullptr, t1, a.keys, a.keys_sorted, nk, 0, 64, s)) != hipSuccess) return e;
+    if ((e = rocprim::unique(nullptr, t2, a.keys_sorted, a.uniq, a.sc, nk, rocprim::equal_to<uint64_t>(), s)) !=
+        hipSuccess)
+        return e;
+    if ((e = rocprim::radix_sort_keys(nullptr, t3, a.mkeys, a.mkeys_sorted, a.n, 0, 64, s)) != hipSuccess) return e;
+    if (a.temp_query) {
+        *a.temp_query = std::max(t1, std::max(t2, t3));
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_map_walk, dim3(blocks_for(a.n)), dim3(256), 0, s, a.v, a.asid, a.maps, a.n, a.res, a.keys,
+                       a.mkeys);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = rocprim::radix_sort_keys(a.temp, t1, a.keys, a.keys_sorted, nk, 0, 64, s)) != hipSuccess) return e;
+    if ((e = rocprim::unique(a.temp, t2, a.keys_sorted, a.uniq, a.sc, nk, rocprim::equal_to<uint64_t>(), s)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_map_check, dim3(1), dim3(64), 0, s, a.uniq, a.sc, a.n_pool, a.n_used);
+    hipLaunchKernelGGL(k_map_fail, dim3(blocks_for(a.n)), dim3(256), 0, s, a.maps, a.n, a.res, a.sc);
+    hipLaunchKernelGGL(k_map_zero, dim3(blocks_for(std::min<uint64_t>(nk * 256, 1ull << 22))), dim3(256), 0, s,
+                       a.v, a.asid, a.pool_hpa, a.sc);
+    hipLaunchKernelGGL(k_map_link, dim3(blocks_for(nk)), dim3(256), 0, s, a.v, a.asid, a.uniq, a.sc, a.pool_gpa,
+                       a.pool_hpa);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = rocprim::radix_sort_keys(a.temp, t3, a.mkeys, a.mkeys_sorted, a.n, 0, 64, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_map_leaf, dim3(blocks_for(a.n)), dim3(256), 0, s, a.v, a.asid, a.maps, a.n, a.mkeys_sorted,
+                       a.uniq, a.sc, a.pool_hpa);
     return hipGetLastError();
 }
 

@@ -81,6 +81,13 @@ Workspace::~Workspace() {
     hipFree(pending);
     hipFree(tiles);
     hipFree(t0);
+    if (map_ev) {
+        hipEventSynchronize(map_ev);
+        hipEventDestroy(map_ev);
+    }
+    hipFree(map_buf);
+    hipFree(map_temp);
+    hipHostFree(map_pool_host);
 }
 
 // While a serving loop runs, only its own thread may drive the context.
@@ -511,6 +518,90 @@ static int grid_for(devirt_ctx *c, uint64_t waves_needed, uint32_t block, uint32
     if (g > cap) g = cap;
     if (g < 1) g = 1;
     return (int)g;
+}
+
+extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *maps, uint64_t n,
+                                const uint64_t *pool_gpa, uint64_t n_pool, devirt_result *res, uint64_t *n_used,
+                                void *stream) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
+    if (n > (1ull << kMapIdxBits)) return dv_fail(-EINVAL, "at most 2^%d maps per call", kMapIdxBits);
+    if (!n_used || (n && (!maps || !res)) || (n_pool && !pool_gpa)) return dv_fail(-EINVAL, "NULL argument");
+    if (((uintptr_t)maps & 7) || ((uintptr_t)res & 7)) return dv_fail(-EINVAL, "maps and res must be 8-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (set_dev(c)) return -EIO;
+    // the pool: aligned, distinct frames inside memslots of the process's VM
+    std::vector<uint64_t> hpa(n_pool);
+    if (asid < c->procs.size() && n_pool) {
+        const VmHost &v = c->vms[c->procs[asid].vm];
+        std::vector<uint64_t> sorted(pool_gpa, pool_gpa + n_pool);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return dv_fail(-EINVAL, "pool frames must be distinct");
+        for (uint64_t k = 0; k < n_pool; ++k) {
+            const uint64_t g = pool_gpa[k];
+            bool found = false;
+            for (const auto &sl : v.slots)
+                if (sl.used && (g & 0xFFF) == 0 && g >= sl.gpa && g - sl.gpa < sl.bytes) {
+                    hpa[k] = sl.off + (g - sl.gpa);
+                    found = true;
+                    break;
+                }
+            if (!found) return dv_fail(-EINVAL, "pool frame %#llx is unaligned or outside every memslot",
+                                       (unsigned long long)g);
+        }
+    }
+    Workspace *w = get_ws(c, s);
+    const uint64_t words = 14 * n + 3 + 2 * n_pool + 8;
+    int rc;
+    if ((rc = grow(c, w, w->map_buf, w->map_cap, words, "map buffers"))) return rc;
+    uint64_t *b = w->map_buf;
+    MapArgs a;
+    a.v = view_of(c);
+    a.asid = asid;
+    a.maps = maps;
+    a.n = n;
+    a.res = res;
+    a.n_used = n_used;
+    a.n_pool = n_pool;
+    a.keys = b;
+    a.keys_sorted = b + 4 * n;
+    a.uniq = b + 8 * n;
+    a.mkeys = b + 12 * n;
+    a.mkeys_sorted = b + 13 * n;
+    a.sc = b + 14 * n;
+    a.pool_gpa = b + 14 * n + 3;
+    a.pool_hpa = b + 14 * n + 3 + n_pool;
+    a.temp = nullptr;
+    size_t need = 0;
+    a.temp_query = &need;
+    HIPCHK(launch_map(s, a));
+    if ((rc = grow(c, w, w->map_temp, w->map_temp_cap, std::max<uint64_t>(need, 256), "map scratch"))) return rc;
+    a.temp = w->map_temp;
+    a.temp_query = nullptr;
+    if (n_pool) {
+        // staged through pinned memory; the previous upload from it must be done
+        if (w->map_ev) HIPCHK(hipEventSynchronize(w->map_ev));
+        if (w->map_pool_host_cap < 2 * n_pool) {
+            hipHostFree(w->map_pool_host);
+            w->map_pool_host = nullptr;
+            w->map_pool_host_cap = 0;
+            HIPCHK(hipHostMalloc((void **)&w->map_pool_host, 2 * n_pool * sizeof(uint64_t), hipHostMallocDefault));
+            w->map_pool_host_cap = 2 * n_pool;
+        }
+        memcpy(w->map_pool_host, pool_gpa, n_pool * sizeof(uint64_t));
+        memcpy(w->map_pool_host + n_pool, hpa.data(), n_pool * sizeof(uint64_t));
+        HIPCHK(hipMemcpyAsync((void *)a.pool_gpa, w->map_pool_host, 2 * n_pool * sizeof(uint64_t),
+                              hipMemcpyHostToDevice, s));
+        if (!w->map_ev) HIPCHK(hipEventCreateWithFlags(&w->map_ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(w->map_ev, s));
+    }
+    if (n == 0) {
+        HIPCHK(hipMemsetAsync(n_used, 0, sizeof(uint64_t), s));
+        return 0;
+    }
+    HIPCHK(launch_map(s, a));  // only arena bytes change: captured batch graphs stay valid
+    return 0;
 }
 
 extern "C" int devirt_translate(devirt_ctx *c, uint32_t asid, const uint64_t *gva_dev, uint64_t n, uint32_t flags,

@@ -46,6 +46,14 @@ struct Workspace {
     std::vector<GraphEntry> graphs;
     hipStream_t side = nullptr;         // translate launches run here, ahead of the copies
     std::vector<hipEvent_t> events;     // per epoch: translate done, copy done; plus the fork
+    // devirt_map_pages
+    uint64_t *map_buf = nullptr;        // keys, sorted keys, unique keys, map keys, scalars, pool
+    uint64_t map_cap = 0;
+    uint8_t *map_temp = nullptr;        // sort / unique scratch
+    uint64_t map_temp_cap = 0;
+    uint64_t *map_pool_host = nullptr;  // pinned staging of the pool (gpa, hpa)
+    uint64_t map_pool_host_cap = 0;
+    hipEvent_t map_ev = nullptr;        // the last pool upload
     ~Workspace();
 };
 

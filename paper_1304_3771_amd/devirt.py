@@ -22,7 +22,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "devirt.h")
 FROM_GUEST, TO_GUEST = 0, 1
 XLAT_WRITE, XLAT_SET_AD = 1, 2
 CODES = {"OK": 0, "NOT_PRESENT": 1, "RESERVED": 2, "PROT_USER": 3, "PROT_WRITE": 4, "NO_MEMSLOT": 5,
-         "NONCANONICAL": 6, "INVALID": 7}
+         "NONCANONICAL": 6, "INVALID": 7, "NO_POOL": 8}
 
 REQUEST_DTYPE = np.dtype([("gva", "<u8"), ("host", "<u8"), ("len", "<u4"), ("asid", "<u4"), ("dir", "u1"),
                           ("rsvd", "u1", (3,)), ("tag", "<u4")])
@@ -32,6 +32,8 @@ FAULT_DTYPE = np.dtype([("req_index", "<u8"), ("fault_gva", "<u8"), ("code", "<u
                         ("pad", "<u2")])
 XLAT_DTYPE = np.dtype([("gpa", "<u8"), ("hpa", "<u8"), ("code", "<u4"), ("level", "u1"), ("page_shift", "u1"),
                        ("vm", "<u2")])
+MAP_DTYPE = np.dtype([("gva", "<u8"), ("gpa", "<u8"), ("flags", "<u4"), ("pad", "<u4")])
+MAP_WRITE = 1
 
 
 class DevirtError(RuntimeError):
@@ -107,6 +109,7 @@ _SIGS = {
     "devirt_copy_from_guest": ([vp, u32, u64, vp, u64, vp, vp]),
     "devirt_copy_to_guest": ([vp, u32, u64, vp, u64, vp, vp]),
     "devirt_submit_batch": ([vp, vp, u64, vp, u32, vp, vp, vp, vp, vp]),
+    "devirt_map_pages": ([vp, u32, vp, u64, vp, u64, vp, vp, vp]),
     "devirt_sync": ([vp, vp]),
     "devirt_get_config": ([vp, ctypes.POINTER(Config)]),
     "devirt_set_config": ([vp, ctypes.POINTER(Config)]),
@@ -242,6 +245,14 @@ class Context:
     def copy_to_guest(self, asid: int, gva: int, src, nbytes: int, res, stream=None):
         _check("devirt_copy_to_guest", lib().devirt_copy_to_guest(self._h, asid, gva, _ptr(src), nbytes,
                                                                   _ptr(res), _stream(stream)))
+
+    def map_pages(self, asid: int, maps, n: int, pool_gpa, res, n_used, stream=None):
+        """maps: device array of MAP_DTYPE records; pool_gpa: host sequence of
+        free guest frames; res: device results; n_used: device uint64."""
+        pool = np.ascontiguousarray(np.asarray(pool_gpa, dtype=np.uint64).reshape(-1))
+        _check("devirt_map_pages", lib().devirt_map_pages(
+            self._h, asid, _ptr(maps), n, pool.ctypes.data if len(pool) else None, len(pool), _ptr(res),
+            _ptr(n_used), _stream(stream)))
 
     def submit_batch(self, reqs, n: int, res, epoch_end=None, faults=None, n_faults=None, t_done=None,
                      stream=None):

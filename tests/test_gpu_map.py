@@ -1,0 +1,207 @@
+"""devirt_map_pages on the GPU vs the oracle, through the C ABI.
+
+Bar: bit-exact: per-map results, the number of pool frames used and every
+arena byte (new tables, links, leaves, and nothing else).
+"""
+import numpy as np
+import pytest
+
+import pins
+from gpu_util import compare, gpu_batch, log, new_ctx, oracle_batch
+from oracle import Oracle
+from workload import device, gen
+
+pytestmark = pytest.mark.gpu
+
+SPECS = pins.small_specs()
+_WL = {}
+
+
+def wl(name):
+    if name not in _WL:
+        _WL[name] = gen.make_workload(SPECS[name])
+    return _WL[name]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1304_3771_amd as dv
+    dv.lib()
+
+
+def _gpu_map(ctx, asid, m, pool):
+    """One devirt_map_pages call; returns (results, frames used)."""
+    import torch
+    import paper_1304_3771_amd as dv
+    n = len(m)
+    dm = torch.from_numpy(np.ascontiguousarray(m).view(np.uint8).reshape(-1).copy()).cuda() if n else \
+        torch.zeros(24, dtype=torch.uint8, device="cuda")
+    res = torch.zeros(max(n, 1) * 24, dtype=torch.uint8, device="cuda")
+    used = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    ctx.map_pages(asid, dm, n, pool, res, used)
+    torch.cuda.synchronize()
+    return res.cpu().numpy()[:n * 24].view(dv.RESULT_DTYPE), int(used.item())
+
+
+def _same(tag, r, used, er, eused, arenas, earenas):
+    errs = []
+    for fld in ("bytes_done", "fault_gva", "code", "level"):
+        if not np.array_equal(r[fld], er[fld]):
+            i = int(np.nonzero(r[fld] != er[fld])[0][0])
+            errs.append(f"{tag}: result.{fld} differs at map {i}: gpu {r[i]} oracle {er[i]}")
+    if used != eused:
+        errs.append(f"{tag}: {used} frames used on the GPU, {eused} in the oracle")
+    for v, (a, b) in enumerate(zip(arenas, earenas)):
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0]
+            errs.append(f"{tag}: vm {v}: {len(bad)} arena bytes differ, first at {hex(int(bad[0]))}")
+    assert not errs, "\n".join(errs)
+
+
+def _golden_map_worlds():
+    return [w for w in pins.golden_worlds() if "maps" in w]
+
+
+@pytest.mark.parametrize("widx", range(len(_golden_map_worlds())))
+def test_golden_maps(widx):
+    """The hand-derived map batches (their expectations pin the oracle)."""
+    import torch
+    from oracle.oracle import MAP_DTYPE
+    w = _golden_map_worlds()[widx]
+    log(f"golden maps {w['name']}")
+    H = pins.H
+    o, arena, _ = pins.build_golden(w)
+    ctx = new_ctx()
+    try:
+        vm = ctx.vm_create(H(w["arena_bytes"]))
+        ctx.vm_write(vm, 0, arena)
+        for i, s in enumerate(w["slots"]):
+            ctx.memslot_set(vm, i, H(s["gpa"]), H(s["bytes"]), H(s["arena_off"]))
+        assert ctx.process_create(vm, H(w["cr3"]), w["levels"]) == 0
+        gm = w["maps"]
+        m = np.zeros(len(gm["batch"]), MAP_DTYPE)
+        for i, b in enumerate(gm["batch"]):
+            m[i] = (H(b["gva"]), H(b["gpa"]), b["flags"], 0)
+        pool = [H(x) for x in gm["pool"]]
+        r, used = _gpu_map(ctx, 0, m, pool)
+        er, eused = o.map_pages(0, m, pool)
+        a = np.empty(H(w["arena_bytes"]), np.uint8)
+        ctx.vm_read(vm, 0, a)
+        _same(w["name"], r, used, er, eused, [a], [arena])
+        assert used == gm["used"]
+        torch.cuda.synchronize()
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("name", ["c1", "mix2m", "lvl5", "lvl5_1g", "pae", "pae_prot", "multi_vm"])
+def test_map_matches_oracle(name):
+    """A mixed batch (remaps, new regions, pages inside large leaves, out of
+    range, duplicates): a too-small pool first (nothing written), then enough,
+    then the same batch again (every table now exists), then the workload's
+    requests through the new tables."""
+    w = wl(name)
+    log(f"map {name}")
+    rng = np.random.default_rng(11)
+    m = pins.map_batch(w, rng)
+    vm = w.procs[0].vm
+    pool = pins.free_frames(w, vm, 3 * len(m), rng)
+    o = Oracle.from_workload(w)
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        # how many tables the batch needs, from a copy of the oracle
+        _, need = Oracle.from_workload(w).map_pages(0, m, pool)
+        assert need > 0
+        r, used = _gpu_map(ctx, 0, m, pool[:need - 1])
+        er, eused = o.map_pages(0, m, pool[:need - 1])
+        _same(f"{name} short pool", r, used, er, eused, device.read_arenas(ctx, dw), o.arenas)
+        assert used == 0 and np.any(r["code"] == pins.CODES["NO_POOL"])
+        r, used = _gpu_map(ctx, 0, m, pool)
+        er, eused = o.map_pages(0, m, pool)
+        _same(f"{name} map", r, used, er, eused, device.read_arenas(ctx, dw), o.arenas)
+        assert used == need
+        r, used = _gpu_map(ctx, 0, m[::-1].copy(), pool[need:])
+        er, eused = o.map_pages(0, m[::-1].copy(), pool[need:])
+        _same(f"{name} again", r, used, er, eused, device.read_arenas(ctx, dw), o.arenas)
+        assert used == 0
+        got = gpu_batch(w, ctx=ctx, dw=dw)
+        res, faults = o.batch(w.requests)
+        assert compare(f"{name} batch after map", got, (res, faults, o.arenas, o.pool)) == []
+    finally:
+        ctx.close()
+
+
+def test_map_large_batch():
+    """2^17 maps in one call (spans many sort tiles), half into a 4 GiB region
+    the tables do not cover yet, half onto mapped pages."""
+    w = wl("mix2m")
+    log("map large")
+    rng = np.random.default_rng(5)
+    from oracle.oracle import MAP_DTYPE
+    p = w.procs[0]
+    n = 1 << 17
+    m = np.zeros(n, MAP_DTYPE)
+    base = np.uint64(0x7000_0000_0000)
+    m["gva"][: n // 2] = base + (rng.integers(0, 1 << 20, n // 2).astype(np.uint64) << np.uint64(12))
+    m["gva"][n // 2:] = p.leaf_va[rng.integers(0, len(p.leaf_va), n // 2)] & ~np.uint64(0xFFF)
+    m["gpa"] = rng.integers(0, w.vms[p.vm].mem_bytes >> 12, n).astype(np.uint64) << np.uint64(12)
+    m["flags"] = rng.integers(0, 2, n)
+    pool = pins.free_frames(w, p.vm, 4096, rng)
+    o = Oracle.from_workload(w)
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        r, used = _gpu_map(ctx, 0, m, pool)
+        er, eused = o.map_pages(0, m, pool)
+        _same("large", r, used, er, eused, device.read_arenas(ctx, dw), o.arenas)
+        assert used > 0
+    finally:
+        ctx.close()
+
+
+def test_map_edge_cases():
+    import paper_1304_3771_amd as dv
+    from oracle.oracle import MAP_DTYPE
+    w = wl("c1")
+    log("map edges")
+    rng = np.random.default_rng(2)
+    p = w.procs[0]
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        a0 = device.read_arenas(ctx, dw)
+        # no maps
+        r, used = _gpu_map(ctx, 0, np.zeros(0, MAP_DTYPE), [])
+        assert used == 0
+        m = pins.map_batch(w, rng, n=60)
+        # an asid with no process: every map INVALID, nothing written
+        r, used = _gpu_map(ctx, len(w.procs), m, pins.free_frames(w, p.vm, 8, rng))
+        assert used == 0 and np.all(r["code"] == pins.CODES["INVALID"])
+        assert np.array_equal(r["fault_gva"], m["gva"])
+        # no pool at all
+        o = Oracle.from_workload(w)
+        r, used = _gpu_map(ctx, 0, m, [])
+        er, eused = o.map_pages(0, m, [])
+        _same("no pool", r, used, er, eused, device.read_arenas(ctx, dw), o.arenas)
+        assert all(np.array_equal(a, b) for a, b in zip(a0, device.read_arenas(ctx, dw)))
+        # rejected pools: unaligned, outside every memslot, repeated
+        import torch
+        dm = torch.from_numpy(m.view(np.uint8).copy()).cuda()
+        res = torch.zeros(len(m) * 24, dtype=torch.uint8, device="cuda")
+        nu = torch.zeros(1, dtype=torch.int64, device="cuda")
+        good = pins.free_frames(w, p.vm, 2, rng)
+        for bad in ([int(good[0]) + 8], [1 << 51], [int(good[0]), int(good[1]), int(good[0])]):
+            with pytest.raises(dv.DevirtError) as ei:
+                ctx.map_pages(0, dm, len(m), bad, res, nu)
+            assert ei.value.rc == -22
+        with pytest.raises(dv.DevirtError) as ei:
+            ctx.map_pages(0, dm, (1 << 19) + 1, [], res, nu)
+        assert ei.value.rc == -22
+        torch.cuda.synchronize()
+        assert all(np.array_equal(a, b) for a, b in zip(a0, device.read_arenas(ctx, dw)))
+    finally:
+        ctx.close()
