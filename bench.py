@@ -253,6 +253,114 @@ def serving(args):
                       "rates": out_rates}))
 
 
+def free_guest_frames(wl, vm):
+    """GPAs of the guest frames that no table and no mapped page of the encoded
+    map uses (the frames a frontend could set aside for new tables)."""
+    v = wl.vms[vm]
+    nfr = v.mem_bytes >> 12
+    cover = np.zeros(nfr + 1, np.int64)
+    np.add.at(cover, v.pt_gfn.astype(np.int64), 1)
+    np.add.at(cover, v.pt_gfn.astype(np.int64) + 1, -1)
+    for p in wl.procs:
+        if p.vm != vm:
+            continue
+        base = (p.leaf_frame >> np.uint64(12)).astype(np.int64)
+        span = np.int64(1) << (9 * (p.leaf_level.astype(np.int64) - 1))
+        np.add.at(cover, base, 1)
+        np.add.at(cover, np.minimum(base + span, nfr), -1)
+    return np.nonzero(np.cumsum(cover[:nfr]) == 0)[0].astype(np.uint64) << np.uint64(12)
+
+
+def map_bench(args):
+    """Mapping pages (the guest-table writer), timed per call with HIP events."""
+    import torch
+    import paper_1304_3771_amd as dv
+    from workload import device, gen
+
+    sp = workload_spec(args.workload)
+    log(f"map: generating {args.workload}")
+    wl = gen.make_workload(sp, requests=False)
+    ctx = dv.Context(0)
+    dw = device.load(ctx, wl)
+    p = wl.procs[0]
+    free = free_guest_frames(wl, p.vm)  # ascending
+    rng = np.random.default_rng(77)
+    n = args.map_n
+    lim = {3: 1 << 32, 4: 1 << 47, 5: 1 << 56}[p.levels]
+    log(f"map: {len(free)} free guest frames, {n} maps per call")
+
+    def fresh_batch():
+        """Runs of 16-4096 contiguous pages (log-uniform), like mmaps of device
+        buffers, at random 2 MiB-aligned GVAs in the upper half of user space."""
+        g = []
+        left = n
+        while left:
+            run = min(left, int(16 * 256 ** rng.random()))
+            base = int(rng.integers(lim >> 22, (lim >> 21) - 8)) << 21  # the run ends below the limit
+            g.append(np.uint64(base) + (np.arange(run, dtype=np.uint64) << np.uint64(12)))
+            left -= run
+        m = np.zeros(n, dv.MAP_DTYPE)
+        m["gva"] = np.concatenate(g)
+        m["gpa"] = rng.integers(0, wl.vms[p.vm].mem_bytes >> 12, n).astype(np.uint64) << np.uint64(12)
+        m["flags"] = dv.MAP_WRITE
+        return m
+
+    def remap_batch():
+        """Maps onto pages the tables already map with 4 KiB leaves."""
+        va = p.leaf_va[p.leaf_level == 1]
+        m = np.zeros(n, dv.MAP_DTYPE)
+        m["gva"] = va[rng.integers(0, len(va), n)]
+        m["gpa"] = rng.integers(0, wl.vms[p.vm].mem_bytes >> 12, n).astype(np.uint64) << np.uint64(12)
+        m["flags"] = rng.integers(0, 2, n)
+        return m
+
+    res = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+    used = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pool_per_call = args.map_pool
+    next_frame = 0
+    out = {}
+    for kind, make in (("fresh", fresh_batch), ("remap", remap_batch)):
+        times, walls, hosts, tables = [], [], [], []
+        for it in range(args.warmup + args.steps):
+            m = make()
+            dm = torch.from_numpy(m.view(np.uint8).copy()).cuda()
+            pool = free[next_frame:next_frame + pool_per_call]  # ascending; the first `used` are taken
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            a.record()
+            ctx.map_pages(0, dm, n, pool, res, used)
+            host = (time.perf_counter() - t0) * 1e3
+            b.record()
+            b.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3
+            u = int(used.item())
+            r = res.cpu().numpy().view(dv.RESULT_DTYPE)
+            bad = int((r["code"] != 0).sum())
+            if bad:
+                raise RuntimeError(f"map bench: {bad} maps failed (codes {np.bincount(r['code'])})")
+            next_frame += u
+            if it >= args.warmup:
+                times.append(a.elapsed_time(b))
+                walls.append(wall)
+                hosts.append(host)
+                tables.append(u)
+        ms = float(np.mean(times))
+        out[kind] = {"ms_per_call": round(ms, 4), "maps_per_s": round(n / ms * 1e3, 1),
+                     "wall_ms_per_call": round(float(np.mean(walls)), 4),
+                     "host_ms_in_call": round(float(np.mean(hosts)), 4),
+                     "new_tables_per_call": int(np.mean(tables)), "calls": len(times)}
+        log(f"map {kind}: {ms:.3f} ms per call of {n} maps, {n / ms / 1e3:.2f} Mmaps/s, "
+            f"{int(np.mean(tables))} new tables per call")
+    ctx.close()
+    print(json.dumps({"metric": "maps/s (guest-table writer)", "value": out["fresh"]["maps_per_s"], "unit": "maps/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+                      "data": "synthetic", "dtype": "int64",
+                      "config": {"workload": f"{args.workload} tables, {n} 4 KiB maps per call; fresh: runs of "
+                                             "16-4096 pages at new 2 MiB-aligned GVAs; remap: mapped 4 KiB pages"},
+                      "fresh": out["fresh"], "remap": out["remap"]}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +376,9 @@ def main():
     ap.add_argument("--profile-only", action="store_true", help="only run K timed steps (for rocprofv3)")
     ap.add_argument("--set", default="", help="launch config overrides, e.g. seg_chunks=64,nontemporal=1")
     ap.add_argument("--serving", action="store_true", help="run the C4 serving sweep instead")
+    ap.add_argument("--map", action="store_true", help="time mapping pages (the guest-table writer) instead")
+    ap.add_argument("--map-n", type=int, default=1 << 19, help="maps per call")
+    ap.add_argument("--map-pool", type=int, default=4096, help="free guest frames handed to each call")
     ap.add_argument("--rates", default="1e5,2.5e5,5e5,1e6,2e6,5e6")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--serve-min-ops", type=int, default=200000)
@@ -295,6 +406,8 @@ def main():
     dv.lib()
     if args.serving:
         return serving(args)
+    if args.map:
+        return map_bench(args)
 
     t_gen = time.time()
     sp = workload_spec(args.workload)

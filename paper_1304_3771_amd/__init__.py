@@ -8,6 +8,8 @@ from .devirt import (  # noqa: F401
     COMPLETION_DTYPE,
     FAULT_DTYPE,
     FROM_GUEST,
+    MAP_DTYPE,
+    MAP_WRITE,
     REQUEST_DTYPE,
     RESULT_DTYPE,
     TO_GUEST,

@@ -133,7 +133,8 @@ hipError_t launch_fault_scatter(hipStream_t s, const devirt_result *res, uint64_
 constexpr int kFaultTile = 1024;
 
 // devirt_map_pages: device buffers and arguments of one call.
-constexpr int kMapIdxBits = 19;  // map index bits in a (page, index) sort key: n <= 2^19
+constexpr uint64_t kMapMax = 1ull << 19;      // maps per call
+constexpr uint64_t kMapRankMax = 1ull << 14;  // longest key list sorted by rank in LDS tiles
 struct MapArgs {
     DView v;
     uint32_t asid;
@@ -143,10 +144,18 @@ struct MapArgs {
     uint64_t *n_used;
     uint64_t n_pool;
     const uint64_t *pool_gpa, *pool_hpa;  // device, n_pool each
-    uint64_t *keys, *keys_sorted, *uniq;  // 4n each
-    uint64_t *mkeys, *mkeys_sorted;       // n each
-    uint64_t *sc;                         // 3 scalars
-    void *temp;                           // sort / unique scratch
+    // the tables the batch lacks: a hash set of their keys (tset_log2 slots),
+    // the distinct keys in insertion order (m = min(4n, n_pool) slots), sorted
+    uint64_t *tset;
+    uint32_t tset_log2;
+    uint64_t *tkeys, *tkeys_sorted;
+    uint64_t m;
+    int rank;                             // sort by rank (m <= kMapRankMax), else a library radix sort
+    // pages: a hash map page -> highest map index (pset_log2 slots)
+    uint64_t *pkey, *pidx;
+    uint32_t pset_log2;
+    uint64_t *sc;                         // 4 scalars
+    void *temp;                           // sort scratch
     size_t *temp_query;                   // non-null: only report the scratch size needed
 };
 hipError_t launch_map(hipStream_t s, const MapArgs &a);

@@ -1323,157 +1323,236 @@ __device__ __forceinline__ int64_t find_key(const uint64_t *keys, uint64_t n, ui
     return (lo < n && keys[lo] == key) ? (int64_t)lo : -1;
 }
 
-// One lane per map: its result, the keys of the tables it lacks (4 slots,
-// unused ones ~0) and its (page, index) key (~0 unless it succeeds).
-__global__ void __launch_bounds__(256) k_map_walk(DView V, uint32_t asid, const devirt_map *maps, uint64_t n,
-                                                   devirt_result *res, uint64_t *keys, uint64_t *mkeys) {
+// Fibonacci hashing (Knuth): the top log2 bits of key * 2^64/phi.
+__device__ __forceinline__ uint64_t hash_slot(uint64_t key, uint32_t log2) {
+    return (key * 0x9E3779B97F4A7C15ull) >> (64 - log2);
+}
+
+// Adds a table key to the set; its first inserter also appends it to the
+// list tkeys[0, m).  sc[0] counts distinct keys.  After a collision the probe
+// gives up, with sc[3] set, once more than m distinct keys exist (the count
+// is read only then: every read of one address is serialized).  Every probe
+// loop is bounded by the set's size.
+__device__ void tset_insert(const MapArgs &a, uint64_t key) {
+    const uint64_t mask = (1ull << a.tset_log2) - 1;
+    uint64_t h = hash_slot(key, a.tset_log2);
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+        const uint64_t cur = atomicCAS((unsigned long long *)&a.tset[h], ~0ull, (unsigned long long)key);
+        if (cur == ~0ull) {
+            const uint64_t idx = atomicAdd((unsigned long long *)&a.sc[0], 1ull);
+            if (idx < a.m) a.tkeys[idx] = key;
+            return;
+        }
+        if (cur == key) return;
+        if (__hip_atomic_load(&a.sc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > a.m) break;
+        h = (h + 1) & mask;
+    }
+    __hip_atomic_store(&a.sc[3], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Records map i for its page: the slot keeps the highest index (the set has
+// at least twice as many slots as maps, so a free slot is always found).
+__device__ void page_note(const MapArgs &a, uint64_t page, uint64_t i) {
+    const uint64_t mask = (1ull << a.pset_log2) - 1;
+    uint64_t h = hash_slot(page, a.pset_log2);
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+        const uint64_t cur = atomicCAS((unsigned long long *)&a.pkey[h], ~0ull, (unsigned long long)page);
+        if (cur == ~0ull || cur == page) {
+            atomicMax((unsigned long long *)&a.pidx[h], (unsigned long long)i);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Fill `ones` with ~0 (empty set slots, list padding) and `zeros` with 0.
+__global__ void __launch_bounds__(256) k_map_clear(uint64_t *ones, uint64_t n_ones, uint64_t *zeros, uint64_t n_zeros) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_ones + n_zeros; t += stride) {
+        if (t < n_ones)
+            ones[t] = ~0ull;
+        else
+            zeros[t - n_ones] = 0;
+    }
+}
+
+// One lane per map: its result; the tables its path lacks go into the set
+// (a key the previous lane of the wavefront holds in the same position is
+// left to that lane); a successful map is noted for its page.
+__global__ void __launch_bounds__(256) k_map_walk(MapArgs a) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const devirt_map m = maps[i];
-    devirt_result r;
-    r.bytes_done = 0;
-    r.fault_gva = m.gva;
-    r.code = DEVIRT_OK;
-    r.level = 0;
-    r.pad = 0;
+    const bool live = i < a.n;
     uint64_t k[4] = {~0ull, ~0ull, ~0ull, ~0ull};
-    uint64_t mk = ~0ull;
-    if (asid >= V.nproc) {
-        r.code = DEVIRT_INVALID;
-    } else {
-        const DProc p = V.procs[asid];
-        const DVm vm = V.vms[p.vm];
-        if ((m.gva & 0xFFFull) || m.gva >= user_limit(p.levels) || (m.gpa & 0xFFFull) || m.gpa >= (1ull << 52)) {
-            r.code = DEVIRT_NONCANONICAL;
+    uint64_t gva = 0;
+    bool ok = false;
+    if (live) {
+        const devirt_map m = a.maps[i];
+        gva = m.gva;
+        devirt_result r;
+        r.bytes_done = 0;
+        r.fault_gva = m.gva;
+        r.code = DEVIRT_OK;
+        r.level = 0;
+        r.pad = 0;
+        if (a.asid >= a.v.nproc) {
+            r.code = DEVIRT_INVALID;
         } else {
-            uint32_t level = 0, missing = 0;
-            r.code = map_walk(vm, p, m.gva, level, missing);
-            r.level = (uint16_t)level;
-            if (r.code == DEVIRT_OK) {
-                r.bytes_done = 4096;
-                r.fault_gva = 0;
-                int j = 0;
-                for (uint32_t l = missing ? missing - 1 : 0; l >= 1 && j < 4; --l) k[j++] = map_key(l, m.gva);
-                mk = ((m.gva >> 12) << kMapIdxBits) | i;
+            const DProc p = a.v.procs[a.asid];
+            const DVm vm = a.v.vms[p.vm];
+            if ((m.gva & 0xFFFull) || m.gva >= user_limit(p.levels) || (m.gpa & 0xFFFull) || m.gpa >= (1ull << 52)) {
+                r.code = DEVIRT_NONCANONICAL;
+            } else {
+                uint32_t level = 0, missing = 0;
+                r.code = map_walk(vm, p, m.gva, level, missing);
+                r.level = (uint16_t)level;
+                if (r.code == DEVIRT_OK) {
+                    r.bytes_done = 4096;
+                    r.fault_gva = 0;
+                    ok = true;
+                    int j = 0;
+                    for (uint32_t l = missing ? missing - 1 : 0; l >= 1 && j < 4; --l) k[j++] = map_key(l, m.gva);
+                }
             }
         }
+        a.res[i] = r;
     }
-    res[i] = r;
+    const int lane = lane_id();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) keys[4 * i + j] = k[j];
-    mkeys[i] = mk;
+    for (int j = 0; j < 4; ++j) {
+        const uint64_t prev = shfl64(k[j], lane > 0 ? lane - 1 : 0);
+        if (k[j] != ~0ull && (lane == 0 || prev != k[j])) tset_insert(a, k[j]);
+    }
+    if (ok) page_note(a, gva >> 12, i);
 }
 
-// sc[0] = unique keys (from the unique step), sc[1] = new tables, sc[2] = 1 if
-// the pool is too small.
-__global__ void k_map_check(const uint64_t *uniq, uint64_t *sc, uint64_t n_pool, uint64_t *n_used) {
-    if (blockIdx.x || threadIdx.x) return;
-    const uint64_t nu = sc[0];
-    const uint64_t nt = (nu && uniq[nu - 1] == ~0ull) ? nu - 1 : nu;
-    const bool fail = nt > n_pool;
-    sc[1] = fail ? 0 : nt;
-    sc[2] = fail ? 1 : 0;
-    *n_used = fail ? 0 : nt;
+// Tables to create: 0 when the pool is too small (then nothing is written).
+__device__ __forceinline__ uint64_t new_tables(const MapArgs &a) {
+    const uint64_t u = a.sc[0];
+    return (a.sc[3] != 0 || u > a.n_pool) ? 0 : u;
+}
+__device__ __forceinline__ bool pool_short(const MapArgs &a) { return a.sc[3] != 0 || a.sc[0] > a.n_pool; }
+
+// The distinct keys are sorted by rank (the number of smaller keys; there are
+// no ties), in LDS tiles: for lists of up to kMapRankMax keys.  The same
+// launch zeroes the new tables, 16 bytes per lane.
+__global__ void __launch_bounds__(256) k_map_rank_zero(const MapArgs a) {
+    __shared__ uint64_t tile[256];
+    const uint64_t nt = new_tables(a);
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (nt && a.asid < a.v.nproc) {
+        uint8_t *arena = a.v.vms[a.v.procs[a.asid].vm].arena;
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t z = t; z < nt * 256; z += stride)
+            *gp<g_u32x4>(arena + a.pool_hpa[z >> 8] + 16 * (z & 255)) = (u32x4){0u, 0u, 0u, 0u};
+    }
+    if (!a.rank || (uint64_t)blockIdx.x * blockDim.x >= nt) return;  // uniform per block
+    const uint64_t key = t < nt ? a.tkeys[t] : ~0ull;
+    uint64_t rank = 0;
+    for (uint64_t base = 0; base < nt; base += 256) {
+        __syncthreads();
+        tile[threadIdx.x] = base + threadIdx.x < nt ? a.tkeys[base + threadIdx.x] : ~0ull;
+        __syncthreads();
+        const uint32_t cnt = (uint32_t)std::min<uint64_t>(256, nt - base);
+        for (uint32_t q = 0; q < cnt; ++q) rank += tile[q] < key;
+    }
+    if (t < nt) a.tkeys_sorted[rank] = key;
 }
 
-__global__ void __launch_bounds__(256) k_map_fail(const devirt_map *maps, uint64_t n, devirt_result *res,
-                                                   const uint64_t *sc) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !sc[2] || res[i].code != DEVIRT_OK) return;
-    res[i].code = DEVIRT_NO_POOL;
-    res[i].bytes_done = 0;
-    res[i].fault_gva = maps[i].gva;
-}
-
-// Zero the new tables: 256 lanes x 16 bytes per table.
-__global__ void __launch_bounds__(256) k_map_zero(DView V, uint32_t asid, const uint64_t *pool_hpa,
-                                                   const uint64_t *sc) {
-    const uint64_t nt = sc[1];
-    if (!nt || asid >= V.nproc) return;
-    uint8_t *arena = V.vms[V.procs[asid].vm].arena;
+// Zero the new tables (after a library sort).
+__global__ void __launch_bounds__(256) k_map_zero(const MapArgs a) {
+    const uint64_t nt = new_tables(a);
+    if (!nt || a.asid >= a.v.nproc) return;
+    uint8_t *arena = a.v.vms[a.v.procs[a.asid].vm].arena;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt * 256; t += stride)
-        *gp<g_u32x4>(arena + pool_hpa[t >> 8] + 16 * (t & 255)) = (u32x4){0u, 0u, 0u, 0u};
+        *gp<g_u32x4>(arena + a.pool_hpa[t >> 8] + 16 * (t & 255)) = (u32x4){0u, 0u, 0u, 0u};
 }
 
-// Link each new table from its parent entry (a new table or an existing one).
-__global__ void __launch_bounds__(256) k_map_link(DView V, uint32_t asid, const uint64_t *uniq, const uint64_t *sc,
-                                                   const uint64_t *pool_gpa, const uint64_t *pool_hpa) {
-    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t nt = sc[1];
-    if (k >= nt || asid >= V.nproc) return;
-    const DProc p = V.procs[asid];
-    const DVm vm = V.vms[p.vm];
-    const uint64_t key = uniq[k];
-    const uint32_t l = 8u - (uint32_t)(key >> 56);
-    const uint64_t id = key & ((1ull << 56) - 1);
-    const uint64_t va = id << (12 + 9 * l);
-    int64_t j = -1;
-    if (l + 1 < p.levels) j = find_key(uniq, nt, map_key(l + 1, va));
-    uint64_t phpa = 0;
-    if (j >= 0)
-        phpa = pool_hpa[j];
-    else if (!existing_table(vm, p, va, l + 1, phpa))
-        return;
-    const bool root_pae = p.levels == 3 && l + 1 == 3;
-    const uint64_t idx = root_pae ? ((va >> 30) & 3) : (id & 511);
-    store_entry(vm.arena, phpa + 8 * idx, pool_gpa[k] | (root_pae ? kP : (kP | kRW | kUS)));
-}
-
-// Leaves: maps sorted by (page, index); the last map of each page writes.
-__global__ void __launch_bounds__(256) k_map_leaf(DView V, uint32_t asid, const devirt_map *maps, uint64_t n,
-                                                   const uint64_t *mk, const uint64_t *uniq, const uint64_t *sc,
-                                                   const uint64_t *pool_hpa) {
+// Lane t links new table t (sorted position t takes pool frame t) from its
+// parent entry, in a new table or an existing one, and handles map t: NO_POOL
+// when the pool is short, else the leaf if it is the last map of its page.
+// Links and leaves touch disjoint entries: a leaf whose page table exists has
+// a fully present path, and links write only not-present entries (in existing
+// tables) or entries of new tables.
+__global__ void __launch_bounds__(256) k_map_write(const MapArgs a) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n || sc[2] || asid >= V.nproc) return;
-    const uint64_t key = mk[t];
-    if (key == ~0ull) return;
-    if (t + 1 < n && mk[t + 1] != ~0ull && (mk[t + 1] >> kMapIdxBits) == (key >> kMapIdxBits)) return;
-    const devirt_map m = maps[key & ((1ull << kMapIdxBits) - 1)];
-    const DProc p = V.procs[asid];
-    const DVm vm = V.vms[p.vm];
-    const int64_t j = find_key(uniq, sc[1], map_key(1, m.gva));
+    const bool short_pool = pool_short(a);
+    const uint64_t nt = short_pool ? 0 : a.sc[0];
+    if (t == 0) *a.n_used = nt;
+    if (a.asid >= a.v.nproc) return;
+    const DProc p = a.v.procs[a.asid];
+    const DVm vm = a.v.vms[p.vm];
+    const uint64_t *uniq = a.tkeys_sorted;
+    if (t < nt) {
+        const uint64_t key = uniq[t];
+        const uint32_t l = 8u - (uint32_t)(key >> 56);
+        const uint64_t id = key & ((1ull << 56) - 1);
+        const uint64_t va = id << (12 + 9 * l);
+        int64_t j = -1;
+        if (l + 1 < p.levels) j = find_key(uniq, nt, map_key(l + 1, va));
+        uint64_t phpa = 0;
+        bool have = true;
+        if (j >= 0)
+            phpa = a.pool_hpa[j];
+        else
+            have = existing_table(vm, p, va, l + 1, phpa);
+        if (have) {
+            const bool root_pae = p.levels == 3 && l + 1 == 3;
+            const uint64_t idx = root_pae ? ((va >> 30) & 3) : (id & 511);
+            store_entry(vm.arena, phpa + 8 * idx, a.pool_gpa[t] | (root_pae ? kP : (kP | kRW | kUS)));
+        }
+    }
+    if (t >= a.n || a.res[t].code != DEVIRT_OK) return;
+    const devirt_map m = a.maps[t];
+    if (short_pool) {
+        a.res[t].code = DEVIRT_NO_POOL;
+        a.res[t].bytes_done = 0;
+        a.res[t].fault_gva = m.gva;
+        return;
+    }
+    const uint64_t page = m.gva >> 12;
+    const uint64_t mask = (1ull << a.pset_log2) - 1;
+    uint64_t h = hash_slot(page, a.pset_log2);
+    for (uint64_t probe = 0; probe <= mask && a.pkey[h] != page; ++probe) h = (h + 1) & mask;
+    if (a.pkey[h] != page || a.pidx[h] != t) return;
+    const int64_t j = find_key(uniq, nt, map_key(1, m.gva));
     uint64_t pt = 0;
     if (j >= 0)
-        pt = pool_hpa[j];
+        pt = a.pool_hpa[j];
     else if (!existing_table(vm, p, m.gva, 1, pt))
         return;
-    store_entry(vm.arena, pt + 8 * ((m.gva >> 12) & 511),
-                m.gpa | kP | kUS | ((m.flags & DEVIRT_MAP_WRITE) ? kRW : 0ull));
+    store_entry(vm.arena, pt + 8 * ((m.gva >> 12) & 511), m.gpa | kP | kUS | ((m.flags & DEVIRT_MAP_WRITE) ? kRW : 0ull));
 }
 
 static unsigned blocks_for(uint64_t n) { return (unsigned)((n + 255) / 256 ? (n + 255) / 256 : 1); }
 
 hipError_t launch_map(hipStream_t s, const MapArgs &a) {
-    size_t t1 = 0, t2 = 0, t3 = 0;
+    size_t tsort = 0;
     hipError_t e;
-    const uint64_t nk = 4 * a.n;
-    if ((e = rocprim::radix_sort_keys(nullptr, t1, a.keys, a.keys_sorted, nk, 0, 64, s)) != hipSuccess) return e;
-    if ((e = rocprim::unique(nullptr, t2, a.keys_sorted, a.uniq, a.sc, nk, rocprim::equal_to<uint64_t>(), s)) !=
-        hipSuccess)
+    if (!a.rank &&
+        (e = rocprim::radix_sort_keys(nullptr, tsort, a.tkeys, a.tkeys_sorted, a.m, 0, 64, s)) != hipSuccess)
         return e;
-    if ((e = rocprim::radix_sort_keys(nullptr, t3, a.mkeys, a.mkeys_sorted, a.n, 0, 64, s)) != hipSuccess) return e;
     if (a.temp_query) {
-        *a.temp_query = std::max(t1, std::max(t2, t3));
+        *a.temp_query = tsort;
         return hipSuccess;
     }
-    hipLaunchKernelGGL(k_map_walk, dim3(blocks_for(a.n)), dim3(256), 0, s, a.v, a.asid, a.maps, a.n, a.res, a.keys,
-                       a.mkeys);
+    const uint64_t nset = (1ull << a.tset_log2), npset = (1ull << a.pset_log2);
+    // tset, tkeys and pkey are contiguous, then pidx and sc
+    const uint64_t ones = nset + a.m + npset, zeros = npset + 4;
+    hipLaunchKernelGGL(k_map_clear, dim3(blocks_for(std::min<uint64_t>(ones + zeros, 1ull << 22))), dim3(256), 0, s,
+                       a.tset, ones, a.pidx, zeros);
+    hipLaunchKernelGGL(k_map_walk, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = rocprim::radix_sort_keys(a.temp, t1, a.keys, a.keys_sorted, nk, 0, 64, s)) != hipSuccess) return e;
-    if ((e = rocprim::unique(a.temp, t2, a.keys_sorted, a.uniq, a.sc, nk, rocprim::equal_to<uint64_t>(), s)) !=
-        hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_map_check, dim3(1), dim3(64), 0, s, a.uniq, a.sc, a.n_pool, a.n_used);
-    hipLaunchKernelGGL(k_map_fail, dim3(blocks_for(a.n)), dim3(256), 0, s, a.maps, a.n, a.res, a.sc);
-    hipLaunchKernelGGL(k_map_zero, dim3(blocks_for(std::min<uint64_t>(nk * 256, 1ull << 22))), dim3(256), 0, s,
-                       a.v, a.asid, a.pool_hpa, a.sc);
-    hipLaunchKernelGGL(k_map_link, dim3(blocks_for(nk)), dim3(256), 0, s, a.v, a.asid, a.uniq, a.sc, a.pool_gpa,
-                       a.pool_hpa);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = rocprim::radix_sort_keys(a.temp, t3, a.mkeys, a.mkeys_sorted, a.n, 0, 64, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_map_leaf, dim3(blocks_for(a.n)), dim3(256), 0, s, a.v, a.asid, a.maps, a.n, a.mkeys_sorted,
-                       a.uniq, a.sc, a.pool_hpa);
+    if (a.rank) {
+        // enough lanes to zero every possible new table in one sweep (at most 2^22)
+        hipLaunchKernelGGL(k_map_rank_zero, dim3(blocks_for(std::max(a.m, std::min<uint64_t>(a.m * 256, 1ull << 22)))),
+                           dim3(256), 0, s, a);
+    } else {
+        if ((e = rocprim::radix_sort_keys(a.temp, tsort, a.tkeys, a.tkeys_sorted, a.m, 0, 64, s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_map_zero, dim3(blocks_for(std::min<uint64_t>(a.m * 256, 1ull << 22))), dim3(256), 0, s, a);
+    }
+    hipLaunchKernelGGL(k_map_write, dim3(blocks_for(std::max(a.n, a.m))), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

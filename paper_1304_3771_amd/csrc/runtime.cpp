@@ -525,7 +525,7 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
                                 void *stream) {
     if (!c) return dv_fail(-EINVAL, "ctx is NULL");
     if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
-    if (n > (1ull << kMapIdxBits)) return dv_fail(-EINVAL, "at most 2^%d maps per call", kMapIdxBits);
+    if (n > kMapMax) return dv_fail(-EINVAL, "at most %llu maps per call", (unsigned long long)kMapMax);
     if (!n_used || (n && (!maps || !res)) || (n_pool && !pool_gpa)) return dv_fail(-EINVAL, "NULL argument");
     if (((uintptr_t)maps & 7) || ((uintptr_t)res & 7)) return dv_fail(-EINVAL, "maps and res must be 8-byte aligned");
     hipStream_t s = (hipStream_t)stream;
@@ -534,25 +534,44 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     std::vector<uint64_t> hpa(n_pool);
     if (asid < c->procs.size() && n_pool) {
         const VmHost &v = c->vms[c->procs[asid].vm];
-        std::vector<uint64_t> sorted(pool_gpa, pool_gpa + n_pool);
-        std::sort(sorted.begin(), sorted.end());
-        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
-            return dv_fail(-EINVAL, "pool frames must be distinct");
+        std::vector<const VmHost::Slot *> sl;
+        for (const auto &x : v.slots)
+            if (x.used) sl.push_back(&x);
+        std::sort(sl.begin(), sl.end(), [](const VmHost::Slot *p, const VmHost::Slot *q) { return p->gpa < q->gpa; });
+        // distinct: a strictly ascending pool (the usual case) needs no sort
+        bool ascending = true;
+        for (uint64_t k = 1; k < n_pool && ascending; ++k) ascending = pool_gpa[k - 1] < pool_gpa[k];
+        if (!ascending) {
+            std::vector<uint64_t> sorted(pool_gpa, pool_gpa + n_pool);
+            std::sort(sorted.begin(), sorted.end());
+            if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+                return dv_fail(-EINVAL, "pool frames must be distinct");
+        }
+        const VmHost::Slot *q = nullptr;  // the slot of the previous frame, tried first
         for (uint64_t k = 0; k < n_pool; ++k) {
             const uint64_t g = pool_gpa[k];
-            bool found = false;
-            for (const auto &sl : v.slots)
-                if (sl.used && (g & 0xFFF) == 0 && g >= sl.gpa && g - sl.gpa < sl.bytes) {
-                    hpa[k] = sl.off + (g - sl.gpa);
-                    found = true;
-                    break;
-                }
-            if (!found) return dv_fail(-EINVAL, "pool frame %#llx is unaligned or outside every memslot",
-                                       (unsigned long long)g);
+            if (!q || g < q->gpa || g - q->gpa >= q->bytes) {
+                // the last slot starting at or below g
+                auto it = std::upper_bound(sl.begin(), sl.end(), g,
+                                           [](uint64_t x, const VmHost::Slot *r) { return x < r->gpa; });
+                q = it == sl.begin() ? nullptr : *(it - 1);
+            }
+            if ((g & 0xFFF) || !q || g - q->gpa >= q->bytes)
+                return dv_fail(-EINVAL, "pool frame %#llx is unaligned or outside every memslot", (unsigned long long)g);
+            hpa[k] = q->off + (g - q->gpa);
         }
     }
     Workspace *w = get_ws(c, s);
-    const uint64_t words = 14 * n + 3 + 2 * n_pool + 8;
+    // hash sets of at least twice the entries they can hold
+    const uint64_t m = std::min<uint64_t>(4 * n, n_pool);
+    auto log2_for = [](uint64_t entries) {
+        uint32_t l = 6;
+        while ((1ull << l) < 2 * entries) ++l;
+        return l;
+    };
+    const uint32_t tl = log2_for(m + 1), pl = log2_for(n);
+    const uint64_t T = 1ull << tl, P = 1ull << pl;
+    const uint64_t words = T + m + P + P + 4 + m + 2 * n_pool;
     int rc;
     if ((rc = grow(c, w, w->map_buf, w->map_cap, words, "map buffers"))) return rc;
     uint64_t *b = w->map_buf;
@@ -564,14 +583,18 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     a.res = res;
     a.n_used = n_used;
     a.n_pool = n_pool;
-    a.keys = b;
-    a.keys_sorted = b + 4 * n;
-    a.uniq = b + 8 * n;
-    a.mkeys = b + 12 * n;
-    a.mkeys_sorted = b + 13 * n;
-    a.sc = b + 14 * n;
-    a.pool_gpa = b + 14 * n + 3;
-    a.pool_hpa = b + 14 * n + 3 + n_pool;
+    a.tset = b;  // tset, tkeys, pkey: cleared to ~0 together; pidx, sc: to 0
+    a.tset_log2 = tl;
+    a.tkeys = b + T;
+    a.m = m;
+    a.rank = m <= kMapRankMax;
+    a.pkey = b + T + m;
+    a.pidx = b + T + m + P;
+    a.pset_log2 = pl;
+    a.sc = b + T + m + 2 * P;
+    a.tkeys_sorted = b + T + m + 2 * P + 4;
+    a.pool_gpa = b + T + 2 * m + 2 * P + 4;
+    a.pool_hpa = b + T + 2 * m + 2 * P + 4 + n_pool;
     a.temp = nullptr;
     size_t need = 0;
     a.temp_query = &need;
@@ -595,10 +618,6 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
                               hipMemcpyHostToDevice, s));
         if (!w->map_ev) HIPCHK(hipEventCreateWithFlags(&w->map_ev, hipEventDisableTiming));
         HIPCHK(hipEventRecord(w->map_ev, s));
-    }
-    if (n == 0) {
-        HIPCHK(hipMemsetAsync(n_used, 0, sizeof(uint64_t), s));
-        return 0;
     }
     HIPCHK(launch_map(s, a));  // only arena bytes change: captured batch graphs stay valid
     return 0;

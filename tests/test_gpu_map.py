@@ -135,11 +135,13 @@ def test_map_matches_oracle(name):
         ctx.close()
 
 
-def test_map_large_batch():
-    """2^17 maps in one call (spans many sort tiles), half into a 4 GiB region
-    the tables do not cover yet, half onto mapped pages."""
-    w = wl("mix2m")
-    log("map large")
+@pytest.mark.parametrize("name,n_pool", [("mix2m", 4096), ("lvl5_1g", 40000)])
+def test_map_large_batch(name, n_pool):
+    """2^17 maps in one call, half into a 4 GiB region the tables do not cover
+    yet, half onto mapped pages.  The small pool has the new tables ordered in
+    LDS tiles, the large one (over 2^14 frames) by the library radix sort."""
+    w = wl(name)
+    log(f"map large {name} pool {n_pool}")
     rng = np.random.default_rng(5)
     from oracle.oracle import MAP_DTYPE
     p = w.procs[0]
@@ -150,7 +152,7 @@ def test_map_large_batch():
     m["gva"][n // 2:] = p.leaf_va[rng.integers(0, len(p.leaf_va), n // 2)] & ~np.uint64(0xFFF)
     m["gpa"] = rng.integers(0, w.vms[p.vm].mem_bytes >> 12, n).astype(np.uint64) << np.uint64(12)
     m["flags"] = rng.integers(0, 2, n)
-    pool = pins.free_frames(w, p.vm, 4096, rng)
+    pool = pins.free_frames(w, p.vm, n_pool, rng)
     o = Oracle.from_workload(w)
     ctx = new_ctx()
     try:
