@@ -48,6 +48,29 @@
  * Page tables live inside guest-physical memory and are read through the
  * memslots.  Request `host` fields are byte offsets into one host pool.
  * Everything is sequential and in request order.
+ *
+ * A VM may instead have its guest-physical space described by a 4-level
+ * extended page table (EPT) kept in its arena: the translation is then
+ * finished by a second software walk, as the paper prescribes for
+ * hypervisors other than KVM (section 4.2; EPT itself in section 2.2).  The
+ * readings that shape that walk:
+ *   - EPT entries: bits 2:0 read, write, execute; not present when all three
+ *     are 0; address bits 51:12; bit 7 makes a level-3 / level-2 entry a
+ *     1 GiB / 2 MiB leaf; bits 63:52, the ignore-PAT bit and the accessed /
+ *     dirty bits are ignored, and this walker sets no EPT bit;
+ *   - misconfigured (EPT_MISCONFIG): write without read; any of bits 7:3 in
+ *     a table entry; a leaf memory type (bits 5:3) of 2, 3 or 7; a large
+ *     leaf with any of bits [shift-1:12] set; a table or page that does not
+ *     lie inside the arena;
+ *   - EPT_VIOLATION: a not-present entry, a guest-physical address at or
+ *     above 2^48, or a missing permission: the read and write bits are
+ *     AND-ed over the walk; a guest page-table frame needs both (the walk
+ *     may write A/D bits into it, and hardware with EPT A/D enabled treats
+ *     such accesses as writes), a data page needs read when copied to the
+ *     host and write when copied into the guest;
+ *   - per level, top-down: present, then misconfiguration; permissions once
+ *     the leaf is reached; the reported level is the guest level whose
+ *     frame failed (0 for the data page), as for a missing memslot.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -63,6 +86,8 @@ enum {
     ORC_NONCANONICAL = 6,
     ORC_INVALID = 7,
     ORC_NO_POOL = 8,
+    ORC_EPT_VIOLATION = 9,
+    ORC_EPT_MISCONFIG = 10,
 };
 
 #define ORC_ADDR_MASK 0x000FFFFFFFFFF000ull
@@ -80,6 +105,8 @@ typedef struct {
     uint64_t arena_bytes;
     const orc_slot *slots;
     uint32_t nslots;
+    int has_ept;             /* translate through the EPT at ept_root instead of the memslots */
+    uint64_t ept_root;       /* arena offset of the EPT's level-4 table */
 } orc_vm;
 
 typedef struct {
@@ -160,6 +187,20 @@ void orc_set_vm(orc_state *s, uint32_t vm, uint8_t *arena, uint64_t arena_bytes,
     s->vms[vm].nslots = nslots;
 }
 
+/* Give a VM an EPT rooted at arena offset `root` (4 KiB aligned, inside the
+ * arena), or take it away with root = ~0.  Returns -1 on a bad root. */
+int orc_set_ept(orc_state *s, uint32_t vm, uint64_t root) {
+    orc_vm *v = &s->vms[vm];
+    if (root == ~0ull) {
+        v->has_ept = 0;
+        return 0;
+    }
+    if ((root & 0xFFF) || root >= v->arena_bytes || v->arena_bytes - root < 4096) return -1;
+    v->has_ept = 1;
+    v->ept_root = root;
+    return 0;
+}
+
 void orc_set_proc(orc_state *s, uint32_t asid, uint32_t vm, uint64_t cr3, uint32_t levels) {
     s->procs[asid].vm = vm;
     s->procs[asid].cr3 = cr3;
@@ -193,6 +234,55 @@ static uint64_t load64(const uint8_t *p) {
     return v;
 }
 
+/* ------------------------------------------------------------------ EPT -- */
+#define ORC_NEED_R 1u
+#define ORC_NEED_W 2u
+#define ORC_NEED_TABLE (ORC_NEED_R | ORC_NEED_W)
+
+/* 1 if the 4 KiB page at arena offset `off` lies inside the arena. */
+static int in_arena(const orc_vm *v, uint64_t off) {
+    return off < v->arena_bytes && v->arena_bytes - off >= 4096;
+}
+
+/* GPA -> arena offset by walking the VM's EPT (see the header comment). */
+static uint32_t ept_walk(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t *hpa) {
+    if (gpa >> 48) return ORC_EPT_VIOLATION;
+    uint64_t table = v->ept_root;
+    int can_r = 1, can_w = 1;
+    for (int lvl = 4; lvl >= 1; lvl--) {
+        uint32_t shift = 12 + 9 * (uint32_t)(lvl - 1);
+        uint64_t e = load64(v->arena + table + 8 * ((gpa >> shift) & 511));
+        if ((e & 7) == 0) return ORC_EPT_VIOLATION;
+        if ((e & 3) == 2) return ORC_EPT_MISCONFIG;
+        can_r &= (int)(e & 1);
+        can_w &= (int)((e >> 1) & 1);
+        int leaf = lvl == 1 || ((lvl == 3 || lvl == 2) && (e & 0x80));
+        if (!leaf) {
+            if (e & 0xF8) return ORC_EPT_MISCONFIG;
+            table = e & ORC_ADDR_MASK;
+            if (!in_arena(v, table)) return ORC_EPT_MISCONFIG;
+            continue;
+        }
+        uint64_t mt = (e >> 3) & 7;
+        if (mt == 2 || mt == 3 || mt == 7) return ORC_EPT_MISCONFIG;
+        uint64_t size = 1ull << shift;
+        if (e & (size - 1) & ~0xFFFull) return ORC_EPT_MISCONFIG;
+        uint64_t h = (e & ORC_ADDR_MASK) | (gpa & (size - 1));
+        if (!in_arena(v, h & ~0xFFFull)) return ORC_EPT_MISCONFIG;
+        if (((need & ORC_NEED_R) && !can_r) || ((need & ORC_NEED_W) && !can_w)) return ORC_EPT_VIOLATION;
+        *hpa = h;
+        return ORC_OK;
+    }
+    return ORC_EPT_VIOLATION;   /* not reached */
+}
+
+/* GPA -> arena offset for an access that needs `need`: the EPT walk, or the
+ * memslots when the VM has no EPT. */
+static uint32_t gpa_to_hpa(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t *hpa) {
+    if (v->has_ept) return ept_walk(v, gpa, need, hpa);
+    return slot_lookup(v, gpa, hpa) ? ORC_OK : ORC_NO_MEMSLOT;
+}
+
 /* ----------------------------------------------------------------- walk -- */
 typedef struct {
     uint32_t code;
@@ -223,8 +313,9 @@ static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write,
          * accessed-bit path and grants every permission */
         uint64_t pdpt = p->cr3 & 0xFFFFFFE0ull;
         uint64_t thpa;
-        if (!slot_lookup(v, pdpt, &thpa)) {
-            w->code = ORC_NO_MEMSLOT;
+        uint32_t c = gpa_to_hpa(v, pdpt, ORC_NEED_TABLE, &thpa);
+        if (c != ORC_OK) {
+            w->code = c;
             w->level = 3;
             return;
         }
@@ -246,8 +337,9 @@ static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write,
         uint32_t shift = 12 + 9 * (uint32_t)(lvl - 1);
         uint64_t idx = (gva >> shift) & 511;
         uint64_t thpa;
-        if (!slot_lookup(v, table, &thpa)) {
-            w->code = ORC_NO_MEMSLOT;
+        uint32_t c = gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);
+        if (c != ORC_OK) {
+            w->code = c;
             w->level = (uint32_t)lvl;
             return;
         }
@@ -303,8 +395,9 @@ static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write,
         w->level = w->leaf_level;
         return;
     }
-    if (!slot_lookup(v, w->gpa, &w->hpa)) {
-        w->code = ORC_NO_MEMSLOT;
+    uint32_t c = gpa_to_hpa(v, w->gpa, write ? ORC_NEED_W : ORC_NEED_R, &w->hpa);
+    if (c != ORC_OK) {
+        w->code = c;
         w->level = 0;
         w->hpa = 0;
         return;
@@ -636,6 +729,7 @@ int64_t orc_map_pages(orc_state *s, uint32_t asid, const orc_map *maps, uint64_t
     const orc_proc *p = &s->procs[asid];
     orc_vm *v = &s->vms[p->vm];
     const int pae = p->levels == 3;
+    if (v->has_ept) return -2;   /* mapping pages is defined for memslot VMs only */
     uint64_t *pool_hpa = (uint64_t *)malloc((n_pool ? n_pool : 1) * sizeof(uint64_t));
     for (uint64_t k = 0; k < n_pool; k++)
         if ((pool[k] & 0xFFF) || !slot_lookup(v, pool[k], &pool_hpa[k])) {

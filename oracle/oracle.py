@@ -17,7 +17,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 CODES = {
     "OK": 0, "NOT_PRESENT": 1, "RESERVED": 2, "PROT_USER": 3, "PROT_WRITE": 4,
-    "NO_MEMSLOT": 5, "NONCANONICAL": 6, "INVALID": 7, "NO_POOL": 8,
+    "NO_MEMSLOT": 5, "NONCANONICAL": 6, "INVALID": 7, "NO_POOL": 8, "EPT_VIOLATION": 9, "EPT_MISCONFIG": 10,
 }
 RESULT_DTYPE = np.dtype([("bytes_done", "<u8"), ("fault_gva", "<u8"), ("code", "<u4"), ("level", "<u2"),
                          ("pad", "<u2")])
@@ -55,6 +55,8 @@ def _load(path: str | None = None):
         lib.orc_free.argtypes = [vp]
         lib.orc_set_vm.argtypes = [vp, u32, vp, u64, vp, u32]
         lib.orc_set_proc.argtypes = [vp, u32, u32, u64, u32]
+        lib.orc_set_ept.argtypes = [vp, u32, u64]
+        lib.orc_set_ept.restype = ctypes.c_int
         lib.orc_set_pool.argtypes = [vp, vp, u64]
         lib.orc_ad_sets.argtypes = [vp]
         lib.orc_ad_sets.restype = u64
@@ -79,9 +81,10 @@ class Oracle:
     ``asid`` values are positions in the process list given at construction.
     """
 
-    def __init__(self, arenas, slots, procs, pool, lib_path: str | None = None):
+    def __init__(self, arenas, slots, procs, pool, lib_path: str | None = None, ept=None):
         """arenas: list of uint8 arrays; slots: list of SLOT_DTYPE arrays;
-        procs: list of (vm, cr3, levels); pool: uint8 array."""
+        procs: list of (vm, cr3, levels); pool: uint8 array; ept: per VM the
+        arena offset of its EPT root, or None for memslot translation."""
         lib = _load(lib_path)
         self._lib = lib
         self.arenas = [np.ascontiguousarray(a) for a in arenas]
@@ -97,6 +100,9 @@ class Oracle:
             lib.orc_set_vm(self._h, i, a.ctypes.data, a.size, s.ctypes.data, len(s))
         for i, (vm, cr3, levels) in enumerate(self.procs):
             lib.orc_set_proc(self._h, i, vm, cr3, levels)
+        for i, root in enumerate(ept or []):
+            if root is not None and lib.orc_set_ept(self._h, i, int(root)) != 0:
+                raise ValueError(f"bad EPT root {root:#x} for VM {i}")
         lib.orc_set_pool(self._h, pool.ctypes.data, pool.size)
 
     @classmethod
@@ -106,7 +112,7 @@ class Oracle:
         if pool is None:
             pool = wl.pool_image()
         return cls(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], pool,
-                   lib_path=lib_path)
+                   lib_path=lib_path, ept=[getattr(v, "ept_root", None) for v in wl.vms])
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -158,6 +164,8 @@ class Oracle:
         res = np.zeros(len(m), RESULT_DTYPE)
         used = self._lib.orc_map_pages(self._h, asid, m.ctypes.data, len(m), pool.ctypes.data if len(pool) else None,
                                        len(pool), res.ctypes.data)
+        if used == -2:
+            raise ValueError("mapping pages is defined for memslot VMs only")
         if used < 0:
             raise ValueError("a pool frame is unaligned or outside every memslot")
         return res, int(used)

@@ -50,7 +50,8 @@ def build_golden(world, lib_path=None, pool_bytes=0x4000):
         slots[i] = (H(s["gpa"]), H(s["bytes"]), H(s["arena_off"]))
     pool = np.zeros(pool_bytes, np.uint8)
     gen.fill_bytes(pool, 78, 4)
-    o = Oracle([arena], [slots], [(0, H(world["cr3"]), world["levels"])], pool, lib_path=lib_path)
+    ept = [H(world["ept_root"])] if "ept_root" in world else None
+    o = Oracle([arena], [slots], [(0, H(world["cr3"]), world["levels"])], pool, lib_path=lib_path, ept=ept)
     return o, arena, pool
 
 
@@ -80,7 +81,7 @@ def check_golden(lib_path=None):
                 if _u64(arena, H(e["arena_off"])) != H(e["value"]):
                     fails.append(f"{w['name']} A/D at {e['arena_off']}: {hex(_u64(arena, H(e['arena_off'])))}"
                                  f" expected {e['value']}")
-        for c in w["copies"]:
+        for c in w.get("copies", []):
             o, arena, pool = build_golden(w, lib_path)
             a0, p0 = arena.copy(), pool.copy()
             req = np.zeros(1, REQ_DTYPE)
@@ -644,4 +645,104 @@ def small_specs():
         "pae": gen.spec("C2", levels=3, mem_bytes=64 * MiB, n_requests=400, n_slots=6, len_hi=40000, seed=17),
         "pae_prot": gen.spec("C2", levels=3, mem_bytes=16 * MiB, n_requests=300, p_readonly=0.1,
                              p_supervisor=0.05, p_upper_np=0.1, len_hi=20000, seed=18),
+        # guest-physical space described by an EPT (a second software walk) instead of memslots
+        "ept": gen.spec("C2", mem_bytes=64 * MiB, n_requests=400, n_slots=6, len_hi=40000, seed=21, ept=True),
+        "ept_faults": gen.spec("C2", mem_bytes=64 * MiB, n_requests=600, n_slots=6, len_hi=40000, seed=22,
+                               ept=True, ept_np=0.03, ept_ro=0.05, ept_mis=0.02),
+        "ept_lvl5": gen.spec("C5", n_vms=2, mem_bytes=32 * MiB, mix=(0.6, 0.4, 0.0), n_requests=300,
+                             len_hi=100000, seed=23, ept=True, ept_np=0.02, ept_ro=0.04, ept_mis=0.02),
+        "ept_pae": gen.spec("C2", levels=3, mem_bytes=64 * MiB, n_requests=400, n_slots=6, len_hi=40000, seed=24,
+                            ept=True, ept_np=0.03, ept_ro=0.05, ept_mis=0.02),
+        "ept_1g": gen.spec("C5", n_vms=1, mem_bytes=3 * GiB // 2, n_slots=1, mapped_frac=0.7,
+                           mix=(0.02, 0.02, 0.96), n_requests=200, len_hi=100000, seed=25, ept=True, ept_align=GiB),
     }
+
+
+# ------------------------------------------------------------------ EPT --
+def check_ept_equivalence(wl, lib_path=None, sample=4000):
+    """A world whose EPT maps every slot exactly as its memslots do must give
+    the same results, fault list, arena and pool bytes, and translations, in
+    EPT mode as in memslot mode."""
+    assert wl.spec.ept and wl.spec.ept_np == wl.spec.ept_ro == wl.spec.ept_mis == 0
+    fails = []
+    e = Oracle.from_workload(wl, lib_path=lib_path)
+    m = Oracle([wl.arena_image(v) for v in range(len(wl.vms))], [v.slots for v in wl.vms],
+               [(p.vm, p.cr3, p.levels) for p in wl.procs], wl.pool_image(), lib_path=lib_path)
+    rng = np.random.default_rng(7)
+    for p in wl.procs:
+        g = p.leaf_va[rng.integers(0, len(p.leaf_va), min(sample, len(p.leaf_va)))]
+        g = g + (rng.integers(0, 4096, len(g)).astype(np.uint64))
+        for fl in (0, XLAT_WRITE | XLAT_SET_AD):
+            a, b = e.translate(p.asid, g, fl), m.translate(p.asid, g, fl)
+            if not np.array_equal(a, b):
+                i = int(np.nonzero(a != b)[0][0])
+                fails.append(f"asid {p.asid} gva {hex(int(g[i]))} flags {fl}: EPT {a[i]} memslots {b[i]}")
+                break
+    re_, fe = e.batch(wl.requests)
+    rm, fm = m.batch(wl.requests)
+    if not np.array_equal(re_, rm) or not np.array_equal(fe, fm):
+        fails.append("batch results or fault list differ between EPT and memslot modes")
+    for v, (x, y) in enumerate(zip(e.arenas, m.arenas)):
+        if not np.array_equal(x, y):
+            fails.append(f"vm {v}: arenas differ between EPT and memslot modes")
+    if not np.array_equal(e.pool, m.pool):
+        fails.append("pools differ between EPT and memslot modes")
+    return fails
+
+
+def check_ept_faults(wl, lib_path=None):
+    """With EPT leaves made not present, read-only or misconfigured, every
+    data page's outcome follows from the leaf that holds its GPA (taken from
+    the generator's list, not from a walk): not present -> EPT_VIOLATION,
+    misconfigured -> EPT_MISCONFIG, read-only -> EPT_VIOLATION on writes into
+    the guest only; every other page copies."""
+    from workload.gen import EPT_LEAF_MIS, EPT_LEAF_NP, EPT_LEAF_RO
+    fails = []
+    o = Oracle.from_workload(wl, lib_path=lib_path)
+    res, _ = o.batch_results(wl.requests)
+    kinds = {}
+    for v in wl.vms:
+        lf = v.ept_leaf
+        kinds[v.vm] = lf
+    seen = {"viol": 0, "mis": 0, "ok_pages": 0, "table_level": 0}
+    for i, (rq, r) in enumerate(zip(wl.requests, res)):
+        p = wl.procs[int(rq["asid"])]
+        lf = kinds[p.vm]
+        wr = int(rq["dir"]) == 1
+        end = int(rq["gva"]) + int(rq["len"])
+        stop = int(r["fault_gva"]) if r["code"] != 0 else end
+        gv = [max(pg, int(rq["gva"])) for pg in range(int(rq["gva"]) & ~0xFFF, stop, 4096)]
+        gv = [g for g in gv if g < stop]  # the pages copied before the fault
+        if r["code"] != 0 and r["level"] == 0 and r["code"] in (CODES["EPT_VIOLATION"], CODES["EPT_MISCONFIG"]):
+            gv.append(int(r["fault_gva"]))
+        elif r["code"] in (CODES["EPT_VIOLATION"], CODES["EPT_MISCONFIG"]):
+            seen["table_level"] += 1
+        if not gv:
+            continue
+        x = o.translate(p.asid, np.array(gv, np.uint64), XLAT_WRITE if wr else 0)
+        for k, g in enumerate(gv):
+            gpa = int(x["gpa"][k])
+            j = int(np.searchsorted(lf["gpa"], np.uint64(gpa), side="right")) - 1
+            if j < 0 or gpa - int(lf["gpa"][j]) >= (1 << int(lf["shift"][j])):
+                fails.append(f"request {i}: GPA {hex(gpa)} is in no EPT leaf")
+                continue
+            kind = int(lf["kind"][j])
+            exp = CODES["EPT_VIOLATION"] if kind == EPT_LEAF_NP or (kind == EPT_LEAF_RO and wr) else \
+                CODES["EPT_MISCONFIG"] if kind == EPT_LEAF_MIS else 0
+            last = k == len(gv) - 1 and r["code"] != 0 and r["level"] == 0
+            got = int(r["code"]) if last else 0
+            if x["level"][k] != 0 or (x["code"][k] != 0 and x["code"][k] not in (CODES["EPT_VIOLATION"],
+                                                                                 CODES["EPT_MISCONFIG"])):
+                if last:
+                    fails.append(f"request {i}: page {hex(g)} faults above the data page")
+                continue
+            if got != exp:
+                fails.append(f"request {i} page {hex(g)} (GPA {hex(gpa)}, leaf kind {kind}, write {wr}): "
+                             f"code {got} expected {exp}")
+                break
+            seen["viol" if exp == CODES["EPT_VIOLATION"] else "mis" if exp else "ok_pages"] += 1
+        if len(fails) > 5:
+            break
+    if not fails and (seen["viol"] == 0 or seen["mis"] == 0 or seen["ok_pages"] == 0):
+        fails.append(f"the world exercises too little: {seen}")
+    return fails

@@ -60,6 +60,22 @@ MUTANTS = {
     "map_new_table_not_zeroed": ("    for (uint64_t k = 0; k < nt; k++) memset(v->arena + pool_hpa[k], 0, 4096);\n", ""),
     "map_pae_root_full_bits": ("(root_pae ? ORC_P :", "(root_pae ? (ORC_P | ORC_RW | ORC_US) :"),
     "map_large_leaf_ignored": ("if (rsvd || (!(pae && lvl == 3) && (e & ORC_PS))) {", "if (rsvd) {"),
+    # the EPT walk (a second walk for the guest-physical space)
+    "ept_index_mask_8bit": ("uint64_t e = load64(v->arena + table + 8 * ((gpa >> shift) & 511));",
+                            "uint64_t e = load64(v->arena + table + 8 * ((gpa >> shift) & 255));"),
+    "ept_write_without_read_ok": ("if ((e & 3) == 2) return ORC_EPT_MISCONFIG;", "if (0) return ORC_EPT_MISCONFIG;"),
+    "ept_table_bits_unchecked": ("if (e & 0xF8) return ORC_EPT_MISCONFIG;", "if (0) return ORC_EPT_MISCONFIG;"),
+    "ept_memtype_unchecked": ("if (mt == 2 || mt == 3 || mt == 7)", "if (mt == 7)"),
+    "ept_large_leaf_bits_unchecked": ("if (e & (size - 1) & ~0xFFFull) return ORC_EPT_MISCONFIG;",
+                                      "if (0) return ORC_EPT_MISCONFIG;"),
+    "ept_write_not_anded": ("can_w &= (int)((e >> 1) & 1);", "can_w = (int)((e >> 1) & 1);"),
+    "ept_gpa_limit_dropped": ("if (gpa >> 48) return ORC_EPT_VIOLATION;", "if (0) return ORC_EPT_VIOLATION;"),
+    "ept_tables_need_read_only": ("uint32_t c = gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);",
+                                  "uint32_t c = gpa_to_hpa(v, table, ORC_NEED_R, &thpa);"),
+    "ept_data_always_read": ("gpa_to_hpa(v, w->gpa, write ? ORC_NEED_W : ORC_NEED_R, &w->hpa)",
+                             "gpa_to_hpa(v, w->gpa, ORC_NEED_R, &w->hpa)"),
+    "ept_large_leaf_offset_dropped": ("uint64_t h = (e & ORC_ADDR_MASK) | (gpa & (size - 1));",
+                                      "uint64_t h = (e & ORC_ADDR_MASK) | (gpa & 0xFFFull);"),
     "copy_direction_swapped": ("        if (to_guest)\n            memcpy(g, h, hi - lo);",
                                "        if (!to_guest)\n            memcpy(g, h, hi - lo);"),
     "ad_before_fault_check": ("        if (w.code != ORC_OK) {\n            res->bytes_done",
@@ -104,6 +120,8 @@ def test_pins_catch_mutant(tmp_path, name):
         lambda: pins.check_golden_maps(lib),
         lambda: pins.check_map_properties(_small("mix2m"), lib),
         lambda: pins.check_map_properties(_small("pae"), lib),
+        lambda: pins.check_ept_equivalence(_small("ept"), lib),
+        lambda: pins.check_ept_faults(_small("ept_faults"), lib),
     ]
     for c in checks:
         if c():

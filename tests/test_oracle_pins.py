@@ -96,3 +96,31 @@ def test_results_only_mode_matches_full_batch(name):
     only = o.batch_results(w.requests)
     assert np.array_equal(full[0], only[0]) and np.array_equal(full[1], only[1])
     assert all(np.array_equal(a, b) for a, b in zip(a0, o.arenas)) and np.array_equal(p0, o.pool)
+
+
+# ------------------------------------------------------------------ EPT --
+@pytest.mark.parametrize("name", ["ept", "ept_1g", "c1", "multi_vm", "lvl5", "pae"])
+def test_ept_equals_memslots(name):
+    """An EPT that maps every slot as the memslots do changes nothing."""
+    sp = SPECS[name] if SPECS[name].ept else SPECS[name].replace(ept=True)
+    assert pins.check_ept_equivalence(gen.make_workload(sp)) == []
+
+
+@pytest.mark.parametrize("name", ["ept_faults", "ept_lvl5", "ept_pae"])
+def test_ept_faults_follow_the_leaves(name):
+    assert pins.check_ept_faults(wl(name)) == []
+
+
+def test_ept_root_checked_and_map_pages_refused():
+    import numpy as np
+    from oracle import Oracle
+    from oracle.oracle import MAP_DTYPE
+    w = wl("ept")
+    v = w.vms[0]
+    for bad in (v.ept_root + 8, v.arena_bytes, v.arena_bytes - 2048):
+        with pytest.raises(ValueError):
+            Oracle([np.zeros(v.arena_bytes, np.uint8)], [v.slots], [(0, w.procs[0].cr3, 4)], w.pool_image(),
+                   ept=[bad])
+    o = Oracle.from_workload(w)
+    with pytest.raises(ValueError):
+        o.map_pages(0, np.zeros(1, MAP_DTYPE), [])

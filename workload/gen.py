@@ -150,6 +150,12 @@ class Spec:
     p_readonly: float = 0.0     # present leaves with R/W = 0
     p_supervisor: float = 0.0   # present leaves with U/S = 0
     p_upper_np: float = 0.0     # upper-level (non-leaf) entries not present
+    # a 4-level EPT for the guest-physical space (instead of memslot translation)
+    ept: bool = False
+    ept_align: int = 2 * MiB    # slots are placed in the arena congruent to their GPA modulo this
+    ept_np: float = 0.0         # EPT leaves not present
+    ept_ro: float = 0.0         # EPT leaves read-only
+    ept_mis: float = 0.0        # EPT leaves misconfigured (write without read, or memory type 2)
 
     def replace(self, **kw) -> "Spec":
         return dataclasses.replace(self, **kw)
@@ -189,6 +195,10 @@ class VMImage:
     pt_gfn: np.ndarray          # uint64 GPA frame numbers of page-table frames
     pt_data: np.ndarray         # (n, 512) uint64 table contents
     key: int
+    ept_root: int | None = None     # arena offset of the EPT's level-4 table
+    ept_off: np.ndarray | None = None   # arena offsets of the EPT table frames
+    ept_data: np.ndarray | None = None  # (n, 512) uint64 EPT table contents
+    ept_leaf: np.ndarray | None = None  # the EPT leaves as generated: gpa, shift, kind (EPT_LEAF_*)
 
 
 @dataclass
@@ -227,6 +237,9 @@ class Workload:
             out = np.empty(v.arena_bytes, np.uint8)
         fill_bytes(out, self.seed, v.key)
         self.overlay_tables(vm, out)
+        if v.ept_root is not None:
+            out.reshape(-1, PAGE)[(v.ept_off >> np.uint64(12)).astype(np.int64)] = \
+                v.ept_data.view(np.uint8).reshape(-1, PAGE)
         return out
 
     def overlay_tables(self, vm: int, arena: np.ndarray) -> None:
@@ -276,7 +289,7 @@ def gpa_to_arena(slots: np.ndarray, gpa: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # generation
 # ---------------------------------------------------------------------------
-def _memslots(rng, mem_bytes: int, n_slots: int):
+def _memslots(rng, mem_bytes: int, n_slots: int, align: int = 0):
     nfr = mem_bytes // PAGE
     n_slots = max(1, min(n_slots, nfr))
     cuts = np.sort(rng.choice(np.arange(1, nfr, dtype=np.int64), n_slots - 1, replace=False)) if n_slots > 1 else \
@@ -289,7 +302,10 @@ def _memslots(rng, mem_bytes: int, n_slots: int):
     arena_off = np.zeros(n_slots, np.uint64)
     pos = np.uint64(0)
     for k, s in enumerate(order):
-        pos += gaps[k]
+        if align:  # congruent to the GPA modulo `align`, so large EPT leaves can map the slot
+            pos += np.uint64((int(gpa[s]) - int(pos)) % align)
+        else:
+            pos += gaps[k]
         arena_off[s] = pos
         pos += size[s]
     arena_bytes = int(pos + gaps[-1])
@@ -394,6 +410,73 @@ def _layout_process(rng, sp: Spec, n1: int, n2: int, n4: int):
     return va, lvl, np.array(vmas, np.uint64).reshape(-1, 2)
 
 
+_EPT_RWX, _EPT_WB = 7, 6 << 3
+EPT_LEAF_OK, EPT_LEAF_NP, EPT_LEAF_RO, EPT_LEAF_MIS = 0, 1, 2, 3
+EPT_LEAF_DTYPE = np.dtype([("gpa", "<u8"), ("shift", "u1"), ("kind", "u1")])
+
+
+def _make_ept(rng, sp: Spec, slots: np.ndarray, arena_bytes: int):
+    """A 4-level EPT mapping every slot's GPAs to the slot's arena bytes, with
+    the largest leaf (1 GiB, 2 MiB, 4 KiB) that both sides' alignment allows;
+    its tables are placed after the guest memory.  Returns (root, offsets,
+    contents, new arena size)."""
+    g_l, h_l, lv_l = [], [], []
+    for sl in slots:
+        g, end, h = int(sl["gpa"]), int(sl["gpa"] + sl["bytes"]), int(sl["arena_off"])
+        while g < end:
+            for lv, size in ((3, GiB), (2, 2 * MiB), (1, PAGE)):
+                if g % size == 0 and h % size == 0 and g + size <= end:
+                    break
+            if lv == 1:  # a run of 4 KiB leaves up to the next 2 MiB boundary (or the slot end)
+                stop = min(end, (g // (2 * MiB) + 1) * 2 * MiB)
+                n = (stop - g) // PAGE
+                g_l.append(np.uint64(g) + (np.arange(n, dtype=np.uint64) << np.uint64(12)))
+                h_l.append(np.uint64(h) + (np.arange(n, dtype=np.uint64) << np.uint64(12)))
+                lv_l.append(np.ones(n, np.uint8))
+                g, h = stop, h + (stop - g)
+            else:
+                g_l.append(np.array([g], np.uint64))
+                h_l.append(np.array([h], np.uint64))
+                lv_l.append(np.array([lv], np.uint8))
+                g, h = g + size, h + size
+    lg, lh, ll = np.concatenate(g_l), np.concatenate(h_l), np.concatenate(lv_l)
+    # tables: level L holds entries for gpa >> (12 + 9 (L-1)); its id is gpa >> (12 + 9 L)
+    ids = {4: np.zeros(1, np.uint64)}
+    need = {1: lg[ll == 1] >> np.uint64(21), 2: lg[ll <= 2] >> np.uint64(30), 3: lg >> np.uint64(39)}
+    for L in (3, 2, 1):
+        ids[L] = np.unique(need[L])
+    n_tab = sum(len(ids[L]) for L in ids)
+    base = (arena_bytes + PAGE - 1) // PAGE * PAGE
+    off, o = {}, base
+    for L in (4, 3, 2, 1):
+        off[L] = np.uint64(o) + (np.arange(len(ids[L]), dtype=np.uint64) << np.uint64(12))
+        o += len(ids[L]) * PAGE
+    data = {L: np.zeros((len(ids[L]), 512), np.uint64) for L in ids}
+    for L in (3, 2, 1):  # link tables at level L from level L+1
+        parent = np.searchsorted(ids[L + 1], ids[L] >> np.uint64(9))
+        data[L + 1][parent, (ids[L] & np.uint64(511)).astype(np.int64)] = off[L] | np.uint64(_EPT_RWX)
+    ent = lh | np.uint64(_EPT_RWX | _EPT_WB) | np.where(ll > 1, np.uint64(0x80), np.uint64(0))
+    r = rng.random(len(ent))
+    truth = np.zeros(len(ent), EPT_LEAF_DTYPE)
+    truth["gpa"], truth["shift"] = lg, (12 + 9 * (ll.astype(np.int64) - 1)).astype(np.uint8)
+    truth["kind"] = np.select([r < sp.ept_np, r < sp.ept_np + sp.ept_ro, r < sp.ept_np + sp.ept_ro + sp.ept_mis],
+                              [EPT_LEAF_NP, EPT_LEAF_RO, EPT_LEAF_MIS], EPT_LEAF_OK)
+    ent = np.where(r < sp.ept_np, np.uint64(0), ent)
+    ent = np.where((r >= sp.ept_np) & (r < sp.ept_np + sp.ept_ro), ent & ~np.uint64(2), ent)
+    mis = (r >= sp.ept_np + sp.ept_ro) & (r < sp.ept_np + sp.ept_ro + sp.ept_mis)
+    alt = rng.random(len(ent)) < 0.5
+    ent = np.where(mis & alt, ent & ~np.uint64(1), ent)                                   # write without read
+    ent = np.where(mis & ~alt, (ent & ~np.uint64(0x38)) | np.uint64(2 << 3), ent)         # memory type 2
+    for L in (3, 2, 1):
+        m = ll == L
+        pos = np.searchsorted(ids[L], lg[m] >> np.uint64(12 + 9 * L))
+        data[L][pos, ((lg[m] >> np.uint64(12 + 9 * (L - 1))) & np.uint64(511)).astype(np.int64)] = ent[m]
+    offs = np.concatenate([off[L] for L in (4, 3, 2, 1)])
+    cont = np.concatenate([data[L] for L in (4, 3, 2, 1)])
+    order = np.argsort(truth["gpa"], kind="stable")
+    return int(off[4][0]), offs, cont, o, truth[order]
+
+
 def _rand_u64(rng, n):
     return rng.integers(0, 2**63, n, dtype=np.uint64) << np.uint64(1) | rng.integers(0, 2, n, dtype=np.uint64)
 
@@ -404,7 +487,7 @@ def make_workload(sp: Spec, requests: bool = True) -> Workload:
     n1, n2, n4 = _split_counts(sp)
     vms, procs = [], []
     for vm in range(sp.n_vms):
-        slots, arena_bytes = _memslots(rng, sp.mem_bytes, sp.n_slots)
+        slots, arena_bytes = _memslots(rng, sp.mem_bytes, sp.n_slots, sp.ept_align if sp.ept else 0)
         nfr = sp.mem_bytes // PAGE
         free = np.ones(nfr, bool)
         lay = []
@@ -529,8 +612,12 @@ def make_workload(sp: Spec, requests: bool = True) -> Workload:
                 cr3 = (root << 12) | int(rng.integers(0, 4096))   # low 12 bits ignored by the walk
             procs.append(ProcTruth(asid, vm, sp.levels, cr3, va, lvl, frames[p], present, ent, t_gfn, t_idx,
                                    {L: (per[L], gfns[L]) for L in per}, vmas))
-        vms.append(VMImage(vm, sp.mem_bytes, slots, arena_bytes,
-                           np.concatenate(pt_gfn_all), np.concatenate(pt_data_all), vm))
+        img = VMImage(vm, sp.mem_bytes, slots, arena_bytes, np.concatenate(pt_gfn_all),
+                      np.concatenate(pt_data_all), vm)
+        if sp.ept:
+            img.ept_root, img.ept_off, img.ept_data, img.arena_bytes, img.ept_leaf = _make_ept(rng, sp, slots,
+                                                                                              arena_bytes)
+        vms.append(img)
     wl = Workload(sp, vms, procs, np.zeros(0, REQ_DTYPE), np.zeros(0, np.uint64), 0, sp.seed)
     if requests and sp.n_requests > 0:
         _make_requests(rng, sp, wl)
