@@ -250,8 +250,8 @@ static uint32_t ept_walk(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t 
     uint64_t table = v->ept_root;
     int can_r = 1, can_w = 1;
     for (int lvl = 4; lvl >= 1; lvl--) {
-        uint32_t shift = 12 + 9 * (uint32_t)(lvl - 1);
-        uint64_t e = load64(v->arena + table + 8 * ((gpa >> shift) & 511));
+        uint32_t eshift = 12u + 9u * (uint32_t)(lvl - 1);
+        uint64_t e = load64(v->arena + table + 8 * ((gpa >> eshift) & 511));
         if ((e & 7) == 0) return ORC_EPT_VIOLATION;
         if ((e & 3) == 2) return ORC_EPT_MISCONFIG;
         can_r &= (int)(e & 1);
@@ -265,7 +265,7 @@ static uint32_t ept_walk(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t 
         }
         uint64_t mt = (e >> 3) & 7;
         if (mt == 2 || mt == 3 || mt == 7) return ORC_EPT_MISCONFIG;
-        uint64_t size = 1ull << shift;
+        uint64_t size = 1ull << eshift;
         if (e & (size - 1) & ~0xFFFull) return ORC_EPT_MISCONFIG;
         uint64_t h = (e & ORC_ADDR_MASK) | (gpa & (size - 1));
         if (!in_arena(v, h & ~0xFFFull)) return ORC_EPT_MISCONFIG;

@@ -61,8 +61,8 @@ MUTANTS = {
     "map_pae_root_full_bits": ("(root_pae ? ORC_P :", "(root_pae ? (ORC_P | ORC_RW | ORC_US) :"),
     "map_large_leaf_ignored": ("if (rsvd || (!(pae && lvl == 3) && (e & ORC_PS))) {", "if (rsvd) {"),
     # the EPT walk (a second walk for the guest-physical space)
-    "ept_index_mask_8bit": ("uint64_t e = load64(v->arena + table + 8 * ((gpa >> shift) & 511));",
-                            "uint64_t e = load64(v->arena + table + 8 * ((gpa >> shift) & 255));"),
+    "ept_index_mask_8bit": ("uint64_t e = load64(v->arena + table + 8 * ((gpa >> eshift) & 511));",
+                            "uint64_t e = load64(v->arena + table + 8 * ((gpa >> eshift) & 255));"),
     "ept_write_without_read_ok": ("if ((e & 3) == 2) return ORC_EPT_MISCONFIG;", "if (0) return ORC_EPT_MISCONFIG;"),
     "ept_table_bits_unchecked": ("if (e & 0xF8) return ORC_EPT_MISCONFIG;", "if (0) return ORC_EPT_MISCONFIG;"),
     "ept_memtype_unchecked": ("if (mt == 2 || mt == 3 || mt == 7)", "if (mt == 7)"),
