@@ -81,6 +81,12 @@ typedef struct {
 #define DEVIRT_INVALID 7u      /* unknown asid                                    */
 #define DEVIRT_NO_POOL 8u      /* devirt_map_pages: too few pool frames for the
                                   tables the batch needs (nothing written)        */
+#define DEVIRT_EPT_VIOLATION 9u /* VM with an EPT: a table (level >= 1) or the
+                                  data page (level 0) is not present in the EPT,
+                                  lacks a permission, or lies at or above 2^48    */
+#define DEVIRT_EPT_MISCONFIG 10u /* VM with an EPT: a misconfigured EPT entry on
+                                  the path (write without read, reserved bits,
+                                  memory type 2/3/7) or one outside the arena     */
 
 /* Per-operation result (24 bytes), the analogue of the per-guest-thread
  * result page (section 5).  Copies have prefix semantics: every byte before
@@ -151,6 +157,25 @@ int devirt_vm_read(devirt_ctx *ctx, uint32_t vm, uint64_t off, void *dst, uint64
 int devirt_memslot_set(devirt_ctx *ctx, uint32_t vm, uint32_t slot, uint64_t gpa, uint64_t bytes,
                        uint64_t arena_off);
 
+/* Describe a VM's guest-physical space by a 4-level extended page table
+ * instead of its memslots: the translation is then finished by a second
+ * software walk, the paper's path for hypervisors other than KVM (section
+ * 4.2; EPT in section 2.2).  root_arena_off: arena offset of the EPT's
+ * level-4 table, 4 KiB aligned, inside the arena; ~0 returns the VM to its
+ * memslots.  EPT tables live in the arena (the caller writes them with
+ * devirt_vm_write); entry addresses are arena offsets.  Entry bits: 0 read,
+ * 1 write, 2 execute (an entry with all three clear is not present), 5:3
+ * memory type, 7 page size at levels 3 and 2 (1 GiB / 2 MiB leaves),
+ * address 51:12; bits 63:52, 6, 8 and 9 are ignored and never written.
+ * A guest page-table frame needs read and write through the EPT (the walk
+ * may set A/D bits in it); a data page needs read when copied to the host or
+ * translated for reading, write when copied into the guest or translated
+ * with DEVIRT_XLAT_WRITE.  Failures report DEVIRT_EPT_VIOLATION or
+ * DEVIRT_EPT_MISCONFIG at the guest level whose frame failed, 0 for the data
+ * page.  -ENOENT for an unknown VM, -EINVAL for a bad root; waits for the
+ * device to be idle, like devirt_memslot_set. */
+int devirt_vm_set_ept(devirt_ctx *ctx, uint32_t vm, uint64_t root_arena_off);
+
 /* Register a guest process by its page-table root (CR3) and paging mode,
  * captured once as the backend does when a thread first makes a call
  * (section 6.3).  levels 4 or 5: x86-64 4-level (48-bit) or 5-level (57-bit)
@@ -199,6 +224,7 @@ int devirt_copy_to_guest(devirt_ctx *ctx, uint32_t asid, uint64_t gva, const voi
  * reports NO_POOL.  *n_used_dev (one uint64_t) receives the frames used.
  * pool_gpa_host: n_pool distinct, 4 KiB aligned frames inside memslots that
  * nothing else uses (-EINVAL otherwise); read before the call returns.
+ * -EOPNOTSUPP when the process's VM translates through an EPT.
  * Asynchronous on hip_stream; no other call may touch the process's tables
  * meanwhile. */
 typedef struct {

@@ -38,7 +38,9 @@ struct DVm {
     uint32_t nslots;
     uint32_t index_complete;
     uint32_t pad;
+    uint64_t ept_root;  // arena offset of the EPT's level-4 table; kNoEpt: memslots translate
 };
+constexpr uint64_t kNoEpt = ~0ull;
 
 struct DProc {
     uint64_t cr3;

@@ -134,6 +134,72 @@ __device__ __forceinline__ bool slot_lookup(const DVm &v, uint64_t gpa, uint64_t
     return true;
 }
 
+// ------------------------------------------------------------------ EPT
+// Hypervisors other than KVM finish the translation with a second software
+// walk, of the extended page table that describes the guest-physical space
+// (section 4.2; EPT in section 2.2).  The EPT is 4-level and lives in the
+// arena; entry addresses are arena offsets.  Per level, top-down: not
+// present (bits 2:0 clear) is a violation; write without read, or any of
+// bits 7:3 in a table entry, is a misconfiguration; read and write are
+// AND-ed down the walk.  At the leaf: a memory type of 2, 3 or 7, reserved
+// bits of a large leaf, or a page outside the arena is a misconfiguration,
+// then a missing permission is a violation.  Addresses at or above 2^48 are
+// violations.  Every table and page the walk yields lies inside the arena.
+constexpr uint32_t kNeedR = 1, kNeedW = 2, kNeedTable = 3;  // a guest table frame may take A/D writes
+
+struct XRes {
+    uint64_t hpa;
+    uint32_t code;
+};
+
+// Inlined: out of line, the call convention costs the translate kernels a
+// wave of occupancy even when no VM has an EPT.
+__device__ __forceinline__ XRes ept_walk(uint8_t *arena, uint64_t arena_bytes, uint64_t root, uint64_t gpa,
+                                      uint32_t need) {
+    XRes r{0, DEVIRT_EPT_VIOLATION};
+    if (gpa >> 48) return r;
+    uint64_t table = root;
+    uint64_t perm = 3;
+    for (int lvl = 4; lvl >= 1; --lvl) {
+        const uint32_t sh = 12u + 9u * (uint32_t)(lvl - 1);
+        const uint64_t e = load_entry(arena, table + 8 * ((gpa >> sh) & 511));
+        if (!(e & 7)) return r;
+        r.code = DEVIRT_EPT_MISCONFIG;
+        if ((e & 3) == 2) return r;
+        perm &= e;
+        const bool leaf = lvl == 1 || ((lvl == 3 || lvl == 2) && (e & 0x80));
+        if (!leaf) {
+            if (e & 0xF8) return r;
+            table = e & kAddrMask;
+            if (table >= arena_bytes || arena_bytes - table < 4096) return r;
+            r.code = DEVIRT_EPT_VIOLATION;
+            continue;
+        }
+        const uint64_t mt = (e >> 3) & 7;
+        if (mt == 2 || mt == 3 || mt == 7) return r;
+        const uint64_t low = (1ull << sh) - 1;
+        if (e & low & ~0xFFFull) return r;
+        const uint64_t h = (e & kAddrMask) | (gpa & low);
+        const uint64_t pg = h & ~0xFFFull;
+        if (pg >= arena_bytes || arena_bytes - pg < 4096) return r;
+        r.code = DEVIRT_EPT_VIOLATION;
+        if (need & ~perm & 3) return r;
+        r.hpa = h;
+        r.code = DEVIRT_OK;
+        return r;
+    }
+    return r;
+}
+
+// GPA -> arena offset for an access that needs `need`: the memslots, or the
+// EPT walk when the VM has one.
+__device__ __forceinline__ uint32_t gpa_xlat(const DVm &v, uint64_t gpa, uint32_t need, uint64_t &hpa) {
+    if (v.ept_root == kNoEpt) return slot_lookup(v, gpa, hpa) ? DEVIRT_OK : DEVIRT_NO_MEMSLOT;
+    const XRes r = ept_walk(v.arena, v.arena_bytes, v.ept_root, gpa, need);
+    if (r.code == DEVIRT_OK) hpa = r.hpa;
+    return r.code;
+}
+
 // ------------------------------------------------------------ upper levels
 // Result of walking the levels above the page directory for one 1 GiB region
 // (x86-64: level 5 (LA57), level 4, level 3).
@@ -163,8 +229,9 @@ __device__ __forceinline__ void walk_upper_t(const DVm &v, uint64_t cr3, uint64_
         const int lvl = LEVELS - i;
         const uint32_t shift = 12 + 9 * (lvl - 1);
         uint64_t th;
-        if (!slot_lookup(v, table, th)) {
-            c.info = DEVIRT_NO_MEMSLOT | (lvl << 4) | (i << 11) | (abits << 13);
+        const uint32_t xc = gpa_xlat(v, table, kNeedTable, th);
+        if (xc) {
+            c.info = xc | (lvl << 4) | (i << 11) | (abits << 13);
             return;
         }
         uint64_t eoff = th + 8 * ((gva >> shift) & 511);
@@ -204,8 +271,9 @@ __device__ __forceinline__ void walk_upper_t(const DVm &v, uint64_t cr3, uint64_
 __device__ __forceinline__ void walk_upper_pae(const DVm &v, uint64_t cr3, uint64_t gva, CEnt &c) {
     c.path[0] = c.path[1] = c.path[2] = 0;
     uint64_t th;
-    if (!slot_lookup(v, cr3 & 0xFFFFFFE0ull, th)) {
-        c.info = DEVIRT_NO_MEMSLOT | (3u << 4);
+    const uint32_t xc = gpa_xlat(v, cr3 & 0xFFFFFFE0ull, kNeedTable, th);
+    if (xc) {
+        c.info = xc | (3u << 4);
         return;
     }
     const uint64_t e = load_entry(v.arena, th + 8 * ((gva >> 30) & 3));
@@ -499,8 +567,9 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                     rbase = ce.base;
                 } else {
                     uint64_t th;
-                    if (!slot_lookup(vmv, ce.base, th)) {
-                        rcode = DEVIRT_NO_MEMSLOT;
+                    const uint32_t xc = gpa_xlat(vmv, ce.base, kNeedTable, th);
+                    if (xc) {
+                        rcode = xc;
                         rlevel = 2;
                     } else {
                         pde_off = th + 8 * ((lo >> 21) & 511);
@@ -526,8 +595,9 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                                 }
                             } else {
                                 uint64_t pt;
-                                if (!slot_lookup(vmv, e & kAddrMask, pt)) {
-                                    rcode = DEVIRT_NO_MEMSLOT;
+                                const uint32_t xc1 = gpa_xlat(vmv, e & kAddrMask, kNeedTable, pt);
+                                if (xc1) {
+                                    rcode = xc1;
                                     rlevel = 1;
                                 } else {
                                     rkind = 0;
@@ -587,9 +657,12 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                 } else if (j_dir && !w) {
                     code = DEVIRT_PROT_WRITE;
                     level = leaf_level;
-                } else if (!slot_lookup(vmv, gpa, hpa)) {
-                    code = DEVIRT_NO_MEMSLOT;
-                    level = 0;
+                } else {
+                    const uint32_t xc = gpa_xlat(vmv, gpa, j_dir ? kNeedW : kNeedR, hpa);
+                    if (xc) {
+                        code = xc;
+                        level = 0;
+                    }
                 }
             }
         }
@@ -936,7 +1009,8 @@ __global__ void __launch_bounds__(64) k_plain(DView v, DBatch b, devirt_request 
 }
 
 // translate-only: one lane per address
-__global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint64_t *gvas, uint64_t n,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_xlat(DView v, uint32_t asid,
+                                                                                     const uint64_t *gvas, uint64_t n,
                                                uint32_t flags, devirt_xlat *out, DCounters *counters) {
     extern __shared__ uint8_t smem[];
     const int wave = threadIdx.x >> 6;
@@ -998,8 +1072,9 @@ __global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint
                     leaf_level = 3;
                 } else {
                     uint64_t th;
-                    if (!slot_lookup(vmv, ce.base, th)) {
-                        code = DEVIRT_NO_MEMSLOT;
+                    const uint32_t xc = gpa_xlat(vmv, ce.base, kNeedTable, th);
+                    if (xc) {
+                        code = xc;
                         level = 2;
                     } else {
                         pde_off = th + 8 * ((gva >> 21) & 511);
@@ -1024,8 +1099,9 @@ __global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint
                                 }
                             } else {
                                 uint64_t pt;
-                                if (!slot_lookup(vmv, e2 & kAddrMask, pt)) {
-                                    code = DEVIRT_NO_MEMSLOT;
+                                const uint32_t xc1 = gpa_xlat(vmv, e2 & kAddrMask, kNeedTable, pt);
+                                if (xc1) {
+                                    code = xc1;
                                     level = 1;
                                 } else {
                                     pte_off = pt + 8 * ((gva >> 12) & 511);
@@ -1060,9 +1136,13 @@ __global__ void __launch_bounds__(256) k_xlat(DView v, uint32_t asid, const uint
                 } else if (write && !w) {
                     code = DEVIRT_PROT_WRITE;
                     level = leaf_level;
-                } else if (!slot_lookup(vmv, gpa, hpa)) {
-                    code = DEVIRT_NO_MEMSLOT;
-                    level = 0;
+                } else {
+                    const uint32_t xc = gpa_xlat(vmv, gpa, write ? kNeedW : kNeedR, hpa);
+                    if (xc) {
+                        code = xc;
+                        level = 0;
+                        hpa = 0;
+                    }
                 }
             }
             x.code = code;

@@ -161,6 +161,7 @@ static int upload_vms(devirt_ctx *c) {
         h[i].nslots = v.nsorted;
         h[i].index_complete = v.index_complete;
         h[i].pad = 0;
+        h[i].ept_root = v.ept_root;
     }
     if (c->vms.size() > c->d_vms_cap) {
         size_t cap = std::max<size_t>(16, c->vms.size() * 2);
@@ -324,6 +325,19 @@ extern "C" int devirt_memslot_set(devirt_ctx *c, uint32_t vm, uint32_t slot, uin
     v.nsorted = (uint32_t)sorted.size();
     v.index_len = (uint32_t)index.size();
     v.index_complete = complete;
+    return upload_vms(c);
+}
+
+extern "C" int devirt_vm_set_ept(devirt_ctx *c, uint32_t vm, uint64_t root) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (vm >= c->vms.size()) return dv_fail(-ENOENT, "no VM %u", vm);
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
+    VmHost &v = c->vms[vm];
+    if (root != ~0ull && ((root & 4095) || root >= v.bytes || v.bytes - root < 4096))
+        return dv_fail(-EINVAL, "EPT root must be a 4 KiB aligned table inside the arena");
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipDeviceSynchronize());
+    v.ept_root = root;
     return upload_vms(c);
 }
 
@@ -532,6 +546,8 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     if (set_dev(c)) return -EIO;
     // the pool: aligned, distinct frames inside memslots of the process's VM
     std::vector<uint64_t> hpa(n_pool);
+    if (asid < c->procs.size() && c->vms[c->procs[asid].vm].ept_root != ~0ull)
+        return dv_fail(-EOPNOTSUPP, "mapping pages is defined for memslot VMs only");
     if (asid < c->procs.size() && n_pool) {
         const VmHost &v = c->vms[c->procs[asid].vm];
         std::vector<const VmHost::Slot *> sl;

@@ -18,6 +18,7 @@ struct VmHost {
     uint64_t *d_index = nullptr;
     dv::DSlot *d_slots = nullptr;
     uint32_t index_len = 0, nsorted = 0, index_complete = 1;
+    uint64_t ept_root = ~0ull;  // ~0: translate through the memslots
 };
 
 struct GraphEntry {

@@ -22,7 +22,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "devirt.h")
 FROM_GUEST, TO_GUEST = 0, 1
 XLAT_WRITE, XLAT_SET_AD = 1, 2
 CODES = {"OK": 0, "NOT_PRESENT": 1, "RESERVED": 2, "PROT_USER": 3, "PROT_WRITE": 4, "NO_MEMSLOT": 5,
-         "NONCANONICAL": 6, "INVALID": 7, "NO_POOL": 8}
+         "NONCANONICAL": 6, "INVALID": 7, "NO_POOL": 8,
+         "EPT_VIOLATION": 9, "EPT_MISCONFIG": 10}
 
 REQUEST_DTYPE = np.dtype([("gva", "<u8"), ("host", "<u8"), ("len", "<u4"), ("asid", "<u4"), ("dir", "u1"),
                           ("rsvd", "u1", (3,)), ("tag", "<u4")])
@@ -104,6 +105,7 @@ _SIGS = {
     "devirt_vm_write": ([vp, u32, u64, vp, u64]),
     "devirt_vm_read": ([vp, u32, u64, vp, u64]),
     "devirt_memslot_set": ([vp, u32, u32, u64, u64, u64]),
+    "devirt_vm_set_ept": ([vp, u32, u64]),
     "devirt_process_create": ([vp, u32, u64, u32, ctypes.POINTER(u32)]),
     "devirt_translate": ([vp, u32, vp, u64, u32, vp, vp]),
     "devirt_copy_from_guest": ([vp, u32, u64, vp, u64, vp, vp]),
@@ -227,6 +229,11 @@ class Context:
 
     def memslot_set(self, vm: int, slot: int, gpa: int, nbytes: int, arena_off: int):
         _check("devirt_memslot_set", lib().devirt_memslot_set(self._h, vm, slot, gpa, nbytes, arena_off))
+
+    def vm_set_ept(self, vm: int, root: int | None):
+        """Translate the VM's guest-physical addresses through the EPT rooted
+        at arena offset `root` (None: back to the memslots)."""
+        _check("devirt_vm_set_ept", lib().devirt_vm_set_ept(self._h, vm, (1 << 64) - 1 if root is None else root))
 
     def process_create(self, vm: int, cr3: int, levels: int) -> int:
         a = u32()

@@ -207,3 +207,28 @@ def test_map_edge_cases():
         assert all(np.array_equal(a, b) for a, b in zip(a0, device.read_arenas(ctx, dw)))
     finally:
         ctx.close()
+
+
+def test_map_refused_on_ept_vm():
+    """Mapping pages is defined for memslot VMs; an EPT VM is refused before any work."""
+    import torch
+    import paper_1304_3771_amd as dv
+    from oracle.oracle import MAP_DTYPE
+    w = wl("ept")
+    log("map on an EPT VM")
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        a0 = device.read_arenas(ctx, dw)
+        m = np.zeros(4, MAP_DTYPE)
+        m["gva"] = np.arange(4, dtype=np.uint64) << np.uint64(12)
+        dm = torch.from_numpy(m.view(np.uint8).copy()).cuda()
+        res = torch.zeros(4 * 24, dtype=torch.uint8, device="cuda")
+        nu = torch.zeros(1, dtype=torch.int64, device="cuda")
+        with pytest.raises(dv.DevirtError) as ei:
+            ctx.map_pages(0, dm, 4, [], res, nu)
+        assert ei.value.rc == -95
+        torch.cuda.synchronize()
+        assert all(np.array_equal(a, b) for a, b in zip(a0, device.read_arenas(ctx, dw)))
+    finally:
+        ctx.close()

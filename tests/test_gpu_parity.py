@@ -42,13 +42,15 @@ def _golden_ctx(world):
     ctx.vm_write(vm, 0, arena)
     for i, s in enumerate(world["slots"]):
         ctx.memslot_set(vm, i, H(s["gpa"]), H(s["bytes"]), H(s["arena_off"]))
+    if "ept_root" in world:
+        ctx.vm_set_ept(vm, H(world["ept_root"]))
     asid = ctx.process_create(vm, H(world["cr3"]), world["levels"])
     assert asid == 0
     dpool = torch.from_numpy(pool.copy()).cuda()
     return ctx, vm, o, arena, pool, dpool, dv
 
 
-@pytest.mark.parametrize("widx", [0, 1, 2, 3])  # 4-level, 5-level, PAE, PAE
+@pytest.mark.parametrize("widx", [0, 1, 2, 3, 4])  # 4-level, 5-level, PAE, PAE, 4-level under an EPT
 def test_golden_translate(widx):
     import torch
     world = pins.golden_worlds()[widx]
@@ -80,7 +82,7 @@ def test_golden_translate(widx):
         ctx.close()
 
 
-@pytest.mark.parametrize("widx", [0, 2, 3])  # the worlds with an A/D expectation
+@pytest.mark.parametrize("widx", [0, 2, 3, 4])  # the worlds with an A/D expectation
 def test_golden_set_ad(widx):
     import torch
     world = pins.golden_worlds()[widx]
@@ -102,7 +104,7 @@ def test_golden_set_ad(widx):
         ctx.close()
 
 
-@pytest.mark.parametrize("widx", [0, 2, 3])  # the worlds with copies
+@pytest.mark.parametrize("widx", [0, 2, 3, 4])  # the worlds with copies
 @pytest.mark.parametrize("path", ["plain", "batch"])
 def test_golden_copies(path, widx):
     import torch
@@ -138,7 +140,7 @@ def test_golden_copies(path, widx):
 
 # ------------------------------------------------------------ batches
 @pytest.mark.parametrize("name", ["tiny4k", "c1", "mix2m", "multi_vm", "lvl5", "lvl5_1g", "prot", "pae",
-                                  "pae_prot"])
+                                  "pae_prot", "ept", "ept_faults", "ept_lvl5", "ept_pae", "ept_1g"])
 def test_batch_matches_oracle(name):
     w = wl(name)
     log(f"batch {name}: {w.n_requests} requests, {len(w.epoch_end)} epochs")
@@ -266,7 +268,7 @@ def test_translate_matches_oracle():
     import torch
     import paper_1304_3771_amd as dv
     from oracle import Oracle
-    for name in ("mix2m", "lvl5_1g", "prot", "multi_vm", "pae_prot"):
+    for name in ("mix2m", "lvl5_1g", "prot", "multi_vm", "pae_prot", "ept_faults", "ept_lvl5", "ept_pae"):
         w = wl(name)
         log(f"translate {name}")
         rng = np.random.default_rng(3)

@@ -37,6 +37,8 @@ def load(ctx, wl: Workload, device: str = "cuda:0", arena_chunk: int = 1 << 30) 
             raise RuntimeError(f"VM ids out of step: got {vm}, generator expects {v.vm}")
         for i, s in enumerate(v.slots):
             ctx.memslot_set(vm, i, int(s["gpa"]), int(s["bytes"]), int(s["arena_off"]))
+        if v.ept_root is not None:
+            ctx.vm_set_ept(vm, v.ept_root)
         if buf is None or buf.size < v.arena_bytes:
             buf = np.empty(v.arena_bytes, np.uint8)
         img = buf[:v.arena_bytes]
