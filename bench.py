@@ -37,6 +37,9 @@ WORKLOADS = {
     "C5": "64 VMs x 2 GiB, 5-level paging, 60/35/5 4KiB/2MiB/1GiB, 3% not-present, 1e7 requests 16B-1MiB",
     "C2-PAE": "C2 under 32-bit PAE paging (4-entry root table, 32-bit addresses): one guest, 4 GiB, "
               "70/30 4KiB/2MiB, 16 memslots, 5% not-present, 1e6 requests log-uniform 64B-64KiB",
+    "C2-EPT": "C2 with its guest-physical space behind a 4-level EPT (a second software walk instead of "
+              "memslots; EPT leaves 2 MiB where aligned, else 4 KiB): one guest, 4 GiB, 70/30 4KiB/2MiB, "
+              "5% not-present, 1e6 requests log-uniform 64B-64KiB",
 }
 
 
@@ -44,6 +47,8 @@ def workload_spec(name):
     from workload import gen
     if name == "C2-PAE":
         return gen.spec("C2", levels=3, seed=1006)
+    if name == "C2-EPT":
+        return gen.spec("C2", ept=True, seed=1007)
     return gen.spec(name)
 
 
@@ -107,7 +112,8 @@ def cpu_baseline(wl, seconds, name, max_vms=8):
     log(f"cpu baseline: building host state for {nvm} of {len(wl.vms)} VMs")
     arenas = [wl.arena_image(v) for v in range(nvm)]
     arenas += [np.zeros(4096, np.uint8) for _ in range(nvm, len(wl.vms))]
-    o = Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], wl.pool_image())
+    o = Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], wl.pool_image(),
+               ept=[v.ept_root if v.vm < nvm else None for v in wl.vms])
     vm_of = np.array([p.vm for p in wl.procs])
     reqs = wl.requests[vm_of[wl.requests["asid"]] < nvm]
     tot_t, tot_b, done, passes = 0.0, 0, 0, 0
