@@ -4,10 +4,12 @@
 // address is translated page by page -- a software walk of the guest's page
 // tables (x86-64 4- or 5-level, or the 32-bit PAE format of the paper's
 // prototype, section 6.2) to a guest-physical address, then the VM's memslots
-// to the host address (KVM style) -- and its bytes are copied between the
-// guest memory image ("arena") and a host buffer.  A fault ends the operation
-// with everything before the faulting byte copied, so the operation can be
-// re-executed (section 6.6).
+// to the host address (KVM style), or, for a VM described by an extended page
+// table, a second software walk of that EPT (the paper's path for other
+// hypervisors) -- and its bytes are copied between the guest memory image
+// ("arena") and a host buffer.  A fault ends the operation with everything
+// before the faulting byte copied, so the operation can be re-executed
+// (section 6.6).
 //
 // Work decomposition (wave64 throughout):
 //   translate  one wavefront owns a group of consecutive requests.  A wave
@@ -31,9 +33,13 @@
 //              never with a read-modify-write of bytes outside the segment.
 //   faults     the ordered fault list is a tile count, a single-workgroup
 //              scan and a ballot/mbcnt scatter.
+//   map pages  one lane per map walks the tables as they are; device hash
+//              sets collect the distinct tables the batch lacks and the last
+//              map of each page; the new tables are ordered by rank in LDS
+//              tiles (or a radix sort), zeroed, linked, and the leaves
+//              written -- four launches.
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_select.hpp>
 
 #include "dv_internal.h"
 
