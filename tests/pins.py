@@ -23,7 +23,7 @@ import os
 
 import numpy as np
 
-from oracle import CODES, RESULT_DTYPE, Oracle
+from oracle import CODES, Oracle
 from oracle.oracle import SLOT_DTYPE, XLAT_SET_AD, XLAT_WRITE
 from workload import REQ_DTYPE, gen
 

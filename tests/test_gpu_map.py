@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import pins
-from gpu_util import compare, gpu_batch, log, new_ctx, oracle_batch
+from gpu_util import compare, gpu_batch, log, new_ctx
 from oracle import Oracle
 from workload import device, gen
 
