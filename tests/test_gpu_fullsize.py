@@ -118,15 +118,24 @@ def _tables_only_oracle(wl):
     for v in wl.vms:
         a = np.zeros(v.arena_bytes, np.uint8)
         wl.overlay_tables(v.vm, a)
+        if v.ept_root is not None:
+            a.reshape(-1, 4096)[(v.ept_off >> np.uint64(12)).astype(np.int64)] = \
+                v.ept_data.view(np.uint8).reshape(-1, 4096)
         arenas.append(a)
     return Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs],
-                  np.zeros(4096, np.uint8))
+                  np.zeros(4096, np.uint8), ept=[v.ept_root for v in wl.vms])
 
 
-@pytest.mark.parametrize("name", ["C3", "C5"])
+_FULL = {"C3": gen.spec("C3"), "C5": gen.spec("C5"),
+         # C2's shape with its guest-physical space behind a 4-level EPT (as the C2-EPT benchmark)
+         "C2-EPT": gen.spec("C2", ept=True, seed=1007)}
+
+
+@pytest.mark.parametrize("name", ["C3", "C5", "C2-EPT"])
 def test_full_size_results_and_ad(name):
-    """16 VMs x 4 processes x 2 GiB, 4e6 requests 16 B-4 MiB (C3), or 64 VMs x 2 GiB with
-    5-level paging and 1 GiB pages, 1e7 requests (C5), run as the benchmark runs them:
+    """16 VMs x 4 processes x 2 GiB, 4e6 requests 16 B-4 MiB (C3), 64 VMs x 2 GiB with
+    5-level paging and 1 GiB pages, 1e7 requests (C5), or C2 behind an EPT, run as the
+    benchmark runs them:
     autotuned launch configuration, HIP graph, all epochs.
     Checked: every 29th request's result against the oracle (exact), the fault list is
     the ascending list of faulting requests with their records, A/D bits of every table
@@ -138,7 +147,7 @@ def test_full_size_results_and_ad(name):
     import paper_1304_3771_amd as dv
     from pins import _leaf_lookup, find_leaf
     log(f"full {name}: generating")
-    wl = gen.make_workload(gen.spec(name))
+    wl = gen.make_workload(_FULL[name])
     n = wl.n_requests
     ctx = new_ctx()
     try:
