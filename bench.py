@@ -359,12 +359,38 @@ def map_bench(args):
         log(f"map {kind}: {ms:.3f} ms per call of {n} maps, {n / ms / 1e3:.2f} Mmaps/s, "
             f"{int(np.mean(tables))} new tables per call")
     ctx.close()
+    # algorithmic bytes of a fresh call: per map the record read, the result
+    # written, the leaf entry written and a page-set slot (key + index); per
+    # new table its 4 KiB zeroed (table-entry reads are left out: the walks
+    # share them through the caches)
+    alg = n * (24 + 24 + 8 + 16) + out["fresh"]["new_tables_per_call"] * 4096
+    achieved = alg / (out["fresh"]["ms_per_call"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "devirt_map_pages (whole call)",
+            "alg_bytes_per_call": alg}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import Oracle
+        log("map: cpu baseline (oracle, fresh batches)")
+        o = Oracle.from_workload(wl)
+        nxt, tot, calls = 0, 0.0, 0
+        while tot < args.cpu_seconds and calls < 80:
+            m = fresh_batch()
+            t0 = time.perf_counter()
+            r, u = o.map_pages(0, m, free[nxt:nxt + pool_per_call])
+            tot += time.perf_counter() - t0
+            nxt += u
+            calls += 1
+        cpu = {"value": round(calls * n / tot, 1), "unit": "maps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{calls} fresh batches of {n} maps on {args.workload}'s tables, sequential, "
+                         f"{tot:.1f} s on one of {os.cpu_count()} host cores"}
+        log(f"map: cpu baseline {cpu['value'] / 1e6:.2f} Mmaps/s")
     print(json.dumps({"metric": "maps/s (guest-table writer)", "value": out["fresh"]["maps_per_s"], "unit": "maps/s",
                       "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
                       "data": "synthetic", "dtype": "int64",
                       "config": {"workload": f"{args.workload} tables, {n} 4 KiB maps per call; fresh: runs of "
                                              "16-4096 pages at new 2 MiB-aligned GVAs; remap: mapped 4 KiB pages"},
-                      "fresh": out["fresh"], "remap": out["remap"]}))
+                      "fresh": out["fresh"], "remap": out["remap"], "roofline": roof, "cpu_baseline": cpu}))
 
 
 def main():
