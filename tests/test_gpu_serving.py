@@ -18,12 +18,17 @@ CLASSES = ((0.60, "uniform", 24, 24, 1), (0.25, "uniform", 4096, 4096, 0),
            (0.14, "loguniform", 16 << 10, 256 << 10, 0), (0.01, "uniform", 1 << 20, 1 << 20, 1))
 
 
-@pytest.fixture(scope="module")
-def trace():
+@pytest.fixture(scope="module", params=["memslots", "ept"])
+def trace(request):
+    """Two VMs translated through their memslots, or through EPTs with some
+    leaves not present, read-only or misconfigured."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    wl = gen.make_workload(gen.spec("C4", n_vms=2, procs_per_vm=2, mem_bytes=256 * MiB, seed=44), requests=False)
+    sp = gen.spec("C4", n_vms=2, procs_per_vm=2, mem_bytes=256 * MiB, seed=44)
+    if request.param == "ept":
+        sp = sp.replace(ept=True, ept_np=0.02, ept_ro=0.03, ept_mis=0.01)
+    wl = gen.make_workload(sp, requests=False)
     tr = gen.make_serving_trace(wl, 3000, 2e5, threads_per_proc=8, window=2 * MiB, classes=CLASSES,
                                 host_mode="unique", seed=45)
     return wl, tr
@@ -120,7 +125,8 @@ def test_alone_vs_mix(trace, alone, completion):
     # both equal the oracle applied in submission order
     arenas = [wl.arena_image(v) for v in range(len(wl.vms))]
     opool = gen.fill_bytes(np.empty(tr.pool_bytes, np.uint8), wl.seed, gen.POOL_KEY)
-    o = Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], opool)
+    o = Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], opool,
+               ept=[v.ept_root for v in wl.vms])
     er, _ = o.batch(tr.requests)
     for f in ("bytes_done", "fault_gva", "code", "level"):
         assert np.array_equal(c[f], er[f]), f
