@@ -277,6 +277,34 @@ def free_guest_frames(wl, vm):
     return np.nonzero(np.cumsum(cover[:nfr]) == 0)[0].astype(np.uint64) << np.uint64(12)
 
 
+def map_fresh_batch(rng, n, lim, mem_frames, dtype, write_flag):
+    """n maps in runs of 16-4096 contiguous pages (log-uniform), like mmaps of
+    device buffers, at random 2 MiB-aligned GVAs in the upper half of the user
+    range [0, lim); frames uniform over the guest's memory."""
+    g = []
+    left = n
+    while left:
+        run = min(left, int(16 * 256 ** rng.random()))
+        base = int(rng.integers(lim >> 22, (lim >> 21) - 8)) << 21  # the run ends below the limit
+        g.append(np.uint64(base) + (np.arange(run, dtype=np.uint64) << np.uint64(12)))
+        left -= run
+    m = np.zeros(n, dtype)
+    m["gva"] = np.concatenate(g)
+    m["gpa"] = rng.integers(0, mem_frames, n).astype(np.uint64) << np.uint64(12)
+    m["flags"] = write_flag
+    return m
+
+
+def map_remap_batch(rng, n, proc, mem_frames, dtype):
+    """n maps onto pages the process's tables already map with 4 KiB leaves."""
+    va = proc.leaf_va[proc.leaf_level == 1]
+    m = np.zeros(n, dtype)
+    m["gva"] = va[rng.integers(0, len(va), n)]
+    m["gpa"] = rng.integers(0, mem_frames, n).astype(np.uint64) << np.uint64(12)
+    m["flags"] = rng.integers(0, 2, n)
+    return m
+
+
 def map_bench(args):
     """Mapping pages (the guest-table writer), timed per call with HIP events."""
     import torch
@@ -295,30 +323,13 @@ def map_bench(args):
     lim = {3: 1 << 32, 4: 1 << 47, 5: 1 << 56}[p.levels]
     log(f"map: {len(free)} free guest frames, {n} maps per call")
 
+    mem_frames = wl.vms[p.vm].mem_bytes >> 12
+
     def fresh_batch():
-        """Runs of 16-4096 contiguous pages (log-uniform), like mmaps of device
-        buffers, at random 2 MiB-aligned GVAs in the upper half of user space."""
-        g = []
-        left = n
-        while left:
-            run = min(left, int(16 * 256 ** rng.random()))
-            base = int(rng.integers(lim >> 22, (lim >> 21) - 8)) << 21  # the run ends below the limit
-            g.append(np.uint64(base) + (np.arange(run, dtype=np.uint64) << np.uint64(12)))
-            left -= run
-        m = np.zeros(n, dv.MAP_DTYPE)
-        m["gva"] = np.concatenate(g)
-        m["gpa"] = rng.integers(0, wl.vms[p.vm].mem_bytes >> 12, n).astype(np.uint64) << np.uint64(12)
-        m["flags"] = dv.MAP_WRITE
-        return m
+        return map_fresh_batch(rng, n, lim, mem_frames, dv.MAP_DTYPE, dv.MAP_WRITE)
 
     def remap_batch():
-        """Maps onto pages the tables already map with 4 KiB leaves."""
-        va = p.leaf_va[p.leaf_level == 1]
-        m = np.zeros(n, dv.MAP_DTYPE)
-        m["gva"] = va[rng.integers(0, len(va), n)]
-        m["gpa"] = rng.integers(0, wl.vms[p.vm].mem_bytes >> 12, n).astype(np.uint64) << np.uint64(12)
-        m["flags"] = rng.integers(0, 2, n)
-        return m
+        return map_remap_batch(rng, n, p, mem_frames, dv.MAP_DTYPE)
 
     res = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
     used = torch.zeros(1, dtype=torch.int64, device="cuda")
