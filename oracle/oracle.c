@@ -70,7 +70,11 @@
  *     host and write when copied into the guest;
  *   - per level, top-down: present, then misconfiguration; permissions once
  *     the leaf is reached; the reported level is the guest level whose
- *     frame failed (0 for the data page), as for a missing memslot.
+ *     frame failed (0 for the data page), as for a missing memslot;
+ *   - mapping pages in such a VM reads and writes the guest's tables through
+ *     the EPT, and translates the pool frames the batch takes through it
+ *     too: if one of them is not readable and writable, nothing is written
+ *     and every map that would have succeeded reports NO_POOL.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -671,9 +675,10 @@ static uint32_t map_walk(const orc_state *s, const orc_proc *p, uint64_t gva, ui
     *missing = 0;
     for (int lvl = (int)p->levels; lvl >= 2; lvl--) {
         uint64_t thpa;
-        if (!slot_lookup(v, table, &thpa)) {
+        uint32_t c = gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);
+        if (c != ORC_OK) {
             *level = (uint32_t)lvl;
-            return ORC_NO_MEMSLOT;
+            return c;
         }
         uint64_t idx = (pae && lvl == 3) ? ((gva >> 30) & 3) : ((gva >> (12 + 9 * (lvl - 1))) & 511);
         uint64_t e = load64(v->arena + thpa + 8 * idx);
@@ -689,9 +694,10 @@ static uint32_t map_walk(const orc_state *s, const orc_proc *p, uint64_t gva, ui
         table = e & ORC_ADDR_MASK;
     }
     uint64_t thpa;
-    if (!slot_lookup(v, table, &thpa)) {   /* the page table itself */
+    uint32_t c = gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);   /* the page table itself */
+    if (c != ORC_OK) {
         *level = 1;
-        return ORC_NO_MEMSLOT;
+        return c;
     }
     return ORC_OK;
 }
@@ -704,11 +710,11 @@ static uint64_t existing_table(const orc_state *s, const orc_proc *p, uint64_t g
     uint64_t table = pae ? (p->cr3 & 0xFFFFFFE0ull) : (p->cr3 & ORC_ADDR_MASK);
     uint64_t hpa = 0;
     for (int lvl = (int)p->levels; lvl > (int)level; lvl--) {
-        slot_lookup(v, table, &hpa);
+        gpa_to_hpa(v, table, ORC_NEED_TABLE, &hpa);
         uint64_t idx = (pae && lvl == 3) ? ((gva >> 30) & 3) : ((gva >> (12 + 9 * (lvl - 1))) & 511);
         table = load64(v->arena + hpa + 8 * idx) & ORC_ADDR_MASK;
     }
-    slot_lookup(v, table, &hpa);
+    gpa_to_hpa(v, table, ORC_NEED_TABLE, &hpa);
     return hpa;
 }
 
@@ -729,10 +735,11 @@ int64_t orc_map_pages(orc_state *s, uint32_t asid, const orc_map *maps, uint64_t
     const orc_proc *p = &s->procs[asid];
     orc_vm *v = &s->vms[p->vm];
     const int pae = p->levels == 3;
-    if (v->has_ept) return -2;   /* mapping pages is defined for memslot VMs only */
     uint64_t *pool_hpa = (uint64_t *)malloc((n_pool ? n_pool : 1) * sizeof(uint64_t));
+    /* memslot VM: every frame must lie in a memslot (an error otherwise);
+     * EPT VM: frames are translated below, once the batch's needs are known */
     for (uint64_t k = 0; k < n_pool; k++)
-        if ((pool[k] & 0xFFF) || !slot_lookup(v, pool[k], &pool_hpa[k])) {
+        if ((pool[k] & 0xFFF) || (!v->has_ept && !slot_lookup(v, pool[k], &pool_hpa[k]))) {
             free(pool_hpa);
             return -1;
         }
@@ -764,7 +771,13 @@ int64_t orc_map_pages(orc_state *s, uint32_t asid, const orc_map *maps, uint64_t
     uint64_t nt = 0;
     for (uint64_t k = 0; k < nk; k++)
         if (nt == 0 || keys[nt - 1] != keys[k]) keys[nt++] = keys[k];
-    if (nt > n_pool) {   /* 2. not enough frames: nothing is written */
+    int short_pool = nt > n_pool;
+    /* EPT VM: the frames the batch takes must be readable and writable
+     * through the EPT, like every table frame; else it is as if the pool
+     * were short */
+    for (uint64_t k = 0; v->has_ept && !short_pool && k < nt; k++)
+        if (gpa_to_hpa(v, pool[k], ORC_NEED_TABLE, &pool_hpa[k]) != ORC_OK) short_pool = 1;
+    if (short_pool) {   /* 2. not enough usable frames: nothing is written */
         for (uint64_t i = 0; i < n; i++)
             if (res[i].code == ORC_OK) {
                 res[i].code = ORC_NO_POOL;

@@ -164,8 +164,6 @@ class Oracle:
         res = np.zeros(len(m), RESULT_DTYPE)
         used = self._lib.orc_map_pages(self._h, asid, m.ctypes.data, len(m), pool.ctypes.data if len(pool) else None,
                                        len(pool), res.ctypes.data)
-        if used == -2:
-            raise ValueError("mapping pages is defined for memslot VMs only")
         if used < 0:
             raise ValueError("a pool frame is unaligned or outside every memslot")
         return res, int(used)

@@ -746,3 +746,66 @@ def check_ept_faults(wl, lib_path=None):
     if not fails and (seen["viol"] == 0 or seen["mis"] == 0 or seen["ok_pages"] == 0):
         fails.append(f"the world exercises too little: {seen}")
     return fails
+
+
+def check_ept_map_equivalence(wl, lib_path=None, seed=5):
+    """Mapping pages in a VM whose EPT mirrors its memslots gives the same
+    results, frames used and arena bytes as in memslot mode, for a short pool
+    and for an ample one."""
+    assert wl.spec.ept and wl.spec.ept_np == wl.spec.ept_ro == wl.spec.ept_mis == 0
+    fails = []
+    rng = np.random.default_rng(seed)
+    p = wl.procs[0]
+    m = map_batch(wl, rng)
+    pool = free_frames(wl, p.vm, 3 * len(m), rng)
+    e = Oracle.from_workload(wl, lib_path=lib_path)
+    s = Oracle([wl.arena_image(v) for v in range(len(wl.vms))], [v.slots for v in wl.vms],
+               [(q.vm, q.cr3, q.levels) for q in wl.procs], wl.pool_image(), lib_path=lib_path)
+    _, need = Oracle.from_workload(wl, lib_path=lib_path).map_pages(0, m, pool)
+    for k in (max(need - 1, 0), len(pool)):
+        re_, ue = e.map_pages(0, m, pool[:k])
+        rs, us = s.map_pages(0, m, pool[:k])
+        if not np.array_equal(re_, rs) or ue != us:
+            fails.append(f"pool of {k}: results or frames used differ between EPT and memslot modes")
+        if not all(np.array_equal(a, b) for a, b in zip(e.arenas, s.arenas)):
+            fails.append(f"pool of {k}: arenas differ between EPT and memslot modes")
+    if need == 0:
+        fails.append("the batch needs no new table")
+    return fails
+
+
+def check_ept_map_bad_pool(wl, lib_path=None, seed=6):
+    """A pool frame the batch takes but the EPT does not map readable and
+    writable (not present or read-only, from the generator's leaf list) makes
+    the whole batch NO_POOL with nothing written; the same frame placed past
+    the frames the batch needs changes nothing."""
+    from workload.gen import EPT_LEAF_NP, EPT_LEAF_OK, EPT_LEAF_RO
+    fails = []
+    rng = np.random.default_rng(seed)
+    p = wl.procs[0]
+    lf = wl.vms[p.vm].ept_leaf
+    m = map_batch(wl, rng)
+    cand = free_frames(wl, p.vm, 4000, rng)
+    j = np.searchsorted(lf["gpa"], cand, side="right") - 1
+    kind = lf["kind"][j]
+    good = cand[kind == EPT_LEAF_OK]
+    bads = {"not present": cand[kind == EPT_LEAF_NP], "read-only": cand[kind == EPT_LEAF_RO]}
+    if len(good) < 2000 or any(len(b) == 0 for b in bads.values()):
+        return ["the world has too few free frames of each kind"]
+    r0, need = Oracle.from_workload(wl, lib_path=lib_path).map_pages(0, m, good)
+    if need < 2:
+        return ["the batch needs fewer than two tables"]
+    ok = r0["code"] == CODES["OK"]
+    for what, bad in bads.items():
+        o = Oracle.from_workload(wl, lib_path=lib_path)
+        a0 = [a.copy() for a in o.arenas]
+        r, used = o.map_pages(0, m, np.concatenate([good[:need // 2], bad[:1], good[need // 2:]]))
+        if used != 0 or not all(np.array_equal(a, b) for a, b in zip(a0, o.arenas)):
+            fails.append(f"a needed {what} frame: something was written")
+        if np.any(r["code"][ok] != CODES["NO_POOL"]) or np.any(r["code"][~ok] != r0["code"][~ok]):
+            fails.append(f"a needed {what} frame: maps not reported NO_POOL")
+        r2, used2 = Oracle.from_workload(wl, lib_path=lib_path).map_pages(
+            0, m, np.concatenate([good[:need], bad[:1]]))
+        if used2 != need or not np.array_equal(r2, r0):
+            fails.append(f"a {what} frame past the needed ones changed the result")
+    return fails

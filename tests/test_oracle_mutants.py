@@ -70,8 +70,14 @@ MUTANTS = {
                                       "if (0) return ORC_EPT_MISCONFIG;"),
     "ept_write_not_anded": ("can_w &= (int)((e >> 1) & 1);", "can_w = (int)((e >> 1) & 1);"),
     "ept_gpa_limit_dropped": ("if (gpa >> 48) return ORC_EPT_VIOLATION;", "if (0) return ORC_EPT_VIOLATION;"),
-    "ept_tables_need_read_only": ("uint32_t c = gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);",
-                                  "uint32_t c = gpa_to_hpa(v, table, ORC_NEED_R, &thpa);"),
+    "ept_tables_need_read_only": ("uint32_t c = gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);\n        if (c != ORC_OK) {\n"
+                                  "            w->code = c;",
+                                  "uint32_t c = gpa_to_hpa(v, table, ORC_NEED_R, &thpa);\n        if (c != ORC_OK) {\n"
+                                  "            w->code = c;"),
+    "map_ept_page_table_read_only": ("gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);   /* the page table itself */",
+                                     "gpa_to_hpa(v, table, ORC_NEED_R, &thpa);   /* the page table itself */"),
+    "map_ept_pool_frames_read_only": ("gpa_to_hpa(v, pool[k], ORC_NEED_TABLE, &pool_hpa[k])",
+                                      "gpa_to_hpa(v, pool[k], ORC_NEED_R, &pool_hpa[k])"),
     "ept_data_always_read": ("gpa_to_hpa(v, w->gpa, write ? ORC_NEED_W : ORC_NEED_R, &w->hpa)",
                              "gpa_to_hpa(v, w->gpa, ORC_NEED_R, &w->hpa)"),
     "ept_large_leaf_offset_dropped": ("uint64_t h = (e & ORC_ADDR_MASK) | (gpa & (size - 1));",
@@ -122,6 +128,7 @@ def test_pins_catch_mutant(tmp_path, name):
         lambda: pins.check_map_properties(_small("pae"), lib),
         lambda: pins.check_ept_equivalence(_small("ept"), lib),
         lambda: pins.check_ept_faults(_small("ept_faults"), lib),
+        lambda: pins.check_ept_map_bad_pool(_small("ept_faults"), lib),
     ]
     for c in checks:
         if c():

@@ -111,16 +111,24 @@ def test_ept_faults_follow_the_leaves(name):
     assert pins.check_ept_faults(wl(name)) == []
 
 
-def test_ept_root_checked_and_map_pages_refused():
+def test_ept_root_checked():
     import numpy as np
     from oracle import Oracle
-    from oracle.oracle import MAP_DTYPE
     w = wl("ept")
     v = w.vms[0]
     for bad in (v.ept_root + 8, v.arena_bytes, v.arena_bytes - 2048):
         with pytest.raises(ValueError):
             Oracle([np.zeros(v.arena_bytes, np.uint8)], [v.slots], [(0, w.procs[0].cr3, 4)], w.pool_image(),
                    ept=[bad])
-    o = Oracle.from_workload(w)
-    with pytest.raises(ValueError):
-        o.map_pages(0, np.zeros(1, MAP_DTYPE), [])
+
+
+@pytest.mark.parametrize("name", ["ept", "pae", "lvl5"])
+def test_ept_map_equals_memslots(name):
+    """Mapping pages through an EPT that mirrors the memslots changes nothing."""
+    sp = SPECS[name] if SPECS[name].ept else SPECS[name].replace(ept=True)
+    assert pins.check_ept_map_equivalence(gen.make_workload(sp)) == []
+
+
+@pytest.mark.parametrize("name", ["ept_faults", "ept_pae"])
+def test_ept_map_bad_pool_frame(name):
+    assert pins.check_ept_map_bad_pool(wl(name)) == []
