@@ -224,7 +224,13 @@ int devirt_copy_to_guest(devirt_ctx *ctx, uint32_t asid, uint64_t gva, const voi
  * reports NO_POOL.  *n_used_dev (one uint64_t) receives the frames used.
  * pool_gpa_host: n_pool distinct, 4 KiB aligned frames inside memslots that
  * nothing else uses (-EINVAL otherwise); read before the call returns.
- * -EOPNOTSUPP when the process's VM translates through an EPT.
+ * A VM with an EPT (devirt_vm_set_ept): the tables are read and written
+ * through the EPT (a failure on the path reports DEVIRT_EPT_VIOLATION or
+ * DEVIRT_EPT_MISCONFIG at its level), and pool frames need only be aligned
+ * and distinct here: the frames the batch takes are translated through the
+ * EPT on the device, and if one is not readable and writable there, nothing
+ * is written and every map that would have succeeded reports NO_POOL.  The
+ * EPT entries for the mapped frames themselves are the hypervisor's.
  * Asynchronous on hip_stream; no other call may touch the process's tables
  * meanwhile. */
 typedef struct {

@@ -145,7 +145,9 @@ struct MapArgs {
     devirt_result *res;
     uint64_t *n_used;
     uint64_t n_pool;
-    const uint64_t *pool_gpa, *pool_hpa;  // device, n_pool each
+    const uint64_t *pool_gpa;             // device, n_pool
+    uint64_t *pool_hpa;                   // device, n_pool: from the host, or (ept_pool) from k_map_pool
+    int ept_pool;                         // the VM has an EPT: pool frames are translated on the device
     // the tables the batch lacks: a hash set of their keys (tset_log2 slots),
     // the distinct keys in insertion order (m = min(4n, n_pool) slots), sorted
     uint64_t *tset;

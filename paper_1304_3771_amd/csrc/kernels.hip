@@ -1359,9 +1359,10 @@ __device__ uint32_t map_walk(const DVm &v, const DProc &p, uint64_t gva, uint32_
     missing = 0;
     for (int lvl = (int)p.levels; lvl >= 2; --lvl) {
         uint64_t th;
-        if (!slot_lookup(v, table, th)) {
+        const uint32_t xc = gpa_xlat(v, table, kNeedTable, th);
+        if (xc) {
             level = (uint32_t)lvl;
-            return DEVIRT_NO_MEMSLOT;
+            return xc;
         }
         const uint64_t e = load_entry(v.arena, th + 8 * entry_index(p.levels, (uint32_t)lvl, gva));
         if (!(e & kP)) {
@@ -1377,9 +1378,10 @@ __device__ uint32_t map_walk(const DVm &v, const DProc &p, uint64_t gva, uint32_
         table = e & kAddrMask;
     }
     uint64_t th;
-    if (!slot_lookup(v, table, th)) {  // the page table itself
+    const uint32_t xc = gpa_xlat(v, table, kNeedTable, th);  // the page table itself
+    if (xc) {
         level = 1;
-        return DEVIRT_NO_MEMSLOT;
+        return xc;
     }
     return DEVIRT_OK;
 }
@@ -1390,10 +1392,10 @@ __device__ uint32_t map_walk(const DVm &v, const DProc &p, uint64_t gva, uint32_
 __device__ bool existing_table(const DVm &v, const DProc &p, uint64_t gva, uint32_t level, uint64_t &th) {
     uint64_t table = root_table(p);
     for (int lvl = (int)p.levels; lvl > (int)level; --lvl) {
-        if (!slot_lookup(v, table, th)) return false;
+        if (gpa_xlat(v, table, kNeedTable, th)) return false;
         table = load_entry(v.arena, th + 8 * entry_index(p.levels, (uint32_t)lvl, gva)) & kAddrMask;
     }
-    return slot_lookup(v, table, th);
+    return gpa_xlat(v, table, kNeedTable, th) == DEVIRT_OK;
 }
 
 // Position of key in the sorted keys[0, n), or -1.
@@ -1509,6 +1511,21 @@ __global__ void __launch_bounds__(256) k_map_walk(MapArgs a) {
         if (k[j] != ~0ull && (lane == 0 || prev != k[j])) tset_insert(a, k[j]);
     }
     if (ok) page_note(a, gva >> 12, i);
+}
+
+// A VM with an EPT: the pool frames the batch takes (the first sc[0]) are
+// translated through the EPT, readable and writable like every table frame;
+// one that is not makes the batch fail as a short pool does (sc[3]).
+__global__ void __launch_bounds__(256) k_map_pool(const MapArgs a) {
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nt = a.sc[0];
+    if (a.sc[3] || nt > a.n_pool || k >= nt || a.asid >= a.v.nproc) return;
+    const DVm vm = a.v.vms[a.v.procs[a.asid].vm];
+    uint64_t h = 0;
+    if (gpa_xlat(vm, a.pool_gpa[k], kNeedTable, h) == DEVIRT_OK)
+        a.pool_hpa[k] = h;
+    else
+        __hip_atomic_store(&a.sc[3], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Tables to create: 0 when the pool is too small (then nothing is written).
@@ -1628,6 +1645,7 @@ hipError_t launch_map(hipStream_t s, const MapArgs &a) {
     hipLaunchKernelGGL(k_map_clear, dim3(blocks_for(std::min<uint64_t>(ones + zeros, 1ull << 22))), dim3(256), 0, s,
                        a.tset, ones, a.pidx, zeros);
     hipLaunchKernelGGL(k_map_walk, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
+    if (a.ept_pool) hipLaunchKernelGGL(k_map_pool, dim3(blocks_for(a.m)), dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (a.rank) {
         // enough lanes to zero every possible new table in one sweep (at most 2^22)

@@ -546,9 +546,19 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     if (set_dev(c)) return -EIO;
     // the pool: aligned, distinct frames inside memslots of the process's VM
     std::vector<uint64_t> hpa(n_pool);
-    if (asid < c->procs.size() && c->vms[c->procs[asid].vm].ept_root != ~0ull)
-        return dv_fail(-EOPNOTSUPP, "mapping pages is defined for memslot VMs only");
-    if (asid < c->procs.size() && n_pool) {
+    // A VM with an EPT: frames are checked for alignment and repeats here;
+    // their translation happens on the device, through the EPT.
+    const bool ept = asid < c->procs.size() && c->vms[c->procs[asid].vm].ept_root != ~0ull;
+    if (ept) {
+        for (uint64_t k = 0; k < n_pool; ++k)
+            if (pool_gpa[k] & 0xFFF)
+                return dv_fail(-EINVAL, "pool frame %#llx is unaligned", (unsigned long long)pool_gpa[k]);
+        std::vector<uint64_t> sorted(pool_gpa, pool_gpa + n_pool);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return dv_fail(-EINVAL, "pool frames must be distinct");
+    }
+    if (asid < c->procs.size() && n_pool && !ept) {
         const VmHost &v = c->vms[c->procs[asid].vm];
         std::vector<const VmHost::Slot *> sl;
         for (const auto &x : v.slots)
@@ -611,6 +621,7 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     a.tkeys_sorted = b + T + m + 2 * P + 4;
     a.pool_gpa = b + T + 2 * m + 2 * P + 4;
     a.pool_hpa = b + T + 2 * m + 2 * P + 4 + n_pool;
+    a.ept_pool = ept ? 1 : 0;
     a.temp = nullptr;
     size_t need = 0;
     a.temp_query = &need;

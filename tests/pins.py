@@ -159,6 +159,17 @@ def free_frames(wl, vm, count, rng):
     return (rng.choice(cand, count, replace=False).astype(np.uint64) << np.uint64(12))
 
 
+def usable_frames(wl, vm, frames):
+    """The frames a VM's EPT maps readable and writable (by the generator's
+    leaf list); all of them for a memslot VM."""
+    lf = wl.vms[vm].ept_leaf
+    if lf is None:
+        return frames
+    from workload.gen import EPT_LEAF_OK
+    kind = lf["kind"][np.searchsorted(lf["gpa"], frames, side="right") - 1]
+    return frames[kind == EPT_LEAF_OK]
+
+
 def map_batch(wl, rng, n=600):
     """Maps for process 0: remaps of mapped 4 KiB pages, pages in mapped and in
     empty regions, pages inside large leaves, out-of-range pages, duplicates."""

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import pins
-from gpu_util import compare, gpu_batch, log, new_ctx
+from gpu_util import compare, log, new_ctx
 from oracle import Oracle
 from workload import device, gen
 
@@ -80,6 +80,8 @@ def test_golden_maps(widx):
         ctx.vm_write(vm, 0, arena)
         for i, s in enumerate(w["slots"]):
             ctx.memslot_set(vm, i, H(s["gpa"]), H(s["bytes"]), H(s["arena_off"]))
+        if "ept_root" in w:
+            ctx.vm_set_ept(vm, H(w["ept_root"]))
         assert ctx.process_create(vm, H(w["cr3"]), w["levels"]) == 0
         gm = w["maps"]
         m = np.zeros(len(gm["batch"]), MAP_DTYPE)
@@ -97,7 +99,8 @@ def test_golden_maps(widx):
         ctx.close()
 
 
-@pytest.mark.parametrize("name", ["c1", "mix2m", "lvl5", "lvl5_1g", "pae", "pae_prot", "multi_vm"])
+@pytest.mark.parametrize("name", ["c1", "mix2m", "lvl5", "lvl5_1g", "pae", "pae_prot", "multi_vm", "ept",
+                                  "ept_faults", "ept_pae"])
 def test_map_matches_oracle(name):
     """A mixed batch (remaps, new regions, pages inside large leaves, out of
     range, duplicates): a too-small pool first (nothing written), then enough,
@@ -108,7 +111,7 @@ def test_map_matches_oracle(name):
     rng = np.random.default_rng(11)
     m = pins.map_batch(w, rng)
     vm = w.procs[0].vm
-    pool = pins.free_frames(w, vm, 3 * len(m), rng)
+    pool = pins.usable_frames(w, vm, pins.free_frames(w, vm, 4 * len(m), rng))
     o = Oracle.from_workload(w)
     ctx = new_ctx()
     try:
@@ -128,9 +131,22 @@ def test_map_matches_oracle(name):
         er, eused = o.map_pages(0, m[::-1].copy(), pool[need:])
         _same(f"{name} again", r, used, er, eused, device.read_arenas(ctx, dw), o.arenas)
         assert used == 0
-        got = gpu_batch(w, ctx=ctx, dw=dw)
-        res, faults = o.batch(w.requests)
-        assert compare(f"{name} batch after map", got, (res, faults, o.arenas, o.pool)) == []
+        # remapped pages may now alias other requests' bytes, so the
+        # workload's epochs no longer separate conflicting requests: one
+        # request per epoch keeps the batch's precondition
+        import torch
+        import paper_1304_3771_amd as dv
+        n = dw.n
+        res = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+        faults = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+        nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ctx.submit_batch(dw.reqs, n, res, np.arange(1, n + 1, dtype=np.uint64), faults, nf)
+        ctx.sync()
+        k = int(nf.item())
+        got = (res.cpu().numpy()[:n * 24].view(dv.RESULT_DTYPE), faults.cpu().numpy()[:k * 24].view(dv.FAULT_DTYPE),
+               device.read_arenas(ctx, dw), dw.pool.cpu().numpy())
+        eres, efaults = o.batch(w.requests)
+        assert compare(f"{name} batch after map", got, (eres, efaults, o.arenas, o.pool)) == []
     finally:
         ctx.close()
 
@@ -209,26 +225,32 @@ def test_map_edge_cases():
         ctx.close()
 
 
-def test_map_refused_on_ept_vm():
-    """Mapping pages is defined for memslot VMs; an EPT VM is refused before any work."""
-    import torch
-    import paper_1304_3771_amd as dv
-    from oracle.oracle import MAP_DTYPE
-    w = wl("ept")
-    log("map on an EPT VM")
+def test_map_ept_bad_pool_frame():
+    """EPT VM: a pool frame the batch takes that the EPT does not map readable
+    and writable fails the batch (NO_POOL, nothing written); past the frames
+    the batch takes it changes nothing.  Compared with the oracle."""
+    from workload.gen import EPT_LEAF_NP, EPT_LEAF_OK, EPT_LEAF_RO
+    w = wl("ept_faults")
+    log("map: EPT VM, bad pool frames")
+    rng = np.random.default_rng(8)
+    p = w.procs[0]
+    lf = w.vms[p.vm].ept_leaf
+    m = pins.map_batch(w, rng)
+    cand = pins.free_frames(w, p.vm, 4000, rng)
+    kind = lf["kind"][np.searchsorted(lf["gpa"], cand, side="right") - 1]
+    good = cand[kind == EPT_LEAF_OK]
+    _, need = Oracle.from_workload(w).map_pages(0, m, good)
+    assert need >= 2
+    pools = [np.concatenate([good[:need // 2], cand[kind == k][:1], good[need // 2:]]) for k in (EPT_LEAF_NP, EPT_LEAF_RO)]
+    pools.append(np.concatenate([good[:need], cand[kind == EPT_LEAF_NP][:1]]))
+    o = Oracle.from_workload(w)
     ctx = new_ctx()
     try:
         dw = device.load(ctx, w)
-        a0 = device.read_arenas(ctx, dw)
-        m = np.zeros(4, MAP_DTYPE)
-        m["gva"] = np.arange(4, dtype=np.uint64) << np.uint64(12)
-        dm = torch.from_numpy(m.view(np.uint8).copy()).cuda()
-        res = torch.zeros(4 * 24, dtype=torch.uint8, device="cuda")
-        nu = torch.zeros(1, dtype=torch.int64, device="cuda")
-        with pytest.raises(dv.DevirtError) as ei:
-            ctx.map_pages(0, dm, 4, [], res, nu)
-        assert ei.value.rc == -95
-        torch.cuda.synchronize()
-        assert all(np.array_equal(a, b) for a, b in zip(a0, device.read_arenas(ctx, dw)))
+        for k, pool in enumerate(pools):
+            r, used = _gpu_map(ctx, 0, m, pool)
+            er, eused = o.map_pages(0, m, pool)
+            _same(f"bad pool {k}", r, used, er, eused, device.read_arenas(ctx, dw), o.arenas)
+            assert (used == 0) == (k < 2)
     finally:
         ctx.close()
