@@ -45,14 +45,19 @@ int main(void) {
          sizeof(devirt_server_cfg), sizeof(devirt_completion));
   printf("%zu %zu %zu %zu\n", offsetof(devirt_request, dir), offsetof(devirt_request, tag),
          offsetof(devirt_xlat, page_shift), offsetof(devirt_completion, t_done_ns));
+  printf("%zu %zu %zu %zu\n", sizeof(devirt_map), offsetof(devirt_map, gpa), offsetof(devirt_map, flags),
+         sizeof(devirt_server_stats));
   return 0;
 }
 ''')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
-    a, b = subprocess.check_output([str(exe)]).decode().split("\n")[:2]
+    a, b, c = subprocess.check_output([str(exe)]).decode().split("\n")[:3]
     sizes = list(map(int, a.split()))
     offs = list(map(int, b.split()))
+    import ctypes
+    assert list(map(int, c.split())) == [dv.MAP_DTYPE.itemsize, dv.MAP_DTYPE.fields["gpa"][1],
+                                         dv.MAP_DTYPE.fields["flags"][1], ctypes.sizeof(binding.ServerStats)]
     import ctypes
     assert sizes == [dv.REQUEST_DTYPE.itemsize, dv.RESULT_DTYPE.itemsize, dv.FAULT_DTYPE.itemsize,
                      dv.XLAT_DTYPE.itemsize, ctypes.sizeof(binding.Config), ctypes.sizeof(binding.Stats),
