@@ -136,6 +136,7 @@ constexpr int kFaultTile = 1024;
 
 // devirt_map_pages: device buffers and arguments of one call.
 constexpr uint64_t kMapMax = 1ull << 19;      // maps per call
+constexpr int kMapIdxBits = 19;               // map index bits in a page-set slot
 constexpr uint64_t kMapRankMax = 1ull << 14;  // longest key list sorted by rank in LDS tiles
 struct MapArgs {
     DView v;
@@ -155,8 +156,8 @@ struct MapArgs {
     uint64_t *tkeys, *tkeys_sorted;
     uint64_t m;
     int rank;                             // sort by rank (m <= kMapRankMax), else a library radix sort
-    // pages: a hash map page -> highest map index (pset_log2 slots)
-    uint64_t *pkey, *pidx;
+    // pages: a hash set of (page << kMapIdxBits | highest map index), ~0 when empty
+    uint64_t *pset;
     uint32_t pset_log2;
     uint64_t *sc;                         // 4 scalars
     void *temp;                           // sort scratch

@@ -1416,15 +1416,17 @@ __device__ __forceinline__ uint64_t hash_slot(uint64_t key, uint32_t log2) {
     return (key * 0x9E3779B97F4A7C15ull) >> (64 - log2);
 }
 
-// Adds a table key to the set; its first inserter also appends it to the
-// list tkeys[0, m).  sc[0] counts distinct keys.  After a collision the probe
-// gives up, with sc[3] set, once more than m distinct keys exist (the count
-// is read only then: every read of one address is serialized).  Every probe
-// loop is bounded by the set's size.
-__device__ void tset_insert(const MapArgs &a, uint64_t key) {
+// Adds a table key to the set, probing from slot h (the key's probe number
+// `probe` there); its first inserter also appends it to the list tkeys[0, m).
+// sc[0] counts distinct keys.  A long probe chain gives up, with sc[3] set,
+// once more than m distinct keys exist: the set holds at least twice m + 1
+// slots, so chains grow long only then, and the count (an address every new
+// key increments, so reads of it serialize) is read only on such chains.
+// Every probe loop is bounded by the set's size.
+constexpr uint64_t kLongChain = 8;
+__device__ void tset_insert_from(const MapArgs &a, uint64_t key, uint64_t h, uint64_t probe) {
     const uint64_t mask = (1ull << a.tset_log2) - 1;
-    uint64_t h = hash_slot(key, a.tset_log2);
-    for (uint64_t probe = 0; probe <= mask; ++probe) {
+    for (; probe <= mask; ++probe) {
         const uint64_t cur = atomicCAS((unsigned long long *)&a.tset[h], ~0ull, (unsigned long long)key);
         if (cur == ~0ull) {
             const uint64_t idx = atomicAdd((unsigned long long *)&a.sc[0], 1ull);
@@ -1432,21 +1434,51 @@ __device__ void tset_insert(const MapArgs &a, uint64_t key) {
             return;
         }
         if (cur == key) return;
-        if (__hip_atomic_load(&a.sc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > a.m) break;
+        if (probe >= kLongChain && __hip_atomic_load(&a.sc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > a.m)
+            break;
         h = (h + 1) & mask;
     }
     __hip_atomic_store(&a.sc[3], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Records map i for its page: the slot keeps the highest index (the set has
-// at least twice as many slots as maps, so a free slot is always found).
+// A lane's (up to four) table keys: the first probes are issued together, so
+// the lane waits for one atomic round trip, not one per key; a key whose first
+// slot holds another key continues in tset_insert_from.
+__device__ void tset_insert4(const MapArgs &a, const uint64_t (&key)[4], const bool (&want)[4]) {
+    const uint64_t mask = (1ull << a.tset_log2) - 1;
+    uint64_t h[4], cur[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        h[j] = hash_slot(key[j], a.tset_log2);
+        cur[j] = want[j] ? (uint64_t)atomicCAS((unsigned long long *)&a.tset[h[j]], ~0ull,
+                                               (unsigned long long)key[j])
+                         : key[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!want[j] || cur[j] == key[j]) continue;
+        if (cur[j] == ~0ull) {
+            const uint64_t idx = atomicAdd((unsigned long long *)&a.sc[0], 1ull);
+            if (idx < a.m) a.tkeys[idx] = key[j];
+        } else {
+            tset_insert_from(a, key[j], (h[j] + 1) & mask, 1);
+        }
+    }
+}
+
+// Records map i for its page: a slot holds (page << kMapIdxBits | index), and
+// a later map of the same page raises it with atomicMax, so the slot ends up
+// naming the page's last map.  A page seen once costs one atomic.  The set
+// has at least twice as many slots as maps, so a free slot is always found.
 __device__ void page_note(const MapArgs &a, uint64_t page, uint64_t i) {
     const uint64_t mask = (1ull << a.pset_log2) - 1;
+    const uint64_t v = (page << kMapIdxBits) | i;
     uint64_t h = hash_slot(page, a.pset_log2);
     for (uint64_t probe = 0; probe <= mask; ++probe) {
-        const uint64_t cur = atomicCAS((unsigned long long *)&a.pkey[h], ~0ull, (unsigned long long)page);
-        if (cur == ~0ull || cur == page) {
-            atomicMax((unsigned long long *)&a.pidx[h], (unsigned long long)i);
+        const uint64_t cur = atomicCAS((unsigned long long *)&a.pset[h], ~0ull, (unsigned long long)v);
+        if (cur == ~0ull) return;
+        if ((cur >> kMapIdxBits) == page) {
+            atomicMax((unsigned long long *)&a.pset[h], (unsigned long long)v);
             return;
         }
         h = (h + 1) & mask;
@@ -1505,11 +1537,13 @@ __global__ void __launch_bounds__(256) k_map_walk(MapArgs a) {
         a.res[i] = r;
     }
     const int lane = lane_id();
+    bool want[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint64_t prev = shfl64(k[j], lane > 0 ? lane - 1 : 0);
-        if (k[j] != ~0ull && (lane == 0 || prev != k[j])) tset_insert(a, k[j]);
+        want[j] = k[j] != ~0ull && (lane == 0 || prev != k[j]);
     }
+    tset_insert4(a, k, want);
     if (ok) page_note(a, gva >> 12, i);
 }
 
@@ -1616,8 +1650,8 @@ __global__ void __launch_bounds__(256) k_map_write(const MapArgs a) {
     const uint64_t page = m.gva >> 12;
     const uint64_t mask = (1ull << a.pset_log2) - 1;
     uint64_t h = hash_slot(page, a.pset_log2);
-    for (uint64_t probe = 0; probe <= mask && a.pkey[h] != page; ++probe) h = (h + 1) & mask;
-    if (a.pkey[h] != page || a.pidx[h] != t) return;
+    for (uint64_t probe = 0; probe <= mask && (a.pset[h] >> kMapIdxBits) != page; ++probe) h = (h + 1) & mask;
+    if (a.pset[h] != ((page << kMapIdxBits) | t)) return;  // not the page's last map
     const int64_t j = find_key(uniq, nt, map_key(1, m.gva));
     uint64_t pt = 0;
     if (j >= 0)
@@ -1640,10 +1674,10 @@ hipError_t launch_map(hipStream_t s, const MapArgs &a) {
         return hipSuccess;
     }
     const uint64_t nset = (1ull << a.tset_log2), npset = (1ull << a.pset_log2);
-    // tset, tkeys and pkey are contiguous, then pidx and sc
-    const uint64_t ones = nset + a.m + npset, zeros = npset + 4;
+    // tset, tkeys and pset are contiguous, then sc
+    const uint64_t ones = nset + a.m + npset, zeros = 4;
     hipLaunchKernelGGL(k_map_clear, dim3(blocks_for(std::min<uint64_t>(ones + zeros, 1ull << 22))), dim3(256), 0, s,
-                       a.tset, ones, a.pidx, zeros);
+                       a.tset, ones, a.sc, zeros);
     hipLaunchKernelGGL(k_map_walk, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
     if (a.ept_pool) hipLaunchKernelGGL(k_map_pool, dim3(blocks_for(a.m)), dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -597,7 +597,7 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     };
     const uint32_t tl = log2_for(m + 1), pl = log2_for(n);
     const uint64_t T = 1ull << tl, P = 1ull << pl;
-    const uint64_t words = T + m + P + P + 4 + m + 2 * n_pool;
+    const uint64_t words = T + m + P + 4 + m + 2 * n_pool;
     int rc;
     if ((rc = grow(c, w, w->map_buf, w->map_cap, words, "map buffers"))) return rc;
     uint64_t *b = w->map_buf;
@@ -609,18 +609,17 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     a.res = res;
     a.n_used = n_used;
     a.n_pool = n_pool;
-    a.tset = b;  // tset, tkeys, pkey: cleared to ~0 together; pidx, sc: to 0
+    a.tset = b;  // tset, tkeys, pset: cleared to ~0 together; sc: to 0
     a.tset_log2 = tl;
     a.tkeys = b + T;
     a.m = m;
     a.rank = m <= kMapRankMax;
-    a.pkey = b + T + m;
-    a.pidx = b + T + m + P;
+    a.pset = b + T + m;
     a.pset_log2 = pl;
-    a.sc = b + T + m + 2 * P;
-    a.tkeys_sorted = b + T + m + 2 * P + 4;
-    a.pool_gpa = b + T + 2 * m + 2 * P + 4;
-    a.pool_hpa = b + T + 2 * m + 2 * P + 4 + n_pool;
+    a.sc = b + T + m + P;
+    a.tkeys_sorted = b + T + m + P + 4;
+    a.pool_gpa = b + T + 2 * m + P + 4;
+    a.pool_hpa = b + T + 2 * m + P + 4 + n_pool;
     a.ept_pool = ept ? 1 : 0;
     a.temp = nullptr;
     size_t need = 0;
