@@ -544,26 +544,12 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     if (((uintptr_t)maps & 7) || ((uintptr_t)res & 7)) return dv_fail(-EINVAL, "maps and res must be 8-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     if (set_dev(c)) return -EIO;
-    // the pool: aligned, distinct frames inside memslots of the process's VM
+    // The pool: aligned, distinct frames.  For a memslot VM each must lie in a
+    // memslot, which gives its arena offset here; for a VM with an EPT the
+    // frames are translated on the device, through the EPT.
     std::vector<uint64_t> hpa(n_pool);
-    // A VM with an EPT: frames are checked for alignment and repeats here;
-    // their translation happens on the device, through the EPT.
     const bool ept = asid < c->procs.size() && c->vms[c->procs[asid].vm].ept_root != ~0ull;
-    if (ept) {
-        for (uint64_t k = 0; k < n_pool; ++k)
-            if (pool_gpa[k] & 0xFFF)
-                return dv_fail(-EINVAL, "pool frame %#llx is unaligned", (unsigned long long)pool_gpa[k]);
-        std::vector<uint64_t> sorted(pool_gpa, pool_gpa + n_pool);
-        std::sort(sorted.begin(), sorted.end());
-        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
-            return dv_fail(-EINVAL, "pool frames must be distinct");
-    }
-    if (asid < c->procs.size() && n_pool && !ept) {
-        const VmHost &v = c->vms[c->procs[asid].vm];
-        std::vector<const VmHost::Slot *> sl;
-        for (const auto &x : v.slots)
-            if (x.used) sl.push_back(&x);
-        std::sort(sl.begin(), sl.end(), [](const VmHost::Slot *p, const VmHost::Slot *q) { return p->gpa < q->gpa; });
+    if (asid < c->procs.size() && n_pool) {
         // distinct: a strictly ascending pool (the usual case) needs no sort
         bool ascending = true;
         for (uint64_t k = 1; k < n_pool && ascending; ++k) ascending = pool_gpa[k - 1] < pool_gpa[k];
@@ -573,6 +559,16 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
             if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
                 return dv_fail(-EINVAL, "pool frames must be distinct");
         }
+        for (uint64_t k = 0; k < n_pool; ++k)
+            if (pool_gpa[k] & 0xFFF)
+                return dv_fail(-EINVAL, "pool frame %#llx is unaligned", (unsigned long long)pool_gpa[k]);
+    }
+    if (asid < c->procs.size() && n_pool && !ept) {
+        const VmHost &v = c->vms[c->procs[asid].vm];
+        std::vector<const VmHost::Slot *> sl;
+        for (const auto &x : v.slots)
+            if (x.used) sl.push_back(&x);
+        std::sort(sl.begin(), sl.end(), [](const VmHost::Slot *p, const VmHost::Slot *q) { return p->gpa < q->gpa; });
         const VmHost::Slot *q = nullptr;  // the slot of the previous frame, tried first
         for (uint64_t k = 0; k < n_pool; ++k) {
             const uint64_t g = pool_gpa[k];
@@ -582,8 +578,8 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
                                            [](uint64_t x, const VmHost::Slot *r) { return x < r->gpa; });
                 q = it == sl.begin() ? nullptr : *(it - 1);
             }
-            if ((g & 0xFFF) || !q || g - q->gpa >= q->bytes)
-                return dv_fail(-EINVAL, "pool frame %#llx is unaligned or outside every memslot", (unsigned long long)g);
+            if (!q || g - q->gpa >= q->bytes)
+                return dv_fail(-EINVAL, "pool frame %#llx is outside every memslot", (unsigned long long)g);
             hpa[k] = q->off + (g - q->gpa);
         }
     }

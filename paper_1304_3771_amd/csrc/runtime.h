@@ -48,9 +48,9 @@ struct Workspace {
     hipStream_t side = nullptr;         // translate launches run here, ahead of the copies
     std::vector<hipEvent_t> events;     // per epoch: translate done, copy done; plus the fork
     // devirt_map_pages
-    uint64_t *map_buf = nullptr;        // keys, sorted keys, unique keys, map keys, scalars, pool
+    uint64_t *map_buf = nullptr;        // table-key set and lists, page set, scalars, pool
     uint64_t map_cap = 0;
-    uint8_t *map_temp = nullptr;        // sort / unique scratch
+    uint8_t *map_temp = nullptr;        // radix-sort scratch (long key lists)
     uint64_t map_temp_cap = 0;
     uint64_t *map_pool_host = nullptr;  // pinned staging of the pool (gpa, hpa)
     uint64_t map_pool_host_cap = 0;
