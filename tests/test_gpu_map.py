@@ -254,3 +254,44 @@ def test_map_ept_bad_pool_frame():
             assert (used == 0) == (k < 2)
     finally:
         ctx.close()
+
+
+def test_map_full_size_c2():
+    """At the benchmark's size: 2^19 maps per call on C2's tables (4 GiB guest),
+    a fresh batch then a remap batch as the benchmark makes them; results,
+    frames used and every arena byte against the oracle."""
+    import sys
+    import torch
+    import os
+    import paper_1304_3771_amd as dv
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    log("map full size: generating C2")
+    w = gen.make_workload(gen.spec("C2"), requests=False)
+    p = w.procs[0]
+    n = 1 << 19
+    mem = w.vms[p.vm].mem_bytes >> 12
+    free = bench.free_guest_frames(w, p.vm)
+    rng = np.random.default_rng(21)
+    batches = [bench.map_fresh_batch(rng, n, 1 << 47, mem, dv.MAP_DTYPE, dv.MAP_WRITE),
+               bench.map_remap_batch(rng, n, p, mem, dv.MAP_DTYPE)]
+    o = Oracle.from_workload(w)
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        log("map full size: uploaded")
+        nxt = 0
+        for k, m in enumerate(batches):
+            pool = free[nxt:nxt + 4096]
+            r, used = _gpu_map(ctx, 0, m, pool)
+            er, eused = o.map_pages(0, m, pool)
+            assert np.array_equal(r.view(np.uint8), er.view(np.uint8)), f"batch {k}: results differ"
+            assert used == eused and (used > 0) == (k == 0), (k, used, eused)
+            nxt += used
+        torch.cuda.synchronize()
+        a = device.read_arenas(ctx, dw)[0]
+        bad = np.count_nonzero(a != o.arenas[0])
+        assert bad == 0, f"{bad} arena bytes differ"
+        log(f"map full size: bit-exact, {nxt} new tables")
+    finally:
+        ctx.close()
