@@ -248,14 +248,28 @@ static int in_arena(const orc_vm *v, uint64_t off) {
     return off < v->arena_bytes && v->arena_bytes - off >= 4096;
 }
 
+/* Arena offsets of every table entry a walk loads (guest tables at every
+ * level, the PAE root table, EPT tables).  Only the conflict checker asks
+ * for them; every other caller passes NULL. */
+typedef struct {
+    uint32_t n;
+    uint64_t off[40];
+} reads_t;
+
+static void note_read(reads_t *rec, uint64_t off) {
+    if (rec && rec->n < 40) rec->off[rec->n++] = off;
+}
+
 /* GPA -> arena offset by walking the VM's EPT (see the header comment). */
-static uint32_t ept_walk(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t *hpa) {
+static uint32_t ept_walk(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t *hpa, reads_t *rec) {
     if (gpa >> 48) return ORC_EPT_VIOLATION;
     uint64_t table = v->ept_root;
     int can_r = 1, can_w = 1;
     for (int lvl = 4; lvl >= 1; lvl--) {
         uint32_t eshift = 12u + 9u * (uint32_t)(lvl - 1);
-        uint64_t e = load64(v->arena + table + 8 * ((gpa >> eshift) & 511));
+        uint64_t eoff = table + 8 * ((gpa >> eshift) & 511);
+        note_read(rec, eoff);
+        uint64_t e = load64(v->arena + eoff);
         if ((e & 7) == 0) return ORC_EPT_VIOLATION;
         if ((e & 3) == 2) return ORC_EPT_MISCONFIG;
         can_r &= (int)(e & 1);
@@ -282,9 +296,13 @@ static uint32_t ept_walk(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t 
 
 /* GPA -> arena offset for an access that needs `need`: the EPT walk, or the
  * memslots when the VM has no EPT. */
-static uint32_t gpa_to_hpa(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t *hpa) {
-    if (v->has_ept) return ept_walk(v, gpa, need, hpa);
+static uint32_t gpa_to_hpa_rec(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t *hpa, reads_t *rec) {
+    if (v->has_ept) return ept_walk(v, gpa, need, hpa, rec);
     return slot_lookup(v, gpa, hpa) ? ORC_OK : ORC_NO_MEMSLOT;
+}
+
+static uint32_t gpa_to_hpa(const orc_vm *v, uint64_t gpa, uint32_t need, uint64_t *hpa) {
+    return gpa_to_hpa_rec(v, gpa, need, hpa, NULL);
 }
 
 /* ----------------------------------------------------------------- walk -- */
@@ -304,7 +322,7 @@ typedef struct {
 #define ORC_PAE_PDPTE_RSVD 0xFFF00000000001E6ull   /* bits 63:52, 8:5, 2:1 */
 #define ORC_PAE_RSVD 0x7FF0000000000000ull         /* bits 62:52 of a PAE PDE/PTE */
 
-static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write, walk_t *w) {
+static void walk_rec(const orc_state *s, const orc_proc *p, uint64_t gva, int write, walk_t *w, reads_t *rec) {
     const orc_vm *v = &s->vms[p->vm];
     uint64_t table = p->cr3 & ORC_ADDR_MASK;
     int user_ok = 1, write_ok = 1;
@@ -317,13 +335,15 @@ static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write,
          * accessed-bit path and grants every permission */
         uint64_t pdpt = p->cr3 & 0xFFFFFFE0ull;
         uint64_t thpa;
-        uint32_t c = gpa_to_hpa(v, pdpt, ORC_NEED_TABLE, &thpa);
+        uint32_t c = gpa_to_hpa_rec(v, pdpt, ORC_NEED_TABLE, &thpa, rec);
         if (c != ORC_OK) {
             w->code = c;
             w->level = 3;
             return;
         }
-        uint64_t e = load64(v->arena + thpa + 8 * ((gva >> 30) & 3));
+        uint64_t roff = thpa + 8 * ((gva >> 30) & 3);
+        note_read(rec, roff);
+        uint64_t e = load64(v->arena + roff);
         if (!(e & ORC_P)) {
             w->code = ORC_NOT_PRESENT;
             w->level = 3;
@@ -341,13 +361,14 @@ static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write,
         uint32_t shift = 12 + 9 * (uint32_t)(lvl - 1);
         uint64_t idx = (gva >> shift) & 511;
         uint64_t thpa;
-        uint32_t c = gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);
+        uint32_t c = gpa_to_hpa_rec(v, table, ORC_NEED_TABLE, &thpa, rec);
         if (c != ORC_OK) {
             w->code = c;
             w->level = (uint32_t)lvl;
             return;
         }
         uint64_t eoff = thpa + 8 * idx;
+        note_read(rec, eoff);
         uint64_t e = load64(v->arena + eoff);
         w->path[w->npath++] = eoff;
         if (!(e & ORC_P)) {
@@ -399,7 +420,7 @@ static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write,
         w->level = w->leaf_level;
         return;
     }
-    uint32_t c = gpa_to_hpa(v, w->gpa, write ? ORC_NEED_W : ORC_NEED_R, &w->hpa);
+    uint32_t c = gpa_to_hpa_rec(v, w->gpa, write ? ORC_NEED_W : ORC_NEED_R, &w->hpa, rec);
     if (c != ORC_OK) {
         w->code = c;
         w->level = 0;
@@ -407,6 +428,10 @@ static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write,
         return;
     }
     w->code = ORC_OK;
+}
+
+static void walk(const orc_state *s, const orc_proc *p, uint64_t gva, int write, walk_t *w) {
+    walk_rec(s, p, gva, write, w, NULL);
 }
 
 /* OR the accessed bit into every entry of the walk and, when writing, the
@@ -544,18 +569,32 @@ int64_t orc_batch_results(orc_state *s, const orc_req *reqs, uint64_t n, orc_res
 }
 
 /* ------------------------------------------------------ conflict checker -- */
-/* The batch precondition: inside one epoch, no two requests touch
- * overlapping guest bytes (same VM) or overlapping pool bytes where at least
- * one of them writes, and no request copies into a page-table frame the
- * epoch walks.  This checker translates every page of every request with
- * the walk above (no side effects), collects byte intervals and sorts them.
- * Returns 0 when the batch is conflict-free, else 1 and the pair in *a, *b. */
+/* The batch precondition, in two rules.
+ *   1. Inside one epoch, no two requests touch overlapping guest bytes (same
+ *      VM) or overlapping pool bytes where at least one of them writes.
+ *   2. Across the whole batch, no request's guest bytes (read or written)
+ *      lie in a frame that holds an entry some walk of the batch loads: a
+ *      guest page table at any level, the PAE root table, an EPT table.
+ * Rule 2 spans epochs because a batched run may translate one epoch while
+ * the previous one is being copied, and it covers reads too because walks
+ * OR accessed/dirty bits into the entries they load.  For rule 2 every page
+ * of a request's range is walked, including pages after its first fault,
+ * since a parallel run translates a request's pages side by side.
+ * The checker walks with the walker above (no side effects), collects byte
+ * intervals and table frames and sorts them.  Returns 0 when the batch
+ * meets both rules, 1 with the offending pair in *ra, *rb (for rule 2: the
+ * request whose bytes lie in the table, then a request whose walk loads
+ * it), -1 when out of memory. */
 typedef struct {
     uint64_t key;      /* vm (or 0xFFFFFFFF for the pool) */
     uint64_t lo, hi;
     uint64_t req;
     int write;
 } ival;
+
+typedef struct {
+    uint64_t vm, frame, req;
+} tframe;
 
 static int ival_cmp(const void *x, const void *y) {
     const ival *a = (const ival *)x, *b = (const ival *)y;
@@ -564,6 +603,14 @@ static int ival_cmp(const void *x, const void *y) {
     return 0;
 }
 
+static int tframe_cmp(const void *x, const void *y) {
+    const tframe *a = (const tframe *)x, *b = (const tframe *)y;
+    if (a->vm != b->vm) return a->vm < b->vm ? -1 : 1;
+    if (a->frame != b->frame) return a->frame < b->frame ? -1 : 1;
+    return 0;
+}
+
+/* Rule 1 for one epoch's intervals. */
 static int sweep(ival *v, uint64_t m, uint64_t *ra, uint64_t *rb) {
     qsort(v, m, sizeof(ival), ival_cmp);
     /* for each interval, compare with all earlier still-open intervals of the
@@ -575,7 +622,10 @@ static int sweep(ival *v, uint64_t m, uint64_t *ra, uint64_t *rb) {
             cur_key = v[i].key;
             w_hi = r_hi = 0;
         }
-        if (v[i].lo < w_hi && w_req != v[i].req) {
+        /* an earlier writer: a conflict with any request, itself included (one
+         * request's intervals share its direction, so two of them overlapping
+         * under a writer are two writes of aliased guest pages) */
+        if (v[i].lo < w_hi) {
             *ra = w_req; *rb = v[i].req; return 1;
         }
         if (v[i].write && v[i].lo < r_hi && r_req != v[i].req) {
@@ -590,16 +640,33 @@ static int sweep(ival *v, uint64_t m, uint64_t *ra, uint64_t *rb) {
     return 0;
 }
 
+/* Sort and deduplicate the table frames collected so far (one walker kept per frame). */
+static uint64_t compact_frames(tframe *t, uint64_t m) {
+    if (m == 0) return 0;
+    qsort(t, m, sizeof(tframe), tframe_cmp);
+    uint64_t k = 1;
+    for (uint64_t i = 1; i < m; i++)
+        if (t[i].vm != t[k - 1].vm || t[i].frame != t[k - 1].frame) t[k++] = t[i];
+    return k;
+}
+
 int orc_check_conflicts(orc_state *s, const orc_req *reqs, uint64_t n, const uint64_t *epoch_end,
                         uint32_t n_epochs, uint64_t *ra, uint64_t *rb) {
+    int rc = 0;
+    /* rule 2 material, whole batch: table frames walked, guest byte intervals */
+    uint64_t tcap = 1024, nt = 0, gcap = 1024, ng = 0;
+    tframe *tf = (tframe *)malloc(tcap * sizeof(tframe));
+    ival *gi = (ival *)malloc(gcap * sizeof(ival));
+    ival *v = NULL;
+    if (!tf || !gi) { rc = -1; goto out; }
     uint64_t start = 0;
     for (uint32_t e = 0; e < n_epochs || (n_epochs == 0 && start < n); e++) {
         uint64_t stop = n_epochs ? epoch_end[e] : n;
-        /* per page: up to 5 walked entries + 1 data interval; per request: 1 pool interval */
+        /* rule 1: per page 1 data interval; per request 1 pool interval */
         uint64_t cap = 1;
-        for (uint64_t i = start; i < stop; i++) cap += 6 * (((uint64_t)reqs[i].len + 4095) / 4096 + 1) + 1;
-        ival *v = (ival *)malloc(cap * sizeof(ival));
-        if (!v) return -1;
+        for (uint64_t i = start; i < stop; i++) cap += ((uint64_t)reqs[i].len + 4095) / 4096 + 2;
+        v = (ival *)malloc(cap * sizeof(ival));
+        if (!v) { rc = -1; goto out; }
         uint64_t m = 0;
         for (uint64_t i = start; i < stop; i++) {
             const orc_req *r = &reqs[i];
@@ -609,27 +676,71 @@ int orc_check_conflicts(orc_state *s, const orc_req *reqs, uint64_t n, const uin
             if (r->gva >= lim || (uint64_t)r->len > lim - r->gva) continue;
             int to_guest = r->dir != 0;
             uint64_t end = r->gva + r->len, done = r->len;
+            int faulted = 0;
             for (uint64_t page = r->gva & ~0xFFFull; page < end; page += 4096) {
                 uint64_t lo = page > r->gva ? page : r->gva;
                 uint64_t hi = page + 4096 < end ? page + 4096 : end;
                 walk_t w;
-                walk(s, p, lo, to_guest, &w);
-                /* the walk's entries are read (and A/D OR-ed, which commutes) */
-                for (uint32_t k = 0; k < w.npath; k++) {
-                    v[m++] = (ival){p->vm, w.path[k], w.path[k] + 8, i, 0};
+                reads_t rd;
+                rd.n = 0;
+                walk_rec(s, p, lo, to_guest, &w, &rd);
+                for (uint32_t k = 0; k < rd.n; k++) {
+                    if (nt == tcap) {
+                        nt = compact_frames(tf, nt);
+                        if (nt * 2 > tcap) {
+                            tframe *g = (tframe *)realloc(tf, 2 * tcap * sizeof(tframe));
+                            if (!g) { rc = -1; goto out; }
+                            tf = g;
+                            tcap *= 2;
+                        }
+                    }
+                    tf[nt++] = (tframe){p->vm, rd.off[k] & ~0xFFFull, i};
                 }
-                if (w.code != ORC_OK) { done = lo - r->gva; break; }
-                v[m++] = (ival){p->vm, w.hpa, w.hpa + (hi - lo), i, to_guest};
+                if (faulted) continue;
+                if (w.code != ORC_OK) { faulted = 1; done = lo - r->gva; continue; }
+                ival d = {p->vm, w.hpa, w.hpa + (hi - lo), i, to_guest};
+                v[m++] = d;
+                if (ng == gcap) {
+                    ival *g = (ival *)realloc(gi, 2 * gcap * sizeof(ival));
+                    if (!g) { rc = -1; goto out; }
+                    gi = g;
+                    gcap *= 2;
+                }
+                gi[ng++] = d;
             }
             if (done) v[m++] = (ival){0xFFFFFFFFull, r->host, r->host + done, i, !to_guest};
         }
         int bad = sweep(v, m, ra, rb);
         free(v);
-        if (bad) return 1;
+        v = NULL;
+        if (bad) { rc = 1; goto out; }
         start = stop;
         if (n_epochs == 0) break;
     }
-    return 0;
+    /* rule 2: does any guest byte interval touch a walked table frame? */
+    nt = compact_frames(tf, nt);
+    for (uint64_t i = 0; i < ng; i++) {
+        /* the first frame of this VM at or above the interval's first frame */
+        uint64_t lo = 0, hi = nt, f0 = gi[i].lo & ~0xFFFull;
+        while (lo < hi) {
+            uint64_t mid = (lo + hi) / 2;
+            if (tf[mid].vm < gi[i].key || (tf[mid].vm == gi[i].key && tf[mid].frame < f0))
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo < nt && tf[lo].vm == gi[i].key && tf[lo].frame < gi[i].hi) {
+            *ra = gi[i].req;
+            *rb = tf[lo].req;
+            rc = 1;
+            goto out;
+        }
+    }
+out:
+    free(v);
+    free(tf);
+    free(gi);
+    return rc;
 }
 
 /* ------------------------------------------------------------ map pages -- */

@@ -666,6 +666,9 @@ def small_specs():
                             ept=True, ept_np=0.03, ept_ro=0.05, ept_mis=0.02),
         "ept_1g": gen.spec("C5", n_vms=1, mem_bytes=3 * GiB // 2, n_slots=1, mapped_frac=0.7,
                            mix=(0.02, 0.02, 0.96), n_requests=200, len_hi=100000, seed=25, ept=True, ept_align=GiB),
+        # many epochs (each fills at most 10% of a VMA) that reuse guest and pool bytes across epochs
+        "epochs": gen.spec("C3", n_vms=2, procs_per_vm=2, mem_bytes=32 * MiB, n_requests=3000, len_hi=64 * KiB,
+                           rho=0.1, seed=31),
     }
 
 
@@ -819,4 +822,165 @@ def check_ept_map_bad_pool(wl, lib_path=None, seed=6):
             0, m, np.concatenate([good[:need], bad[:1]]))
         if used2 != need or not np.array_equal(r2, r0):
             fails.append(f"a {what} frame past the needed ones changed the result")
+    return fails
+
+
+# ------------------------------------------------------ conflict checker --
+_ADDR = 0x000FFFFFFFFFF000
+
+
+def _entry_off(wl, p, i):
+    """Arena offset of leaf i's entry (from the encoder's record of where it wrote it)."""
+    v = wl.vms[p.vm]
+    t = int(gen.gpa_to_arena(v.slots, np.array([int(p.leaf_table_gfn[i]) << 12], np.uint64))[0])
+    return t + 8 * int(p.leaf_index[i])
+
+
+def _set_u64(arena, off, val):
+    arena[off:off + 8] = np.frombuffer(int(val).to_bytes(8, "little"), np.uint8)
+
+
+def _req(gva, host, n, asid, d):
+    r = np.zeros(1, REQ_DTYPE)
+    r[0] = (gva, host, n, asid, d, (0, 0, 0), 0)
+    return r
+
+
+def _ept_leaf_off(arena, root, gpa):
+    """Arena offset of the EPT entry that maps gpa (generator-built EPT; no checks)."""
+    table = root
+    for lvl in (4, 3, 2, 1):
+        off = table + 8 * ((gpa >> (12 + 9 * (lvl - 1))) & 511)
+        e = _u64(arena, off)
+        if lvl == 1 or (e & 0x80):
+            return off, lvl
+        table = e & _ADDR
+
+
+def check_conflict_plants(lib_path=None):
+    """The conflict checker against planted batches whose answer follows from
+    the batch precondition: a request whose guest bytes lie in a page-table
+    frame that some walk loads (same epoch, a later or an earlier epoch, read
+    or write, a walk past the walker's first fault, the PAE root table, an EPT
+    table), writes to aliased guest pages, and overlaps inside one epoch.
+    Each plant rewrites a leaf so that a guest page lands on the frame in
+    question; the same requests without the plant must pass."""
+    fails = []
+    specs = small_specs()
+    W, R = gen.TO_GUEST, gen.FROM_GUEST
+
+    def check(tag, o, reqs, ends, want):
+        got = o.check_conflicts(np.concatenate(reqs), ends)
+        if (got is not None) != want:
+            fails.append(f"{tag}: checker says {got}, expected {'a conflict' if want else 'none'}")
+
+    # ---- 4-level world: leaf Y rewritten onto X's leaf table frame
+    wl = gen.make_workload(specs["c1"])
+    p = wl.procs[0]
+    four = np.nonzero((p.leaf_level == 1) & p.leaf_present)[0]
+    x = int(four[0])
+    fx = int(p.leaf_table_gfn[x]) << 12
+    y = int(next(i for i in four if int(p.leaf_table_gfn[i]) << 12 != fx))
+    z = int(next(i for i in four if int(p.leaf_table_gfn[i]) != p.leaf_table_gfn[x] and
+                 int(p.leaf_table_gfn[i]) != p.leaf_table_gfn[y] and i != y))
+    vx, vy, vz = int(p.leaf_va[x]), int(p.leaf_va[y]), int(p.leaf_va[z])
+
+    def world(plant):
+        a = wl.arena_image(0)
+        if plant:
+            off = _entry_off(wl, p, y)
+            _set_u64(a, off, (_u64(a, off) & ~_ADDR) | fx)
+        return Oracle([a], [wl.vms[0].slots], [(0, p.cr3, p.levels)], wl.pool_image(), lib_path=lib_path)
+
+    yw, yr = _req(vy + 100, 0, 64, 0, W), _req(vy + 100, 0, 64, 0, R)
+    xr, zr = _req(vx + 8, 4096, 64, 0, R), _req(vz + 8, 8192, 64, 0, R)
+    o0, o1 = world(False), world(True)
+    check("unplanted, one epoch", o0, [yw, xr, zr], [3], False)
+    check("unplanted, three epochs", o0, [yw, xr, zr], [1, 2, 3], False)
+    check("write onto a table walked in the same epoch", o1, [yw, xr], [2], True)
+    check("write onto a table walked in a later epoch", o1, [yw, xr], [1, 2], True)
+    check("write onto a table walked in an earlier epoch", o1, [xr, yw], [1, 2], True)
+    check("read of a table walked in another epoch", o1, [xr, yr], [1, 2], True)
+    check("bytes in a table no request walks", o1, [yw, zr], [1, 2], False)
+
+    # ---- a walk past its request's first fault: the walker starts on a page
+    # made not present, and its next page's leaf table is the planted one
+    nxt = {int(v): i for i, v in zip(four, p.leaf_va[four])}
+    starts = [i for i in four if int(p.leaf_index[i]) == 0 and int(p.leaf_va[i]) - 4096 in nxt and
+              p.leaf_table_gfn[nxt[int(p.leaf_va[i]) - 4096]] != p.leaf_table_gfn[i]]
+    if not starts:
+        fails.append("no 2 MiB boundary between two 4 KiB leaf tables in the world")
+    else:
+        x2 = int(starts[0])
+        p0 = nxt[int(p.leaf_va[x2]) - 4096]
+        f2 = int(p.leaf_table_gfn[x2]) << 12
+        y2 = int(next(i for i in four if p.leaf_table_gfn[i] not in (p.leaf_table_gfn[x2], p.leaf_table_gfn[p0])))
+        a = wl.arena_image(0)
+        off = _entry_off(wl, p, p0)
+        _set_u64(a, off, _u64(a, off) & ~1)          # page before x2: not present
+        off = _entry_off(wl, p, y2)
+        _set_u64(a, off, (_u64(a, off) & ~_ADDR) | f2)
+        o2 = Oracle([a], [wl.vms[0].slots], [(0, p.cr3, p.levels)], wl.pool_image(), lib_path=lib_path)
+        walker = _req(int(p.leaf_va[x2]) - 32, 4096, 64, 0, R)   # faults on its first page
+        res, _ = o2.batch(walker)
+        if int(res[0]["code"]) != CODES["NOT_PRESENT"] or int(res[0]["bytes_done"]) != 0:
+            fails.append(f"planted walker should fault at once, got {res[0]}")
+        check("write onto a table walked only past a first fault", o2,
+              [_req(int(p.leaf_va[y2]) + 8, 0, 64, 0, W), walker], [1, 2], True)
+
+    # ---- aliased writes inside one request: page y+1 rewritten onto y's frame
+    nb = [i for i in four if int(p.leaf_va[i]) + 4096 in nxt]
+    ya = int(nb[0])
+    yb = nxt[int(p.leaf_va[ya]) + 4096]
+    a = wl.arena_image(0)
+    off = _entry_off(wl, p, yb)
+    _set_u64(a, off, (_u64(a, off) & ~_ADDR) | int(p.leaf_frame[ya]))
+    o3 = Oracle([a], [wl.vms[0].slots], [(0, p.cr3, p.levels)], wl.pool_image(), lib_path=lib_path)
+    span = _req(int(p.leaf_va[ya]) + 100, 0, 4200, 0, W)        # frame bytes 100..203 written twice
+    check("one request writing two aliased pages", o3, [span], [1], True)
+    check("one request reading two aliased pages", o3, [_req(int(p.leaf_va[ya]) + 100, 0, 4200, 0, R)], [1], False)
+
+    # ---- overlap inside one epoch: a read starting below a write of the same
+    # guest bytes (the reader sorts first), and two writers of one pool range
+    g = vx + 512
+    check("guest read below an overlapping guest write", o0, [_req(g, 0, 64, 0, R), _req(g + 32, 4096, 64, 0, W)],
+          [2], True)
+    check("the same pair in two epochs", o0, [_req(g, 0, 64, 0, R), _req(g + 32, 4096, 64, 0, W)], [1, 2], False)
+    check("two writers of one pool range", o0, [_req(vx + 8, 0, 64, 0, R), _req(vz + 8, 32, 64, 0, R)], [2], True)
+
+    # ---- PAE: a leaf rewritten onto the frame of the 4-entry root table
+    wp = gen.make_workload(specs["pae"])
+    pp = wp.procs[0]
+    fp = np.nonzero((pp.leaf_level == 1) & pp.leaf_present)[0]
+    yp, xp = int(fp[0]), int(fp[-1])
+    a = wp.arena_image(0)
+    off = _entry_off(wp, pp, yp)
+    _set_u64(a, off, (_u64(a, off) & ~_ADDR) | (pp.cr3 & ~0xFFF))
+    o4 = Oracle([a], [wp.vms[0].slots], [(0, pp.cr3, 3)], wp.pool_image(), lib_path=lib_path)
+    check("PAE: write onto the root table's frame", o4,
+          [_req(int(pp.leaf_va[yp]) + 2048, 0, 64, 0, W), _req(int(pp.leaf_va[xp]), 4096, 64, 0, R)], [1, 2], True)
+
+    # ---- EPT: the EPT leaf of a guest data page rewritten onto the EPT root table
+    we = gen.make_workload(specs["ept"])
+    pe, ve = we.procs[0], we.vms[0]
+    a = we.arena_image(0)
+    fe = np.nonzero((pe.leaf_level == 1) & pe.leaf_present)[0]
+    ye = None
+    for i in fe:
+        eoff, lvl = _ept_leaf_off(a, ve.ept_root, int(pe.leaf_frame[i]))
+        if lvl == 1:
+            ye = int(i)
+            break
+    if ye is None:
+        fails.append("no guest 4 KiB page with a 4 KiB EPT leaf in the EPT world")
+    else:
+        xe = int(next(i for i in fe if i != ye))
+        reqs = [_req(int(pe.leaf_va[ye]) + 64, 0, 64, 0, W), _req(int(pe.leaf_va[xe]), 4096, 64, 0, R)]
+        o5 = Oracle([a.copy()], [ve.slots], [(0, pe.cr3, pe.levels)], we.pool_image(), lib_path=lib_path,
+                    ept=[ve.ept_root])
+        check("EPT: unplanted", o5, reqs, [1, 2], False)
+        _set_u64(a, eoff, (_u64(a, eoff) & ~_ADDR) | ve.ept_root)
+        o6 = Oracle([a], [ve.slots], [(0, pe.cr3, pe.levels)], we.pool_image(), lib_path=lib_path,
+                    ept=[ve.ept_root])
+        check("EPT: write onto the EPT root table", o6, reqs, [1, 2], True)
     return fails

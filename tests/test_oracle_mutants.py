@@ -61,8 +61,8 @@ MUTANTS = {
     "map_pae_root_full_bits": ("(root_pae ? ORC_P :", "(root_pae ? (ORC_P | ORC_RW | ORC_US) :"),
     "map_large_leaf_ignored": ("if (rsvd || (!(pae && lvl == 3) && (e & ORC_PS))) {", "if (rsvd) {"),
     # the EPT walk (a second walk for the guest-physical space)
-    "ept_index_mask_8bit": ("uint64_t e = load64(v->arena + table + 8 * ((gpa >> eshift) & 511));",
-                            "uint64_t e = load64(v->arena + table + 8 * ((gpa >> eshift) & 255));"),
+    "ept_index_mask_8bit": ("uint64_t eoff = table + 8 * ((gpa >> eshift) & 511);",
+                            "uint64_t eoff = table + 8 * ((gpa >> eshift) & 255);"),
     "ept_write_without_read_ok": ("if ((e & 3) == 2) return ORC_EPT_MISCONFIG;", "if (0) return ORC_EPT_MISCONFIG;"),
     "ept_table_bits_unchecked": ("if (e & 0xF8) return ORC_EPT_MISCONFIG;", "if (0) return ORC_EPT_MISCONFIG;"),
     "ept_memtype_unchecked": ("if (mt == 2 || mt == 3 || mt == 7)", "if (mt == 7)"),
@@ -70,18 +70,28 @@ MUTANTS = {
                                       "if (0) return ORC_EPT_MISCONFIG;"),
     "ept_write_not_anded": ("can_w &= (int)((e >> 1) & 1);", "can_w = (int)((e >> 1) & 1);"),
     "ept_gpa_limit_dropped": ("if (gpa >> 48) return ORC_EPT_VIOLATION;", "if (0) return ORC_EPT_VIOLATION;"),
-    "ept_tables_need_read_only": ("uint32_t c = gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);\n        if (c != ORC_OK) {\n"
-                                  "            w->code = c;",
-                                  "uint32_t c = gpa_to_hpa(v, table, ORC_NEED_R, &thpa);\n        if (c != ORC_OK) {\n"
-                                  "            w->code = c;"),
+    "ept_tables_need_read_only": ("uint32_t c = gpa_to_hpa_rec(v, table, ORC_NEED_TABLE, &thpa, rec);",
+                                  "uint32_t c = gpa_to_hpa_rec(v, table, ORC_NEED_R, &thpa, rec);"),
     "map_ept_page_table_read_only": ("gpa_to_hpa(v, table, ORC_NEED_TABLE, &thpa);   /* the page table itself */",
                                      "gpa_to_hpa(v, table, ORC_NEED_R, &thpa);   /* the page table itself */"),
     "map_ept_pool_frames_read_only": ("gpa_to_hpa(v, pool[k], ORC_NEED_TABLE, &pool_hpa[k])",
                                       "gpa_to_hpa(v, pool[k], ORC_NEED_R, &pool_hpa[k])"),
-    "ept_data_always_read": ("gpa_to_hpa(v, w->gpa, write ? ORC_NEED_W : ORC_NEED_R, &w->hpa)",
-                             "gpa_to_hpa(v, w->gpa, ORC_NEED_R, &w->hpa)"),
+    "ept_data_always_read": ("gpa_to_hpa_rec(v, w->gpa, write ? ORC_NEED_W : ORC_NEED_R, &w->hpa, rec)",
+                             "gpa_to_hpa_rec(v, w->gpa, ORC_NEED_R, &w->hpa, rec)"),
     "ept_large_leaf_offset_dropped": ("uint64_t h = (e & ORC_ADDR_MASK) | (gpa & (size - 1));",
                                       "uint64_t h = (e & ORC_ADDR_MASK) | (gpa & 0xFFFull);"),
+    # the conflict checker (the batch precondition)
+    "checker_table_frames_dropped": ("walk_rec(s, p, lo, to_guest, &w, &rd);", "walk_rec(s, p, lo, to_guest, &w, NULL);"),
+    "checker_read_vs_write_dropped": ("if (v[i].write && v[i].lo < r_hi && r_req != v[i].req) {", "if (0) {"),
+    "checker_table_rule_writes_only": ("        gi[ng++] = d;", "        if (to_guest) gi[ng++] = d;"),
+    "checker_table_rule_per_epoch": ("        start = stop;\n        if (n_epochs == 0) break;",
+                                     "        start = stop;\n        nt = 0;\n        if (n_epochs == 0) break;"),
+    "checker_stops_at_first_fault": ("{ faulted = 1; done = lo - r->gva; continue; }",
+                                     "{ faulted = 1; done = lo - r->gva; break; }"),
+    "checker_self_alias_allowed": ("        if (v[i].lo < w_hi) {", "        if (v[i].lo < w_hi && w_req != v[i].req) {"),
+    "checker_pae_root_unrecorded": ("        note_read(rec, roff);\n", ""),
+    "checker_ept_reads_unrecorded": ("        note_read(rec, eoff);\n        uint64_t e = load64(v->arena + eoff);\n        if ((e & 7) == 0)",
+                                     "        uint64_t e = load64(v->arena + eoff);\n        if ((e & 7) == 0)"),
     "copy_direction_swapped": ("        if (to_guest)\n            memcpy(g, h, hi - lo);",
                                "        if (!to_guest)\n            memcpy(g, h, hi - lo);"),
     "ad_before_fault_check": ("        if (w.code != ORC_OK) {\n            res->bytes_done",
@@ -129,6 +139,7 @@ def test_pins_catch_mutant(tmp_path, name):
         lambda: pins.check_ept_equivalence(_small("ept"), lib),
         lambda: pins.check_ept_faults(_small("ept_faults"), lib),
         lambda: pins.check_ept_map_bad_pool(_small("ept_faults"), lib),
+        lambda: pins.check_conflict_plants(lib),
     ]
     for c in checks:
         if c():
