@@ -130,9 +130,13 @@ typedef struct {
 
 /* ---------------------------------------------------------------- context */
 
-/* Open a context on HIP device `hip_device`. */
+/* Open a context on HIP device `hip_device`.  A context plays the part of the
+ * host-side backend of the common virtual driver (section 3.1): it holds the
+ * guests' memory images, memslots and registered processes, and serves
+ * forwarded operations against them.  -EIO if the device cannot be used. */
 int devirt_open(int hip_device, devirt_ctx **out);
-/* Release everything the context owns (arenas, tables, workspaces). */
+/* Release everything the context owns (arenas, tables, workspaces); waits
+ * for the device first.  A server must have been stopped. */
 int devirt_close(devirt_ctx *ctx);
 /* Message for the calling thread's last failed call ("" if none). */
 const char *devirt_last_error(void);
@@ -140,7 +144,10 @@ const char *devirt_last_error(void);
 /* ------------------------------------------------- guest memory and tables */
 
 /* Allocate a VM's guest-memory arena of `arena_bytes` (multiple of 4 KiB) in
- * HBM; returns its id in *vm.  The arena starts zeroed. */
+ * HBM; returns its id in *vm.  The arena starts zeroed.  It stands for the
+ * host memory that backs the guest's physical memory (section 2.2), which the
+ * backend reads and writes at host addresses (section 4.2).  -ENOMEM if HBM
+ * cannot hold it. */
 int devirt_vm_create(devirt_ctx *ctx, uint64_t arena_bytes, uint32_t *vm);
 /* Borrow the arena's device pointer and size (valid until devirt_close). */
 int devirt_vm_arena(devirt_ctx *ctx, uint32_t vm, void **dev_ptr, uint64_t *bytes);
@@ -244,12 +251,19 @@ int devirt_map_pages(devirt_ctx *ctx, uint32_t asid, const devirt_map *maps_dev,
                      const uint64_t *pool_gpa_host, uint64_t n_pool, devirt_result *res_dev, uint64_t *n_used_dev,
                      void *hip_stream);
 
-/* Many operations from many guests in one submission.  Results equal
+/* Many operations from many guests in one submission.  The paper forwards
+ * one operation, a handful of scalar arguments, per hypercall (section 6.1),
+ * and with dual threads the operations of different guest threads proceed
+ * concurrently while each guest thread waits for its own (section 5); here
+ * a whole batch of such operations is handed over at once.  Results equal
  * applying the requests one after another in index order, provided that
  * inside each epoch no two requests touch overlapping guest bytes of one VM
- * or overlapping host bytes where one of them writes, and that no request
- * writes a guest page table; epochs run in order (translation of an epoch
- * may run ahead, during the copies of the previous one).  epoch_end_host: n_epochs ascending exclusive
+ * or overlapping host bytes where one of them writes, and that no request's
+ * guest bytes, read or written, lie in a frame that any request of the batch
+ * walks (a guest page table, a PAE root table or an EPT table); epochs run
+ * in order (translation of an epoch may run ahead, during the copies of the
+ * previous one, and ORs A/D bits meanwhile).  A violation gives undefined
+ * bytes, never a fault of the library.  epoch_end_host: n_epochs ascending exclusive
  * end indices, the last == n (NULL: one epoch).  res_dev: n devirt_result;
  * faults_dev: room for n devirt_fault (may be NULL together with
  * n_faults_dev); n_faults_dev: one uint64_t; t_done_dev: NULL or n uint64_t
@@ -259,7 +273,9 @@ int devirt_submit_batch(devirt_ctx *ctx, const devirt_request *reqs_dev, uint64_
                         const uint64_t *epoch_end_host, uint32_t n_epochs, devirt_result *res_dev,
                         devirt_fault *faults_dev, uint64_t *n_faults_dev, uint64_t *t_done_dev, void *hip_stream);
 
-/* Wait for everything the context enqueued on hip_stream. */
+/* Wait for everything the context enqueued on hip_stream: the blocking use of
+ * the data path, where the caller sleeps until its operations are done
+ * (section 5).  -EIO on a HIP failure. */
 int devirt_sync(devirt_ctx *ctx, void *hip_stream);
 
 /* ---------------------------------------------------------------- tuning */
@@ -294,6 +310,20 @@ int devirt_autotune(devirt_ctx *ctx, const devirt_request *reqs_dev, uint64_t n,
                     uint32_t n_epochs, devirt_result *res_dev, devirt_fault *faults_dev, uint64_t *n_faults_dev,
                     void *hip_stream, uint32_t reps, devirt_config *best, double *best_ms);
 
+/* devirt_autotune with a persistent cache of its winners.  cache_path_host:
+ * a text file, one JSON object per line, {"key": ..., "ms": ..., "config":
+ * {...}}; the key is the device (architecture name and CU count) and
+ * workload_key_host (the caller's name for the batch's shape, without quotes,
+ * backslashes or newlines).  If the file holds the key (the last such line
+ * wins), its config is set and returned with its recorded time, nothing is
+ * executed and *hit = 1.  Otherwise devirt_autotune runs (same effects) and a
+ * line is appended; *hit = 0.  -EIO if the file cannot be written. */
+int devirt_autotune_cached(devirt_ctx *ctx, const char *cache_path_host, const char *workload_key_host,
+                           const devirt_request *reqs_dev, uint64_t n, const uint64_t *epoch_end_host,
+                           uint32_t n_epochs, devirt_result *res_dev, devirt_fault *faults_dev,
+                           uint64_t *n_faults_dev, void *hip_stream, uint32_t reps, devirt_config *best,
+                           double *best_ms, int *hit);
+
 /* ---------------------------------------------------------------- metrics */
 
 typedef struct {
@@ -312,6 +342,10 @@ typedef struct {
     uint64_t segments;       /* copy segments queued                               */
     uint64_t inline_segments;/* segments copied by the translating wavefront       */
     uint64_t ad_atomics;     /* A/D atomic ORs issued                              */
+    uint64_t spilled_groups; /* request groups whose runs overflowed the segment
+                                queue while an earlier epoch was being copied:
+                                translated again and copied after that epoch's
+                                copy (the spill pass)                              */
 } devirt_stats;
 
 /* Profiling flags.  While any is set, data-path calls run without graphs.

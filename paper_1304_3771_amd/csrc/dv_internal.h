@@ -79,14 +79,17 @@ constexpr uint32_t kQParts = 32;
 constexpr uint32_t kLineWords = 32;
 
 // Per-epoch device counters (word 0 of each line is used).  A segment count
-// may exceed its part's capacity; segments past it were copied by the
-// translating wavefront.
+// may exceed its part's capacity; segments past it were either copied by the
+// translating wavefront or, when that wavefront may run during an earlier
+// epoch's copies, left to the epoch's spill pass (DBatch::spill_mode).
 struct DEpochCtr {
     uint32_t group_cursor;  // groups claimed beyond each wavefront's first
     uint32_t pad[kLineWords - 1];
     // segments in part p of the long queue (q[p]) and of the short queue
     // (q[kQParts + p])
     uint32_t q[2 * kQParts][kLineWords];
+    uint32_t spill_n;  // groups on the epoch's spill list
+    uint32_t pad2[kLineWords - 1];
 };
 static_assert(2 * kQParts == 64, "one counter per lane of a wavefront");
 
@@ -98,6 +101,7 @@ struct DCounters {
     unsigned long long segments;
     unsigned long long inline_segments;
     unsigned long long ad_atomics;
+    unsigned long long spilled_groups;
 };
 
 // Everything one batch launch needs besides the view.
@@ -108,7 +112,18 @@ struct DBatch {
     uint32_t *pending;        // per request, queued segments not yet copied (t_done only)
     DSeg *segs;               // long segments
     DSeg *shorts;             // short segments (len <= kShortRun)
-    uint64_t seg_cap;         // capacity of each of the two queues (kQParts parts each)
+    uint64_t part_cap;        // segments per queue part (a batch uses kQParts parts of each
+                              // queue; a per-request call only part 0, as large as the queue)
+    // Groups whose segments did not all fit their queue part.  With spill_mode
+    // set, translation may run while an earlier epoch is still being copied, so
+    // a translating wavefront must not move payload bytes: it puts its group's
+    // first request index on the spill list instead (slots [r0, r1) of the
+    // epoch's requests; a group appears at most once), and the spill pass,
+    // launched after the epoch's copy, translates those groups again and copies
+    // all of their runs.  Without spill_mode the wavefront copies them itself.
+    uint64_t *spill;
+    uint32_t spill_mode;
+    uint32_t pad0;
     DEpochCtr *ctr;           // per epoch
     DCounters *counters;      // null unless profiling
     uint64_t *t0;             // device wall clock at batch start
@@ -125,6 +140,8 @@ hipError_t launch_reset(hipStream_t s, DBatch b, uint32_t n_epochs);
 hipError_t launch_translate_groups(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0,
                                    uint64_t r1, uint32_t epoch, int direct);
 hipError_t launch_copy(hipStream_t s, int grid, int block, DBatch b, uint32_t epoch);
+hipError_t launch_spill(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0, uint64_t r1,
+                        uint32_t epoch);
 hipError_t launch_plain(hipStream_t s, DView v, DBatch b, devirt_request req, int inline_copy);
 hipError_t launch_xlat(hipStream_t s, int grid, int block, DView v, uint32_t asid, const uint64_t *gva,
                        uint64_t n, uint32_t flags, devirt_xlat *out, DCounters *counters);

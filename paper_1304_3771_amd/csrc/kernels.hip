@@ -443,17 +443,20 @@ __device__ __forceinline__ void copy_lane(uint8_t *dst_, const uint8_t *src_, ui
 // One wavefront, requests [r0, r0+gn) (or one request passed by value).
 // Must be entered by all 64 lanes.
 struct GroupOut {
-    unsigned long long pages, hits, misses, segs, inl, atomics;
+    unsigned long long pages, hits, misses, segs, inl, atomics, spills;
 };
 
+// Returns (wave-uniformly) true when some run of the group found its queue
+// part full while B.spill_mode is set: such runs are neither queued nor
+// copied, and the caller puts the group on the epoch's spill list.
 template <bool kPlain>
-__device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint32_t gn,
+__device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint32_t gn,
                               const devirt_request &preq, uint32_t epoch, CEnt *cache, uint32_t *owner,
                               bool coop_all, DEpochCtr *ctr, GroupOut &st) {
     const int lane = lane_id();
     // this wavefront's part of the segment queues
     const uint32_t qpart = kPlain ? 0u : (uint32_t)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kQParts);
-    const uint64_t pcap = B.seg_cap / kQParts;
+    const uint64_t pcap = B.part_cap;
     // ---- load and validate the group's requests (lane k owns request k)
     uint64_t gva = 0, host = 0, cr3 = 0;
     uint32_t len = 0, asid = 0, dir = 0, vm = 0, levels = 4, code0 = 0, nch = 0;
@@ -504,6 +507,7 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
     // per-request (owner lane) state
     uint32_t ff = kNone, fcode = 0, flevel = 0, queued = 0;
     uint64_t flo = 0;
+    bool spilled = false;
 
     for (uint32_t base = 0; base < total; base += 64) {
         const uint32_t c = base + (uint32_t)lane;
@@ -806,6 +810,8 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                     sg.pad = 0;
                     gp<DV_GLOBAL DSeg>(is_short ? B.shorts : B.segs)[qpart * pcap + pos] = sg;
                     q_ok = 1;
+                } else if (B.spill_mode) {
+                    spilled = true;  // queue full: the spill pass copies it
                 } else {
                     coop = true;  // queue full: the wavefront copies it below
                 }
@@ -859,17 +865,20 @@ __device__ void process_group(const DView &V, const DBatch &B, uint64_t r0, uint
             if (queued == 0) B.t_done[r0 + lane] = now_ns(B);
         }
     }
+    return __ballot(spilled) != 0;
 }
 
 // ------------------------------------------------------------------ kernels
 __global__ void k_reset(DBatch b, uint32_t n_epochs) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *b.t0 = wall_clock64();
-    constexpr uint32_t per = 1 + 2 * kQParts;  // counters per epoch
+    constexpr uint32_t per = 2 + 2 * kQParts;  // counters per epoch
     for (; i < n_epochs * per; i += gridDim.x * blockDim.x) {
         const uint32_t e = i / per, k = i % per;
         if (k == 0)
             b.ctr[e].group_cursor = 0;
+        else if (k == per - 1)
+            b.ctr[e].spill_n = 0;
         else
             b.ctr[e].q[k - 1][0] = 0;
     }
@@ -877,10 +886,10 @@ __global__ void k_reset(DBatch b, uint32_t n_epochs) {
 
 __device__ __forceinline__ void flush_counters(DCounters *c, const GroupOut &st) {
     if (!c) return;
-    unsigned long long v[6] = {st.pages, st.hits, st.misses, st.segs, st.inl, st.atomics};
+    unsigned long long v[7] = {st.pages, st.hits, st.misses, st.segs, st.inl, st.atomics, st.spills};
     // lane-local partial sums -> one atomic per counter per wavefront
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 7; ++i) {
         unsigned long long x = v[i];
         for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
         v[i] = x;
@@ -892,6 +901,7 @@ __device__ __forceinline__ void flush_counters(DCounters *c, const GroupOut &st)
         atomicAdd(&c->segments, v[3] / 64);
         atomicAdd(&c->inline_segments, v[4] / 64);
         atomicAdd(&c->ad_atomics, v[5]);
+        atomicAdd(&c->spilled_groups, v[6] / 64);
     }
 }
 
@@ -909,7 +919,7 @@ __global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uin
     const uint64_t n = r1 - r0;
     const uint32_t G = b.group;
     const uint64_t ngroups = (n + G - 1) / G;
-    GroupOut st = {0, 0, 0, 0, 0, 0};
+    GroupOut st = {0, 0, 0, 0, 0, 0, 0};
     devirt_request dummy = {};
     // Each wavefront takes group (its global index) first, without an atomic;
     // further groups come from the cursor, numbered after those first ones.
@@ -924,7 +934,13 @@ __global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uin
         if (claim && lane_id() == 0) g = atomicAdd(&b.ctr[epoch].group_cursor, 1u);
         const uint64_t gs = r0 + gi * G;
         const uint32_t gn = (uint32_t)((r1 - gs) < G ? (r1 - gs) : G);
-        process_group<false>(v, b, gs, gn, dummy, epoch, cache, owner, direct != 0, b.ctr, st);
+        if (process_group<false>(v, b, gs, gn, dummy, epoch, cache, owner, direct != 0, b.ctr, st)) {
+            st.spills++;
+            if (lane_id() == 0) {
+                const uint32_t k = atomicAdd(&b.ctr[epoch].spill_n, 1u);
+                gp<g_u64>(b.spill)[r0 + k] = gs;  // at most one slot per group of [r0, r1)
+            }
+        }
         if (!claim) break;
         gi = nwaves + uniform_u32(shfl32(g, 0));
     }
@@ -940,7 +956,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const uint64_t w0 = uniform_u64((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const bool nt = b.nontemporal != 0;
     const int lane = lane_id();
-    const uint64_t pcap = b.seg_cap / kQParts;
+    const uint64_t pcap = b.part_cap;
     // lane p < 32: part p of the long queue; lane 32 + p: part p of the short
     // queue.  Exclusive scan of the part counts within each half.
     uint32_t cnt = b.ctr[epoch].q[lane][0];
@@ -999,6 +1015,34 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     }
 }
 
+// Spill pass of one epoch: the groups whose runs did not all fit the queues
+// while translation ran during an earlier epoch's copies.  Launched on the
+// copy stream after the epoch's copy, so every payload byte still moves in
+// epoch order.  Each group is translated again (same results: page tables
+// change only in A/D bits, which are OR-ed) and its wavefront copies every
+// run of it; runs the copy kernel already moved are moved again with the same
+// bytes, since nothing else in the epoch touches them (batch precondition).
+__global__ void __launch_bounds__(256) k_spill(DView v, DBatch b, uint64_t r0, uint64_t r1, uint32_t epoch) {
+    extern __shared__ uint8_t smem[];
+    const int wave = threadIdx.x >> 6;
+    CEnt *cache = (CEnt *)smem + wave * kCacheWays;
+    uint32_t *owner = (uint32_t *)((CEnt *)smem + (blockDim.x >> 6) * kCacheWays) + wave * kCacheWays;
+    const uint32_t n = uniform_u32(*gp<const g_u32>(&b.ctr[epoch].spill_n));
+    if (n == 0) return;
+    if ((threadIdx.x & 63) < kCacheWays) cache[threadIdx.x & 63].key = ~0ull;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    GroupOut st = {0, 0, 0, 0, 0, 0, 0};
+    devirt_request dummy = {};
+    for (uint64_t i = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (uint64_t)wave; i < n; i += nwaves) {
+        const uint64_t gs = uniform_u64(gp<const g_u64>(b.spill)[r0 + i]);
+        const uint32_t gn = (uint32_t)((r1 - gs) < b.group ? (r1 - gs) : b.group);
+        process_group<false>(v, b, gs, gn, dummy, epoch, cache, owner, true, b.ctr, st);
+    }
+    flush_counters(b.counters, st);
+}
+
 __global__ void __launch_bounds__(64) k_plain(DView v, DBatch b, devirt_request req, int inline_copy) {
     __shared__ CEnt cache[kCacheWays];
     __shared__ uint32_t owner[kCacheWays];
@@ -1009,7 +1053,7 @@ __global__ void __launch_bounds__(64) k_plain(DView v, DBatch b, devirt_request 
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    GroupOut st = {0, 0, 0, 0, 0, 0};
+    GroupOut st = {0, 0, 0, 0, 0, 0, 0};
     process_group<true>(v, b, 0, 1, req, 0, cache, owner, inline_copy != 0, b.ctr, st);
     flush_counters(b.counters, st);
 }
@@ -1191,7 +1235,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         if (in) gp<DV_GLOBAL devirt_xlat>(out)[i] = x;
     }
     if (counters) {
-        GroupOut st = {0, hits, misses, 0, 0, atom};
+        GroupOut st = {0, hits, misses, 0, 0, atom, 0};
         flush_counters(counters, st);
     }
 }
@@ -1295,6 +1339,12 @@ hipError_t launch_translate_groups(hipStream_t s, int grid, int block, DView v, 
 
 hipError_t launch_copy(hipStream_t s, int grid, int block, DBatch b, uint32_t epoch) {
     hipLaunchKernelGGL(k_copy, dim3(grid), dim3(block), 0, s, b, epoch);
+    return hipGetLastError();
+}
+
+hipError_t launch_spill(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0, uint64_t r1,
+                        uint32_t epoch) {
+    hipLaunchKernelGGL(k_spill, dim3(grid), dim3(block), wave_lds(block), s, v, b, r0, r1, epoch);
     return hipGetLastError();
 }
 

@@ -81,6 +81,7 @@ Workspace::~Workspace() {
     hipFree(pending);
     hipFree(tiles);
     hipFree(t0);
+    hipFree(spill);
     if (map_ev) {
         hipEventSynchronize(map_ev);
         hipEventDestroy(map_ev);
@@ -420,6 +421,7 @@ int ensure_ws(devirt_ctx *c, Workspace *w, uint64_t n_req, uint64_t n_epochs, bo
     if ((rc = grow(c, w, w->shorts, w->short_cap, w->seg_cap, "short segments"))) return rc;
     if ((rc = grow(c, w, w->ctr, w->ctr_cap, std::max<uint64_t>(n_epochs, 1), "epoch counters"))) return rc;
     if ((rc = grow(c, w, w->t0, w->t0_cap, 1, "clock"))) return rc;
+    if ((rc = grow(c, w, w->spill, w->spill_cap, std::max<uint64_t>(n_req, 1), "spill list"))) return rc;
     uint64_t tiles = (n_req + kFaultTile - 1) / kFaultTile;
     if ((rc = grow(c, w, w->tiles, w->tiles_cap, std::max<uint64_t>(tiles, 1), "fault tiles"))) return rc;
     if (need_pending && (rc = grow(c, w, w->pending, w->pending_cap, std::max<uint64_t>(n_req, 1), "pending")))
@@ -432,7 +434,8 @@ DBatch make_batch(devirt_ctx *c, Workspace *w) {
     memset(&b, 0, sizeof b);
     b.segs = w->segs;
     b.shorts = w->shorts;
-    b.seg_cap = std::min(w->seg_cap, w->short_cap);
+    b.part_cap = std::min(w->seg_cap, w->short_cap) / kQParts;
+    b.spill = w->spill;
     b.ctr = w->ctr;
     b.pending = w->pending;
     b.t0 = w->t0;
@@ -510,6 +513,7 @@ extern "C" int devirt_get_stats(devirt_ctx *c, devirt_stats *out) {
     out->segments = h.segments;
     out->inline_segments = h.inline_segments;
     out->ad_atomics = h.ad_atomics;
+    out->spilled_groups = h.spilled_groups;
     return 0;
 }
 
@@ -688,6 +692,9 @@ static int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host,
     if (rc) return rc;
     DBatch b = make_batch(c, w);
     b.res = res;
+    // one request: part 0 spans the whole queue, which holds at least one
+    // segment per page, so no run overflows it
+    b.part_cap = std::min(w->seg_cap, w->short_cap);
     devirt_request rq;
     memset(&rq, 0, sizeof rq);
     rq.gva = gva;
@@ -718,11 +725,18 @@ extern "C" int devirt_copy_to_guest(devirt_ctx *c, uint32_t asid, uint64_t gva, 
 // Enqueue one batch on stream `s` using workspace `w` (no capture logic here).
 //
 // Translation of an epoch does not depend on the copies of earlier epochs
-// (page tables only change in their A/D bits, which are OR-ed), so with
-// several epochs the translate launches run on a side stream ahead of the
-// copies: translate(e) overlaps copy(e-1).  The segment queue is split in two
-// halves used by alternate epochs; translate(e) waits for copy(e-2), the last
-// user of its half.  Copies stay in epoch order on `s`.
+// (page tables only change in their A/D bits, which are OR-ed, and no request
+// touches a page-table frame), so with several epochs the translate launches
+// run on a side stream ahead of the copies: translate(e) overlaps copy(e-1).
+// The segment queue is split in two halves used by alternate epochs;
+// translate(e) waits for copy(e-2), the last user of its half.  Copies stay in
+// epoch order on `s`.
+//
+// Every payload byte moves on `s`, in epoch order: a translate launch that may
+// overlap an earlier epoch's copy (overlap on, e >= 1) copies nothing itself.
+// It gets no inline copies, and a group whose runs overflow its queue part
+// goes to the epoch's spill list; the spill pass runs on `s` right after the
+// epoch's copy.
 static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStream_t s) {
     DBatch b = make_batch(c, w);
     b.reqs = a.reqs;
@@ -767,7 +781,9 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
         DBatch be = b;
         be.segs = w->segs + (overlap ? (e & 1) * half : 0);
         be.shorts = w->shorts + (overlap ? (e & 1) * half : 0);
-        be.seg_cap = half;
+        be.part_cap = half / kQParts;
+        be.spill_mode = (overlap && e >= 1) ? 1u : 0u;
+        if (be.spill_mode) be.inline_bytes = 0;
         hipEvent_t t_done = overlap ? w->events[2 * e] : nullptr;
         hipEvent_t c_done = overlap ? w->events[2 * e + 1] : nullptr;
         if (r1 > r0) {
@@ -791,7 +807,12 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
                                (uint32_t)e));
             if ((rc = prof_end(c, s, pe))) return rc;
         }
+        // the spill pass uses no queue: translate(e+2) need not wait for it
         if (overlap) HIPCHK(hipEventRecord(c_done, s));
+        if (r1 > r0 && be.spill_mode)
+            HIPCHK(launch_spill(s, grid_for(c, (r1 - r0 + be.group - 1) / be.group, c->cfg.xlat_wg,
+                                            c->cfg.xlat_wgs_per_cu),
+                                (int)c->cfg.xlat_wg, v, be, r0, r1, (uint32_t)e));
         r0 = r1;
     }
     // every translate launch is already joined into `s` through its copy's wait
@@ -1012,5 +1033,119 @@ extern "C" int devirt_autotune(devirt_ctx *c, const devirt_request *reqs, uint64
     if (rc) return rc;
     if (best) *best = cur;
     if (best_ms) *best_ms = cur_ms;
+    return 0;
+}
+
+// ------------------------------------------------------- tuning cache
+// One JSON object per line:
+//   {"key": "<device>|<workload key>", "ms": <median ms>, "config": {"group": 64, ...}}
+// <device> is the architecture name and the CU count.  The last line with a
+// key wins; lines that do not parse are skipped.
+struct CfgField {
+    const char *name;
+    uint32_t devirt_config::*field;
+};
+static const CfgField kCfgFields[] = {
+    {"group", &devirt_config::group},
+    {"seg_chunks", &devirt_config::seg_chunks},
+    {"xlat_wg", &devirt_config::xlat_wg},
+    {"xlat_wgs_per_cu", &devirt_config::xlat_wgs_per_cu},
+    {"copy_wg", &devirt_config::copy_wg},
+    {"copy_wgs_per_cu", &devirt_config::copy_wgs_per_cu},
+    {"nontemporal", &devirt_config::nontemporal},
+    {"inline_bytes", &devirt_config::inline_bytes},
+    {"use_graph", &devirt_config::use_graph},
+    {"overlap", &devirt_config::overlap},
+};
+
+static std::string device_key(devirt_ctx *c) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, c->device) != hipSuccess) return std::string();
+    char buf[320];
+    snprintf(buf, sizeof buf, "%s/%dcu", p.gcnArchName, p.multiProcessorCount);
+    return std::string(buf);
+}
+
+// Parses one cache line; true when it names `key` and holds a valid config.
+static bool parse_tune_line(const std::string &line, const std::string &key, devirt_config *cfg, double *ms) {
+    const std::string kk = "\"key\": \"";
+    size_t a = line.find(kk);
+    if (a == std::string::npos) return false;
+    a += kk.size();
+    size_t b = line.find('"', a);
+    if (b == std::string::npos || line.compare(a, b - a, key) != 0 || b - a != key.size()) return false;
+    size_t m = line.find("\"ms\": ", b);
+    if (m == std::string::npos) return false;
+    *ms = strtod(line.c_str() + m + 6, nullptr);
+    devirt_config k;
+    memset(&k, 0, sizeof k);
+    for (const CfgField &f : kCfgFields) {
+        const std::string name = std::string("\"") + f.name + "\": ";
+        size_t p = line.find(name, m);
+        if (p == std::string::npos) return false;
+        k.*(f.field) = (uint32_t)strtoul(line.c_str() + p + name.size(), nullptr, 10);
+    }
+    if (check_config(k)) return false;
+    *cfg = k;
+    return true;
+}
+
+extern "C" int devirt_autotune_cached(devirt_ctx *c, const char *cache_path, const char *workload_key,
+                                      const devirt_request *reqs, uint64_t n, const uint64_t *epoch_end,
+                                      uint32_t n_epochs, devirt_result *res, devirt_fault *faults, uint64_t *n_faults,
+                                      void *stream, uint32_t reps, devirt_config *best, double *best_ms, int *hit) {
+    if (!c || !cache_path || !workload_key) return dv_fail(-EINVAL, "NULL argument");
+    if (strchr(workload_key, '"') || strchr(workload_key, '\\') || strchr(workload_key, '\n'))
+        return dv_fail(-EINVAL, "workload key must not hold quotes, backslashes or newlines");
+    if (set_dev(c)) return -EIO;
+    const std::string dev = device_key(c);
+    if (dev.empty()) return dv_fail(-EIO, "hipGetDeviceProperties failed");
+    const std::string key = dev + "|" + workload_key;
+    devirt_config found;
+    double found_ms = 0;
+    bool have = false;
+    if (FILE *f = fopen(cache_path, "r")) {
+        char buf[4096];
+        while (fgets(buf, sizeof buf, f)) {
+            devirt_config k;
+            double ms;
+            if (parse_tune_line(buf, key, &k, &ms)) {
+                found = k;
+                found_ms = ms;
+                have = true;
+            }
+        }
+        fclose(f);
+    }
+    if (hit) *hit = have ? 1 : 0;
+    if (have) {
+        int rc = devirt_set_config(c, &found);
+        if (rc) return rc;
+        if (best) *best = found;
+        if (best_ms) *best_ms = found_ms;
+        return 0;
+    }
+    devirt_config k;
+    double ms = 0;
+    int rc = devirt_autotune(c, reqs, n, epoch_end, n_epochs, res, faults, n_faults, stream, reps, &k, &ms);
+    if (rc) return rc;
+    if (best) *best = k;
+    if (best_ms) *best_ms = ms;
+    std::string line = "{\"key\": \"" + key + "\", \"ms\": ";
+    char num[64];
+    snprintf(num, sizeof num, "%.6f", ms);
+    line += num;
+    line += ", \"config\": {";
+    bool first = true;
+    for (const CfgField &f : kCfgFields) {
+        snprintf(num, sizeof num, "%s\"%s\": %u", first ? "" : ", ", f.name, k.*(f.field));
+        line += num;
+        first = false;
+    }
+    line += "}}\n";
+    FILE *f = fopen(cache_path, "a");
+    if (!f) return dv_fail(-EIO, "cannot append to the tuning cache %s", cache_path);
+    const bool ok = fputs(line.c_str(), f) >= 0;
+    if (fclose(f) != 0 || !ok) return dv_fail(-EIO, "cannot write the tuning cache %s", cache_path);
     return 0;
 }

@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
                 ("graph_replays", ctypes.c_uint64), ("copy_launches", ctypes.c_uint64), ("copy_ms", ctypes.c_double),
                 ("xlat_launches", ctypes.c_uint64), ("xlat_ms", ctypes.c_double),
                 ("pages_walked", ctypes.c_uint64), ("cache_hits", ctypes.c_uint64), ("cache_misses", ctypes.c_uint64),
-                ("segments", ctypes.c_uint64), ("inline_segments", ctypes.c_uint64), ("ad_atomics", ctypes.c_uint64)]
+                ("segments", ctypes.c_uint64), ("inline_segments", ctypes.c_uint64), ("ad_atomics", ctypes.c_uint64),
+                ("spilled_groups", ctypes.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -117,6 +118,8 @@ _SIGS = {
     "devirt_set_config": ([vp, ctypes.POINTER(Config)]),
     "devirt_autotune": ([vp, vp, u64, vp, u32, vp, vp, vp, vp, u32, ctypes.POINTER(Config),
                          ctypes.POINTER(ctypes.c_double)]),
+    "devirt_autotune_cached": ([vp, ctypes.c_char_p, ctypes.c_char_p, vp, u64, vp, u32, vp, vp, vp, vp, u32,
+                                ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]),
     "devirt_set_profiling": ([vp, i32]),
     "devirt_get_stats": ([vp, ctypes.POINTER(Stats)]),
     "devirt_reset_stats": ([vp]),
@@ -299,6 +302,21 @@ class Context:
             self._h, _ptr(reqs), n, ep.ctypes.data if ep is not None else None, ne, _ptr(res), _ptr(faults),
             _ptr(n_faults), _stream(stream), reps, ctypes.byref(best), ctypes.byref(ms)))
         return best.as_dict(), ms.value
+
+    def autotune_cached(self, cache_path: str, key: str, reqs, n, res, epoch_end=None, faults=None, n_faults=None,
+                        stream=None, reps=3):
+        """devirt_autotune_cached: returns (config, ms, hit)."""
+        ep = None
+        ne = 0
+        if epoch_end is not None:
+            ep = np.ascontiguousarray(np.asarray(epoch_end, dtype=np.uint64))
+            ne = len(ep)
+        best, ms, hit = Config(), ctypes.c_double(), ctypes.c_int()
+        _check("devirt_autotune_cached", lib().devirt_autotune_cached(
+            self._h, os.fsencode(cache_path), key.encode(), _ptr(reqs), n, ep.ctypes.data if ep is not None else None,
+            ne, _ptr(res), _ptr(faults), _ptr(n_faults), _stream(stream), reps, ctypes.byref(best), ctypes.byref(ms),
+            ctypes.byref(hit)))
+        return best.as_dict(), ms.value, bool(hit.value)
 
     def set_profiling(self, on=True, counters: bool = True):
         """Timing events (and, unless counters=False, device counters); off when on is False."""

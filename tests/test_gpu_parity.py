@@ -374,6 +374,68 @@ def test_queue_overflow_copies_inline(monkeypatch):
     assert compare("overflow", got, exp) == []
 
 
+def _cross_epoch_reuse(w):
+    """Pairs of consecutive epochs whose requests share guest bytes (same process)
+    and whose host ranges overlap."""
+    r = w.requests
+    ep = np.repeat(np.arange(len(w.epoch_end)), np.diff(np.concatenate([[0], w.epoch_end.astype(np.int64)])))
+    guest = host = 0
+    for e in range(len(w.epoch_end) - 1):
+        a, b = r[ep == e], r[ep == e + 1]
+        for x, y, key in ((a, b, "gva"), (a, b, "host")):
+            lo = np.sort(x[key])
+            hi = (x[key] + x["len"].astype(np.uint64))[np.argsort(x[key])]
+            for q in y[:200]:
+                j = np.searchsorted(lo, q[key] + np.uint64(q["len"])) - 1
+                if j >= 0 and np.any(hi[:j + 1] > q[key]):
+                    if key == "host":
+                        host += 1
+                    elif np.any(x["asid"][np.argsort(x[key])][:j + 1][hi[:j + 1] > q[key]] == q["asid"]):
+                        guest += 1
+                    break
+    return guest, host
+
+
+@pytest.mark.parametrize("overlap", [1, 0])
+def test_overflow_across_epochs(monkeypatch, overlap):
+    """Many epochs that reuse guest and host bytes, a segment queue of 64
+    (one segment per queue part and half), inline copies of runs up to 256 B:
+    with translation overlapped (the next epoch is translated while the
+    previous one is copied) no translating wavefront may move payload bytes,
+    so inline copies are off after the first epoch and overflowing groups are
+    copied by the spill pass; without overlap the translating wavefronts copy
+    them in place.  Bit-exact on results, faults, every arena and pool byte,
+    with graphs, and again with device counters that show both paths ran."""
+    import torch
+    monkeypatch.setenv("DEVIRT_SEG_CAP", "64")
+    w = wl("epochs")
+    assert len(w.epoch_end) >= 8
+    g, h = _cross_epoch_reuse(w)
+    assert g > 0 and h > 0, (g, h)
+    cfg = dict(inline_bytes=256, overlap=overlap, group=8)
+    exp = oracle_batch(w)
+    got = gpu_batch(w, cfg=cfg)
+    assert compare(f"epochs overlap={overlap}", got, exp) == []
+    got = gpu_batch(w, cfg=cfg, t_done=True)
+    assert compare(f"epochs overlap={overlap} t_done", got, exp) == []
+    assert np.all(got[4]["t_done"] > 0)
+    ctx = new_ctx(**cfg)
+    try:
+        ctx.set_profiling(True, counters=True)
+        got = gpu_batch(w, ctx=ctx)
+        st = got[4]["stats"]
+    finally:
+        ctx.close()
+    assert compare(f"epochs overlap={overlap} counters", got, exp) == []
+    log(f"overlap={overlap}: {st['spilled_groups']} groups spilled, {st['inline_segments']} runs copied "
+        f"by translating wavefronts, {st['segments']} queued")
+    assert st["inline_segments"] > 0
+    if overlap:
+        assert st["spilled_groups"] > 0
+    else:
+        assert st["spilled_groups"] == 0
+
+
 def test_completion_times_and_repeat():
     w = wl("multi_vm")
     got = gpu_batch(w, t_done=True)
