@@ -47,7 +47,12 @@
  * the guest's RAM); a memslot maps [gpa, gpa+bytes) to [arena_off, ...).
  * Page tables live inside guest-physical memory and are read through the
  * memslots.  Request `host` fields are byte offsets into one host pool.
- * Everything is sequential and in request order.
+ * Everything is sequential and in request order, except orc_batch_mt: it
+ * splits each epoch's requests over threads, which the batch precondition
+ * (no two requests of an epoch touch overlapping bytes where one writes, no
+ * request touches a walked table frame) makes equivalent.  For that case
+ * entry bytes are loaded and A/D bits OR-ed with relaxed byte atomics; the
+ * bits a walk decides on never change during a batch.
  *
  * A VM may instead have its guest-physical space described by a 4-level
  * extended page table (EPT) kept in its arena: the translation is then
@@ -76,6 +81,7 @@
  *     too: if one of them is not readable and writable, nothing is written
  *     and every map that would have succeeded reports NO_POOL.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -234,7 +240,7 @@ static int slot_lookup(const orc_vm *v, uint64_t gpa, uint64_t *hpa) {
 
 static uint64_t load64(const uint8_t *p) {
     uint64_t v = 0;
-    for (int i = 7; i >= 0; i--) v = (v << 8) | p[i];   /* little endian */
+    for (int i = 7; i >= 0; i--) v = (v << 8) | __atomic_load_n(&p[i], __ATOMIC_RELAXED);   /* little endian */
     return v;
 }
 
@@ -441,8 +447,8 @@ static void set_ad(orc_state *s, const orc_proc *p, const walk_t *w, int write) 
     for (uint32_t i = 0; i < w->npath; i++) {
         uint8_t want = (uint8_t)ORC_A;
         if (write && i + 1 == w->npath) want |= (uint8_t)ORC_D;
-        if ((a[w->path[i]] & want) != want) s->n_ad_sets++;
-        a[w->path[i]] |= want;
+        uint8_t old = __atomic_fetch_or(&a[w->path[i]], want, __ATOMIC_RELAXED);
+        if ((old & want) != want) __atomic_fetch_add(&s->n_ad_sets, 1, __ATOMIC_RELAXED);
     }
 }
 
@@ -487,11 +493,18 @@ void orc_translate(orc_state *s, uint32_t asid, const uint64_t *gvas, uint64_t n
 }
 
 /* ----------------------------------------------------------------- copy -- */
+/* What a copy does besides computing its result. */
+enum {
+    ORC_MOVE_NONE = 0,  /* result only: no byte moves, no A/D update          */
+    ORC_MOVE_ALL = 1,   /* A/D update and byte moves: the operation itself    */
+    ORC_MOVE_AD = 2,    /* A/D update only (the page-table side of the copy)  */
+};
+
 /* One copy between guest memory at req->gva and the pool at req->host,
- * page by page (section 4.2).  With move == 0 only the result is computed:
- * no byte moves and no A/D update (a result depends only on the page tables,
- * whose translation bits copies never change).  Returns -1 if the request
- * names pool bytes outside the pool (a caller error the tests never make). */
+ * page by page (section 4.2).  A result depends only on the page tables,
+ * whose translation bits copies never change, so the three modes above give
+ * the same result.  Returns -1 if the request names pool bytes outside the
+ * pool (a caller error the tests never make). */
 static int copy_req(orc_state *s, const orc_req *req, orc_result *res, int move) {
     memset(res, 0, sizeof(*res));
     if (req->asid >= s->nproc) {
@@ -507,7 +520,8 @@ static int copy_req(orc_state *s, const orc_req *req, orc_result *res, int move)
         res->fault_gva = req->gva;
         return 0;
     }
-    if (move && (req->host > s->pool_bytes || (uint64_t)req->len > s->pool_bytes - req->host)) return -1;
+    if (move == ORC_MOVE_ALL && (req->host > s->pool_bytes || (uint64_t)req->len > s->pool_bytes - req->host))
+        return -1;
     int to_guest = req->dir != 0;
     uint8_t *arena = s->vms[p->vm].arena;
     uint64_t end = req->gva + req->len;
@@ -523,8 +537,9 @@ static int copy_req(orc_state *s, const orc_req *req, orc_result *res, int move)
             res->level = (uint16_t)w.level;
             return 0;
         }
-        if (!move) continue;
+        if (move == ORC_MOVE_NONE) continue;
         set_ad(s, p, &w, to_guest);
+        if (move == ORC_MOVE_AD) continue;
         uint8_t *g = arena + w.hpa;
         uint8_t *h = s->pool + req->host + (lo - req->gva);
         if (to_guest)
@@ -536,15 +551,13 @@ static int copy_req(orc_state *s, const orc_req *req, orc_result *res, int move)
     return 0;
 }
 
-int orc_copy(orc_state *s, const orc_req *req, orc_result *res) { return copy_req(s, req, res, 1); }
+int orc_copy(orc_state *s, const orc_req *req, orc_result *res) { return copy_req(s, req, res, ORC_MOVE_ALL); }
 
-/* A batch is its requests applied one after another in index order; the
- * fault list holds one record per request whose code is not OK, ascending
- * by request index.  Returns the number of faults, or -1 on a pool error. */
-static int64_t batch(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res, orc_fault *faults, int move) {
+/* The fault list: one record per request whose code is not OK, ascending by
+ * request index.  Returns the number of faults. */
+static int64_t fault_list(const orc_result *res, uint64_t n, orc_fault *faults) {
     int64_t nf = 0;
     for (uint64_t i = 0; i < n; i++) {
-        if (copy_req(s, &reqs[i], &res[i], move) != 0) return -1;
         if (res[i].code != ORC_OK) {
             if (faults) {
                 faults[nf].req_index = i;
@@ -559,13 +572,85 @@ static int64_t batch(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *
     return nf;
 }
 
+/* A batch is its requests applied one after another in index order.
+ * Returns the number of faults, or -1 on a pool error. */
+static int64_t batch(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res, orc_fault *faults, int move) {
+    for (uint64_t i = 0; i < n; i++)
+        if (copy_req(s, &reqs[i], &res[i], move) != 0) return -1;
+    return fault_list(res, n, faults);
+}
+
 int64_t orc_batch(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res, orc_fault *faults) {
-    return batch(s, reqs, n, res, faults, 1);
+    return batch(s, reqs, n, res, faults, ORC_MOVE_ALL);
 }
 
 /* Results and fault list of a batch, without moving bytes or touching A/D. */
 int64_t orc_batch_results(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res, orc_fault *faults) {
-    return batch(s, reqs, n, res, faults, 0);
+    return batch(s, reqs, n, res, faults, ORC_MOVE_NONE);
+}
+
+/* Results, fault list and the A/D bits of a batch, without moving payload
+ * bytes: the final page-table frames equal those after orc_batch. */
+int64_t orc_batch_ad(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *res, orc_fault *faults) {
+    return batch(s, reqs, n, res, faults, ORC_MOVE_AD);
+}
+
+/* The same batch on several threads: epochs in order, the requests of one
+ * epoch split into `nthreads` contiguous slices, one thread each.  Under the
+ * batch precondition the final state equals orc_batch's (move = 1) or
+ * orc_batch_ad's (move = 2).  epoch_end: n_epochs ascending exclusive ends,
+ * the last == n.  Returns the number of faults, -1 on a pool error, -3 if
+ * the epoch ends do not finish at n.  A slice no thread can be started for
+ * runs on the calling thread. */
+typedef struct {
+    orc_state *s;
+    const orc_req *reqs;
+    orc_result *res;
+    uint64_t lo, hi;
+    int move, rc;
+} slice_t;
+
+static void *run_slice(void *arg) {
+    slice_t *t = (slice_t *)arg;
+    for (uint64_t i = t->lo; i < t->hi && t->rc == 0; i++)
+        if (copy_req(t->s, &t->reqs[i], &t->res[i], t->move) != 0) t->rc = -1;
+    return NULL;
+}
+
+int64_t orc_batch_mt(orc_state *s, const orc_req *reqs, uint64_t n, const uint64_t *epoch_end, uint32_t n_epochs,
+                     uint32_t nthreads, int move, orc_result *res, orc_fault *faults) {
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    slice_t t[256];
+    pthread_t th[256];
+    int started[256];
+    uint64_t r0 = 0;
+    for (uint32_t e = 0; e < n_epochs; e++) {
+        const uint64_t r1 = epoch_end[e];
+        const uint64_t m = r1 - r0;
+        for (uint32_t j = 0; j < nthreads; j++) {
+            t[j].s = s;
+            t[j].reqs = reqs;
+            t[j].res = res;
+            t[j].lo = r0 + m * j / nthreads;
+            t[j].hi = r0 + m * (j + 1) / nthreads;
+            t[j].move = move;
+            t[j].rc = 0;
+            started[j] = j + 1 < nthreads && t[j].hi > t[j].lo &&
+                         pthread_create(&th[j], NULL, run_slice, &t[j]) == 0;
+        }
+        for (uint32_t j = 0; j < nthreads; j++)  /* the last slice, and any no thread took */
+            if (!started[j]) run_slice(&t[j]);
+        int rc = 0;
+        for (uint32_t j = 0; j < nthreads; j++) {
+            if (started[j]) pthread_join(th[j], NULL);
+            if (t[j].rc) rc = t[j].rc;
+        }
+        if (rc) return rc;
+        r0 = r1;
+    }
+    if (r0 != n) return -3;
+    return fault_list(res, n, faults);
 }
 
 /* ------------------------------------------------------ conflict checker -- */

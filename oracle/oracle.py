@@ -34,7 +34,7 @@ XLAT_SET_AD = 2
 def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -67,6 +67,10 @@ def _load(path: str | None = None):
         lib.orc_batch.restype = ctypes.c_int64
         lib.orc_batch_results.argtypes = [vp, vp, u64, vp, vp]
         lib.orc_batch_results.restype = ctypes.c_int64
+        lib.orc_batch_ad.argtypes = [vp, vp, u64, vp, vp]
+        lib.orc_batch_ad.restype = ctypes.c_int64
+        lib.orc_batch_mt.argtypes = [vp, vp, u64, vp, u32, u32, ctypes.c_int, vp, vp]
+        lib.orc_batch_mt.restype = ctypes.c_int64
         lib.orc_check_conflicts.argtypes = [vp, vp, u64, vp, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         lib.orc_check_conflicts.restype = ctypes.c_int
         lib.orc_map_pages.argtypes = [vp, u32, vp, u64, vp, u64, vp]
@@ -143,6 +147,32 @@ class Oracle:
         res = np.zeros(n, RESULT_DTYPE)
         faults = np.zeros(n, FAULT_DTYPE)
         nf = self._lib.orc_batch(self._h, r.ctypes.data, n, res.ctypes.data, faults.ctypes.data)
+        if nf < 0:
+            raise ValueError("request names pool bytes outside the pool")
+        return res, faults[:nf].copy()
+
+    def batch_ad(self, reqs):
+        """Results, fault list and A/D updates, without moving payload bytes."""
+        r = np.ascontiguousarray(reqs)
+        n = len(r)
+        res = np.zeros(n, RESULT_DTYPE)
+        faults = np.zeros(n, FAULT_DTYPE)
+        nf = self._lib.orc_batch_ad(self._h, r.ctypes.data, n, res.ctypes.data, faults.ctypes.data)
+        return res, faults[:nf].copy()
+
+    def batch_mt(self, reqs, epoch_end=None, threads: int = 1, ad_only: bool = False):
+        """The batch with each epoch's requests split over `threads` threads
+        (the batch precondition makes that equal to the sequential batch);
+        ad_only: A/D updates without payload moves, as batch_ad."""
+        r = np.ascontiguousarray(reqs)
+        n = len(r)
+        e = np.ascontiguousarray(np.asarray(epoch_end if epoch_end is not None else [n], np.uint64))
+        if len(e) == 0 or int(e[-1]) != n or np.any(np.diff(e.astype(np.int64)) < 0):
+            raise ValueError("epoch ends must ascend and end at n")
+        res = np.zeros(n, RESULT_DTYPE)
+        faults = np.zeros(n, FAULT_DTYPE)
+        nf = self._lib.orc_batch_mt(self._h, r.ctypes.data, n, e.ctypes.data, len(e), int(threads),
+                                    2 if ad_only else 1, res.ctypes.data, faults.ctypes.data)
         if nf < 0:
             raise ValueError("request names pool bytes outside the pool")
         return res, faults[:nf].copy()

@@ -637,6 +637,16 @@ def check_invariants(wl, lib_path=None):
     return fails
 
 
+def table_pages(wl, vm):
+    """Arena page numbers of every table frame of a VM: its guest page tables
+    (through the memslots) and its EPT tables, if it has an EPT."""
+    v = wl.vms[vm]
+    pages = [(gen.gpa_to_arena(v.slots, v.pt_gfn << np.uint64(12)) >> 12).astype(np.int64)]
+    if v.ept_root is not None:
+        pages.append((v.ept_off >> np.uint64(12)).astype(np.int64))
+    return np.unique(np.concatenate(pages))
+
+
 def small_specs():
     """Reduced configurations with the named ones' structure, sized for seconds on the CPU."""
     KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30

@@ -117,7 +117,7 @@ def _build(tmp_path, name):
     path = tmp_path / f"{name}.c"
     path.write_text(src.replace(old, new))
     lib = tmp_path / f"lib{name}.so"
-    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", str(path), "-o", str(lib)])
+    subprocess.check_call(["gcc", "-O1", "-std=gnu11", "-fPIC", "-shared", "-pthread", str(path), "-o", str(lib)])
     return str(lib)
 
 
