@@ -102,20 +102,46 @@ def measured_traffic(workload):
     return d.get("bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads for the oracle's parallel leg: the cores this process may run
+    on, at most 16 (one GPU's share of its host)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
 def cpu_baseline(wl, seconds, name, max_vms=8):
-    """Time the oracle on the host cores: request prefixes in index order,
-    restricted to the first `max_vms` VMs (the oracle keeps every arena it
-    walks in host memory), until `seconds` of oracle time have passed."""
+    """Time the oracle on the host cores, restricted to the first `max_vms`
+    VMs (the oracle keeps every arena it touches in host memory): one thread
+    on request prefixes in index order, then N threads (each epoch's requests
+    split over them, epochs in order) on whole passes over the requests,
+    each leg until `seconds` of oracle time have passed."""
     from oracle import Oracle
-    from workload import gen
     nvm = min(len(wl.vms), max_vms)
     log(f"cpu baseline: building host state for {nvm} of {len(wl.vms)} VMs")
-    arenas = [wl.arena_image(v) for v in range(nvm)]
-    arenas += [np.zeros(4096, np.uint8) for _ in range(nvm, len(wl.vms))]
-    o = Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], wl.pool_image(),
-               ept=[v.ept_root if v.vm < nvm else None for v in wl.vms])
+
+    def fresh():
+        arenas = [wl.arena_image(v) for v in range(nvm)]
+        arenas += [np.zeros(4096, np.uint8) for _ in range(nvm, len(wl.vms))]
+        return Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs],
+                      wl.pool_image(), ept=[v.ept_root if v.vm < nvm else None for v in wl.vms])
+
     vm_of = np.array([p.vm for p in wl.procs])
-    reqs = wl.requests[vm_of[wl.requests["asid"]] < nvm]
+    idx = np.nonzero(vm_of[wl.requests["asid"]] < nvm)[0]
+    reqs = wl.requests[idx]
+    ends = np.unique(np.searchsorted(idx, wl.epoch_end.astype(np.int64), side="left").astype(np.uint64))
+    what = f"{len(reqs)} requests of VMs 0-{nvm - 1}" if nvm < len(wl.vms) else f"{len(reqs)} requests"
+    # one thread
+    o = fresh()
     tot_t, tot_b, done, passes = 0.0, 0, 0, 0
     chunk = 4096
     i = 0
@@ -135,11 +161,29 @@ def cpu_baseline(wl, seconds, name, max_vms=8):
         i += len(part)
         if dt < 0.2:
             chunk *= 2
-    sample = (f"{done} requests: {name}'s " + (f"{len(reqs)} requests of VMs 0-{nvm - 1}" if nvm < len(wl.vms)
-              else f"{len(reqs)} requests") + f" in index order, {done / len(reqs):.2f} passes, sequential, "
-              f"{tot_t:.1f} s on one of {os.cpu_count()} host cores")
-    return {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle", "sample": sample,
-            "mreq_s": round(done / tot_t / 1e6, 4)}
+    del o
+    one = {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1,
+           "mreq_s": round(done / tot_t / 1e6, 4),
+           "sample": f"{done} requests: {name}'s {what} in index order, {done / len(reqs):.2f} passes, "
+                     f"{tot_t:.1f} s"}
+    # N threads
+    nt = host_threads()
+    o = fresh()
+    tot_t, tot_b, npass = 0.0, 0, 0
+    while tot_t < seconds and npass < 20:
+        t0 = time.perf_counter()
+        r, _ = o.batch_mt(reqs, ends, threads=nt)
+        tot_t += time.perf_counter() - t0
+        tot_b += int(r["bytes_done"].sum())
+        npass += 1
+    del o
+    model = cpu_model()
+    return {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": nt, "kind": "oracle",
+            "mreq_s": round(npass * len(reqs) / tot_t / 1e6, 4), "cpu_model": model,
+            "host_cores_visible": os.cpu_count(),
+            "sample": f"{npass} passes over {name}'s {what}, each epoch's requests split over {nt} threads, "
+                      f"epochs in order, {tot_t:.1f} s on {model}",
+            "single_thread": one}
 
 
 def serving(args):
@@ -411,6 +455,161 @@ def map_bench(args):
                       "fresh": out["fresh"], "remap": out["remap"], "roofline": roof, "cpu_baseline": cpu}))
 
 
+TUNE_CACHE = os.path.join(ROOT, "paper_1304_3771_amd", "tuning_cache.jsonl")
+
+
+def tune(ctx, wl, name, dw, res, faults, nf, args):
+    """The launch configuration: the tuning cache's entry for this workload on
+    this device, else a tuning run (stored in the cache).  --retune tunes
+    afresh and appends the new entry."""
+    from workload import gen
+    key = gen.workload_key(wl, name)
+    n = wl.n_requests
+    reps = 3 if n <= 2_000_000 else 1
+    t0 = time.time()
+    if args.retune:
+        tmp = args.tune_cache + ".new"
+        if os.path.exists(tmp):
+            os.remove(tmp)
+        best, ms, hit = ctx.autotune_cached(tmp, key, dw.reqs, n, res, wl.epoch_end, faults, nf, reps=reps)
+        with open(tmp) as f, open(args.tune_cache, "a") as g:
+            g.write(f.read())
+        os.remove(tmp)
+    else:
+        best, ms, hit = ctx.autotune_cached(args.tune_cache, key, dw.reqs, n, res, wl.epoch_end, faults, nf,
+                                            reps=reps)
+    src = "tuning cache" if hit else "tuned now"
+    log(f"{name}: launch config from the {src} in {time.time() - t0:.1f}s: {best} ({ms:.3f} ms)")
+    return {"key": key, "source": src, "tuned_ms": round(ms, 4)}
+
+
+class Batched:
+    """Timed steps of one batched workload: between steps (untimed) the
+    page-table frames are restored and 1 GiB is written to flush the caches."""
+
+    def __init__(self, ctx, wl, dw, res, faults, nf, flush):
+        self.ctx, self.wl, self.dw, self.res, self.faults, self.nf, self.flush = ctx, wl, dw, res, faults, nf, flush
+
+    def reset(self):
+        import torch
+        restore_tables(self.ctx, self.wl)
+        self.flush.fill_(1)
+        torch.cuda.synchronize()
+
+    def step(self, t_done=None):
+        self.ctx.submit_batch(self.dw.reqs, self.wl.n_requests, self.res, self.wl.epoch_end, self.faults, self.nf,
+                              t_done)
+
+    def warm(self, k):
+        for _ in range(k):
+            self.reset()
+            self.step()
+            self.ctx.sync()
+        log(f"warmup done ({k})")
+
+    def profiled_steps(self, k, counters=False):
+        """k steps with HIP events around every kernel launch (no graphs); summed stats.
+        Device counters (which add atomics of their own) only when asked for."""
+        tot = None
+        for _ in range(k):
+            self.reset()
+            self.ctx.set_profiling(True, counters=counters)
+            self.ctx.reset_stats()
+            self.step()
+            self.ctx.sync()
+            st = self.ctx.get_stats()
+            self.ctx.set_profiling(False)
+            tot = st if tot is None else {key: tot[key] + st[key] for key in st}
+        return tot
+
+    def measure(self, warmup, steps, name, roof_steps=ROOF_STEPS):
+        """Timed steps, the copy kernel's roofline (overlapped, then alone) and
+        one step of device counters."""
+        import torch
+        import paper_1304_3771_amd as dv
+        ctx = self.ctx
+        self.warm(warmup)
+        times = []
+        for _ in range(steps):
+            self.reset()
+            t0 = time.perf_counter()
+            self.step()
+            ctx.sync()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        r = self.res.cpu().numpy().view(dv.RESULT_DTYPE)
+        copied = int(r["bytes_done"].sum())
+        ms_step = 1e3 * float(np.mean(times))
+        gbs = copied / (ms_step * 1e-3) / 1e9
+        nfaults = int(self.nf.item())
+        log(f"{name} batched: {ms_step:.3f} ms/step, {gbs:.1f} GB/s copied, {nfaults} faults")
+        # roofline of the dominant kernel (copy): HIP events around each launch
+        # on its stream, over roof_steps steps of the same batch and config
+        st = self.profiled_steps(roof_steps)
+        copy_launches = max(1, st["copy_launches"])
+        copy_ms = st["copy_ms"]
+        alg_copy = 2 * copied * roof_steps  # every copied byte is read once and written once
+        achieved = (alg_copy / copy_launches) / (copy_ms / copy_launches * 1e-3) / 1e9 if copy_ms > 0 else None
+        roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                "traffic": measured_traffic(name), "kernel": "k_copy", "launches": copy_launches,
+                "avg_launch_ms": round(copy_ms / copy_launches, 4), "alg_bytes_per_launch": alg_copy // copy_launches}
+        # the copy kernel alone on the GPU: translation not overlapped
+        tuned = ctx.get_config()
+        ctx.set_config(**{**tuned, "overlap": 0, "xlat_wgs_per_cu": 3})
+        st_alone = self.profiled_steps(roof_steps)
+        ctx.set_config(**tuned)
+        alone_ms = st_alone["copy_ms"] / max(1, st_alone["copy_launches"])
+        alone = (alg_copy / copy_launches) / (alone_ms * 1e-3) / 1e9 if alone_ms > 0 else None
+        roof_alone = {"bound": "hbm", "achieved": round(alone, 1) if alone else None, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(alone / HBM_PEAK_GBS, 4) if alone else None,
+                      "kernel": "k_copy", "avg_launch_ms": round(alone_ms, 4), "config": "overlap off"}
+        log(f"{name} copy kernel alone (no overlap): {alone_ms:.4f} ms/launch, {alone:.1f} GB/s algorithmic")
+        ps = self.profiled_steps(1, counters=True)  # device counters, in a step of their own
+        cnt = {k: ps[k] for k in ("pages_walked", "cache_hits", "cache_misses", "segments", "inline_segments",
+                                  "spilled_groups", "ad_atomics")}
+        lookups = cnt["cache_hits"] + cnt["cache_misses"]
+        cnt["cache_hit_rate"] = round(cnt["cache_hits"] / lookups, 4) if lookups else None
+        log(f"{name} copy kernel: {copy_launches // roof_steps} launches/step, {copy_ms / roof_steps:.3f} ms/step, "
+            f"{achieved:.1f} GB/s algorithmic; translate kernel: {st['xlat_ms'] / roof_steps:.3f} ms/step; "
+            f"per step: {cnt}")
+        return {"ms_per_step": ms_step, "gbs": gbs, "bytes_copied_per_step": copied, "faults": nfaults,
+                "req_per_s": self.wl.n_requests / (ms_step * 1e-3), "roofline": roof,
+                "roofline_copy_alone": roof_alone, "translate_ms_per_step": round(st["xlat_ms"] / roof_steps, 4),
+                "counters": cnt, "launch": ctx.get_config()}
+
+
+def extra_workload(name, args):
+    """Another batched workload measured in the same run (its own context):
+    tuned launch, timed steps, copy-kernel roofline and counters."""
+    import torch
+    import paper_1304_3771_amd as dv
+    from workload import device, gen
+    t0 = time.time()
+    log(f"{name}: generating")
+    wl = gen.make_workload(workload_spec(name))
+    n = wl.n_requests
+    ctx = dv.Context(0)
+    try:
+        dw = device.load(ctx, wl)
+        log(f"{name}: {n} requests, {len(wl.epoch_end)} epochs, loaded in {time.time() - t0:.1f}s")
+        res = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+        faults = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+        nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+        flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        tuning = tune(ctx, wl, name, dw, res, faults, nf, args)
+        m = Batched(ctx, wl, dw, res, faults, nf, flush).measure(1, args.extra_steps, name, roof_steps=2)
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
+    return {"workload": f"{name}: {WORKLOADS[name]}", "requests": n, "epochs": int(len(wl.epoch_end)),
+            "ms_per_step": round(m["ms_per_step"], 3), "value": round(m["gbs"], 2), "unit": "GB/s",
+            "req_per_s": round(m["req_per_s"], 1), "bytes_copied_per_step": m["bytes_copied_per_step"],
+            "faults": m["faults"], "roofline": m["roofline"], "roofline_copy_alone": m["roofline_copy_alone"],
+            "translate_ms_per_step": m["translate_ms_per_step"], "counters": m["counters"],
+            "launch": m["launch"], "tuning": tuning, "steps": args.extra_steps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -423,6 +622,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="skip autotuning the batch launch")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, help="tuning cache (JSON lines) to read and extend")
+    ap.add_argument("--retune", action="store_true", help="tune afresh and append the result to the cache")
+    ap.add_argument("--extra", default=None,
+                    help="more batched workloads measured after the main one (default: C3,C5 after C2)")
+    ap.add_argument("--extra-steps", type=int, default=3, help="timed steps of each extra workload")
     ap.add_argument("--profile-only", action="store_true", help="only run K timed steps (for rocprofv3)")
     ap.add_argument("--set", default="", help="launch config overrides, e.g. seg_chunks=64,nontemporal=1")
     ap.add_argument("--serving", action="store_true", help="run the C4 serving sweep instead")
@@ -474,43 +678,16 @@ def main():
     faults = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
     nf = torch.zeros(1, dtype=torch.int64, device="cuda")
     flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-
+    tuning = None
     if not args.no_autotune and not args.set:
-        t_at = time.time()
-        best, ms = ctx.autotune(dw.reqs, n, res, wl.epoch_end, faults, nf, reps=3 if n <= 2_000_000 else 1)
-        log(f"autotuned in {time.time() - t_at:.1f}s: {best} ({ms:.3f} ms)")
+        tuning = tune(ctx, wl, args.workload, dw, res, faults, nf, args)
 
-    def reset():
-        restore_tables(ctx, wl)
-        flush.fill_(1)
-        torch.cuda.synchronize()
-
-    def step():
-        ctx.submit_batch(dw.reqs, n, res, wl.epoch_end, faults, nf)
-
-    def profiled_steps(k, counters=False):
-        """k steps with HIP events around every kernel launch (no graphs); summed stats.
-        Device counters (which add atomics of their own) only when asked for."""
-        tot = None
-        for _ in range(k):
-            reset()
-            ctx.set_profiling(True, counters=counters)
-            ctx.reset_stats()
-            step()
-            ctx.sync()
-            st = ctx.get_stats()
-            ctx.set_profiling(False)
-            tot = st if tot is None else {key: tot[key] + st[key] for key in st}
-        return tot
-
-    for i in range(args.warmup):
-        reset()
-        step()
-        ctx.sync()
-    log(f"warmup done ({args.warmup})")
+    n_epochs = int(len(wl.epoch_end))
+    B = Batched(ctx, wl, dw, res, faults, nf, flush)
     if args.profile_only:
+        B.warm(args.warmup)
         # the steps the roofline is measured on, for rocprofv3 to trace
-        st = profiled_steps(args.steps)
+        st = B.profiled_steps(args.steps)
         r = res.cpu().numpy().view(dv.RESULT_DTYPE)
         copied = int(r["bytes_done"].sum())
         # a plain copy-like kernel of known size (1 GiB read + 1 GiB written) to scale HBM counters
@@ -526,64 +703,23 @@ def main():
                           "copy_launches_per_step": int(len(wl.epoch_end)),
                           "alg_copy_bytes_per_step": 2 * copied, "calibration_bytes_each_way": 1 << 30}))
         return
-    times = []
-    for i in range(args.steps):
-        reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        step()
-        ctx.sync()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    r = res.cpu().numpy().view(dv.RESULT_DTYPE)
-    copied = int(r["bytes_done"].sum())
-    ms_step = 1e3 * float(np.mean(times))
-    gbs = copied / (ms_step * 1e-3) / 1e9
-    log(f"batched: {ms_step:.3f} ms/step, {gbs:.1f} GB/s copied, {int(nf.item())} faults")
-
-    # ---- roofline of the dominant kernel (copy): HIP events around each
-    # launch on its stream, over ROOF_STEPS steps of the same batch and config
-    st = profiled_steps(ROOF_STEPS)
-    copy_ms = st["copy_ms"]
-    copy_launches = max(1, st["copy_launches"])
-    alg_copy = 2 * copied * ROOF_STEPS  # every copied byte is read once and written once
-    achieved = (alg_copy / copy_launches) / (copy_ms / copy_launches * 1e-3) / 1e9 if copy_ms > 0 else None
-    traffic = measured_traffic(args.workload)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": traffic,
-            "kernel": "k_copy", "launches": copy_launches,
-            "avg_launch_ms": round(copy_ms / copy_launches, 4),
-            "alg_bytes_per_launch": alg_copy // copy_launches}
-    # the same measurement with translation not overlapped: the copy kernel alone on the GPU
-    tuned = ctx.get_config()
-    ctx.set_config(**{**tuned, "overlap": 0, "xlat_wgs_per_cu": 3})
-    st_alone = profiled_steps(ROOF_STEPS)
-    ctx.set_config(**tuned)
-    alone_ms = st_alone["copy_ms"] / max(1, st_alone["copy_launches"])
-    alone = (alg_copy / copy_launches) / (alone_ms * 1e-3) / 1e9 if alone_ms > 0 else None
-    roof_alone = {"bound": "hbm", "achieved": round(alone, 1) if alone else None, "peak": HBM_PEAK_GBS,
-                  "unit": "GB/s", "frac": round(alone / HBM_PEAK_GBS, 4) if alone else None,
-                  "kernel": "k_copy", "avg_launch_ms": round(alone_ms, 4), "config": "overlap off"}
-    log(f"copy kernel alone (no overlap): {alone_ms:.4f} ms/launch, {alone:.1f} GB/s algorithmic")
-    ps = profiled_steps(1, counters=True)  # one more step for the device counters
-    log(f"copy kernel: {copy_launches // ROOF_STEPS} launches/step, {copy_ms / ROOF_STEPS:.3f} ms/step, "
-        f"{achieved:.1f} GB/s algorithmic; translate kernel: {st['xlat_ms'] / ROOF_STEPS:.3f} ms/step; "
-        f"per step: pages {ps['pages_walked']}, cache hits {ps['cache_hits']} misses {ps['cache_misses']}, "
-        f"segments {ps['segments']}, A/D ORs {ps['ad_atomics']}")
-    path_alg = 2 * copied + 56 * n + 8 * ps["pages_walked"] + 24 * int(nf.item())
+    m = B.measure(args.warmup, args.steps, args.workload)
+    ms_step, gbs, copied = m["ms_per_step"], m["gbs"], m["bytes_copied_per_step"]
+    roof, roof_alone, counters = m["roofline"], m["roofline_copy_alone"], m["counters"]
+    path_alg = 2 * copied + 56 * n + 8 * counters["pages_walked"] + 24 * int(nf.item())
     path_frac = path_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
     # ---- batched per-request completion latency (device clock)
-    reset()
+    B.reset()
     td = torch.zeros(n, dtype=torch.int64, device="cuda")
-    ctx.submit_batch(dw.reqs, n, res, wl.epoch_end, faults, nf, td)
+    B.step(td)
     ctx.sync()
     tdn = td.cpu().numpy() / 1e3
     lat_batched = {"p50_us": pct(tdn, 50), "p99_us": pct(tdn, 99), "max_us": float(tdn.max())}
     log(f"batched latency p50 {lat_batched['p50_us']:.1f} us p99 {lat_batched['p99_us']:.1f} us")
 
     # ---- plain per-request launches (throughput over a sample, then latency)
-    reset()
+    B.reset()
     ps = min(args.plain_sample, n)
     hreq = dw.reqs_host
     pres = torch.zeros(ps * 24, dtype=torch.uint8, device="cuda")
@@ -637,11 +773,24 @@ def main():
     mreq = args.xlat_n / float(np.median(xt)) / 1e6
     log(f"translate: {mreq:.1f} Mreq/s")
 
-    # ---- CPU baseline: the oracle, single thread, on a bounded sample of the same workload
+    launch = ctx.get_config()
+    ctx.close()
+    del dw, res, faults, nf, flush, B, td, xo, dg, pres
+    torch.cuda.empty_cache()
+
+    # ---- CPU baseline: the oracle, one thread and N threads, on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, args.cpu_seconds, args.workload)
-        log(f"cpu baseline: {cpu['value']} GB/s ({cpu['sample']})")
+        log(f"cpu baseline: {cpu['value']} GB/s on {cpu['cores']} threads, {cpu['single_thread']['value']} GB/s "
+            f"on one ({cpu['sample']})")
+    del wl
+
+    # ---- the other batched workloads, measured in the same run
+    extra = {}
+    extra_names = args.extra if args.extra is not None else ("C3,C5" if args.workload == "C2" else "")
+    for name in [x for x in extra_names.split(",") if x and x != args.workload]:
+        extra[name] = extra_workload(name, args)
 
     out = {
         "metric": METRIC,
@@ -657,8 +806,7 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "requests": n,
-                   "epochs": int(len(wl.epoch_end)), "bytes_copied_per_step": copied,
-                   "launch": ctx.get_config()},
+                   "epochs": n_epochs, "bytes_copied_per_step": copied, "launch": launch, "tuning": tuning},
         "translate_mreq_s": round(mreq, 2),
         "batched": {"req_per_s": round(batched_req_s, 1), "latency_us": lat_batched,
                     "latency_clock": "device wall clock, from the start of the submission"},
@@ -667,9 +815,10 @@ def main():
         "roofline": roof,
         "roofline_copy_alone": roof_alone,
         "path_roofline_frac": round(path_frac, 4),
+        "counters": counters,
         "cpu_baseline": cpu,
+        "workloads": extra,
     }
-    ctx.close()
     print(json.dumps(out))
 
 

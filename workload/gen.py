@@ -24,7 +24,11 @@ Workload recipe (each VM, each process):
   so that no epoch places more than ``rho`` of any VMA, and inside an epoch
   they are packed into their VMA in index order at random gaps, so requests
   of one epoch never overlap in guest memory.  Host offsets are disjoint
-  within an epoch with a random 0-63 byte skew.
+  within an epoch with a random 0-63 byte skew.  With ``pool_mode="unique"``
+  every request has pool bytes of its own; with ``"reuse"`` each VM owns a
+  range of the pool, and in every epoch its requests take consecutive
+  stretches of that range from its start, so later epochs reuse the bytes of
+  earlier ones while different VMs never share a pool byte.
 
 The page-table format written here is the x86-64 one (4-level, and 5-level
 with 57-bit addresses): 512 eight-byte entries per 4 KiB table; bit 0 present,
@@ -229,6 +233,8 @@ class Workload:
     pool_bytes: int
     seed: int
     req_vma: np.ndarray = field(default=None)
+    # reuse mode: VM v's requests use pool bytes [pool_vm[v, 0], pool_vm[v, 0] + pool_vm[v, 1])
+    pool_vm: np.ndarray = field(default=None)
 
     # -- images -------------------------------------------------------------
     def arena_image(self, vm: int, out: np.ndarray | None = None) -> np.ndarray:
@@ -270,6 +276,17 @@ class Workload:
         for e in self.epoch_end:
             yield s, int(e)
             s = int(e)
+
+
+def workload_key(wl: Workload, name: str) -> str:
+    """A name for the batch's shape: the workload's name and a digest of its
+    spec, requests and epoch cuts (keys the tuning cache)."""
+    import hashlib
+    h = hashlib.blake2b(digest_size=8)
+    h.update(repr(wl.spec).encode())
+    h.update(np.ascontiguousarray(wl.requests).view(np.uint8).tobytes())
+    h.update(np.ascontiguousarray(wl.epoch_end, np.uint64).tobytes())
+    return f"{name}-{h.hexdigest()}"
 
 
 def gpa_to_arena(slots: np.ndarray, gpa: np.ndarray) -> np.ndarray:
@@ -695,11 +712,26 @@ def _make_requests(rng, sp: Spec, wl: Workload) -> None:
         host = np.cumsum(span) - length
         pool = int(host[-1] + length[-1]) if n else 0
     else:
-        cs = np.cumsum(span).astype(np.int64)
-        ep_start = np.concatenate([[0], epoch_end[:-1].astype(np.int64)])
-        base = np.where(ep_start > 0, cs[np.maximum(ep_start - 1, 0)], 0)
-        host = (cs - base[epoch_of] - length.astype(np.int64)).astype(np.uint64)
-        pool = int((host + length).max()) if n else 0
+        # consecutive stretches per (epoch, VM), inside the VM's own pool range
+        n_vms = len(wl.vms)
+        vm_of = np.array([p.vm for p in wl.procs], np.int64)[asid] if n else np.zeros(0, np.int64)
+        key = epoch_of * n_vms + vm_of
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        sp_o = span[order].astype(np.int64)
+        cs = np.cumsum(sp_o)
+        first = np.concatenate([[0], np.nonzero(np.diff(ks))[0] + 1]) if n else np.zeros(0, np.int64)
+        gid = np.repeat(np.arange(len(first)), np.diff(np.concatenate([first, [n]])))
+        end_in = cs - (cs[first] - sp_o[first])[gid]      # end of each request inside its stretch
+        need = np.zeros(n_vms, np.int64)
+        if n:
+            np.maximum.at(need, vm_of[order[first]], end_in[np.concatenate([first[1:] - 1, [n - 1]])])
+        size = (need + 4095) & ~4095
+        vbase = np.concatenate([[0], np.cumsum(size)[:-1]]).astype(np.int64)
+        host = np.zeros(n, np.uint64)
+        host[order] = (vbase[vm_of[order]] + end_in - length[order].astype(np.int64)).astype(np.uint64)
+        pool = int(size.sum())
+        wl.pool_vm = np.stack([vbase, size], axis=1).astype(np.uint64)
     pool = (pool + 4095) & ~4095
     req = np.zeros(n, REQ_DTYPE)
     req["gva"], req["host"], req["len"], req["asid"], req["dir"] = gva, host, length.astype(np.uint32), asid, direction
