@@ -295,6 +295,9 @@ typedef struct {
                                  and replay it                                     */
     uint32_t overlap;         /* 1: translate epoch e+1 on a second stream while
                                  epoch e is being copied                          */
+    uint32_t fifo_entries;    /* per-request path: entries of each process's FIFO
+                                 translation cache (section 4.2 uses 10), 0..16;
+                                 0 = no cache (see devirt_fifo_counts)             */
 } devirt_config;
 
 int devirt_get_config(devirt_ctx *ctx, devirt_config *cfg);
@@ -323,6 +326,28 @@ int devirt_autotune_cached(devirt_ctx *ctx, const char *cache_path_host, const c
                            uint32_t n_epochs, devirt_result *res_dev, devirt_fault *faults_dev,
                            uint64_t *n_faults_dev, void *hip_stream, uint32_t reps, devirt_config *best,
                            double *best_ms, int *hit);
+
+/* The per-process translation cache of section 4.2 (the backend keeps each
+ * guest process's recent translations in a FIFO of 10 entries).  With
+ * devirt_config.fifo_entries = k > 0, the per-request calls (devirt_copy_*)
+ * look each page they translate up in the process's k-entry FIFO, in page
+ * order, up to and including the first faulting page.  A lookup hits when the
+ * 4 KiB page is held and, for a copy into the guest, was filled or last
+ * refreshed by such a copy; a hit skips the page walk (its A/D bits are
+ * already set).  A miss walks; a successful walk inserts the page at the
+ * tail, evicting the oldest entry when full (or marks a held entry written);
+ * hits never reorder; failed walks insert nothing.  Results are the same with
+ * and without the cache.  Any devirt_vm_write, memslot, EPT, process or
+ * devirt_map_pages call empties every cache (counts are kept); a caller that
+ * writes page tables through the devirt_vm_arena pointer must call
+ * devirt_fifo_flush.  Per-request calls of one process must be ordered (one
+ * stream) while the cache is on.  The batched and serving paths do not use
+ * it.
+ * devirt_fifo_counts: the process's hits and misses since the last flush
+ * (synchronises the device); -ENOENT for an unknown asid.
+ * devirt_fifo_flush: empty every process's cache and zero its counts. */
+int devirt_fifo_counts(devirt_ctx *ctx, uint32_t asid, uint64_t *hits, uint64_t *misses);
+int devirt_fifo_flush(devirt_ctx *ctx);
 
 /* ---------------------------------------------------------------- metrics */
 
@@ -381,16 +406,22 @@ int devirt_reset_stats(devirt_ctx *ctx);
  *  DEVIRT_SERVE_BLOCKING the server waits for each batch before it admits
  *                        anything else: one batch at a time, no overlap (the
  *                        blocking mode of section 5).
- * Results do not depend on the mode. */
+ * Results do not depend on the mode.  DEVIRT_SERVE_DEVICE_TIMES may be OR-ed
+ * into the mode: each batch is then bracketed by timing events on its
+ * stream, and every completion carries its batch's window on the device
+ * clock (dev_start_ns, dev_end_ns); two batches whose windows overlap were
+ * executing on the GPU at the same time. */
 #define DEVIRT_SERVE_POLL 0u
 #define DEVIRT_SERVE_NOTIFY 1u
 #define DEVIRT_SERVE_BLOCKING 2u
+#define DEVIRT_SERVE_DEVICE_TIMES 0x100u
 typedef struct {
     uint32_t max_inflight; /* descriptor slots (operations admitted, not yet done)  */
     uint64_t pool_bytes;   /* byte budget of operations in flight                   */
     uint32_t max_batch;    /* operations per launch (0: max_inflight)               */
     uint32_t streams;      /* launches in flight at once, 1..8                      */
-    uint32_t flags;        /* completion mode: one DEVIRT_SERVE_* value             */
+    uint32_t flags;        /* completion mode: one DEVIRT_SERVE_* mode, optionally
+                              | DEVIRT_SERVE_DEVICE_TIMES                          */
 } devirt_server_cfg;
 
 typedef struct {
@@ -399,6 +430,9 @@ typedef struct {
     uint64_t t_submit_ns;  /* host steady clock: submitted                          */
     uint64_t t_admit_ns;   /* admitted into a launch                                */
     uint64_t t_done_ns;    /* completion observed by the server                     */
+    uint64_t dev_start_ns; /* DEVIRT_SERVE_DEVICE_TIMES: the batch's window on the
+                              device, ns after the server started (else 0)        */
+    uint64_t dev_end_ns;
 } devirt_completion;
 
 /* Start a server thread on the context.  While it runs, the context may

@@ -60,6 +60,7 @@ struct GThread {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
+    hipEvent_t t_start = nullptr, t_end = nullptr;  // DEVIRT_SERVE_DEVICE_TIMES: the batch's window
     devirt_server *srv = nullptr;  // for the completion host function
     uint32_t idx = 0;
     devirt_request *h_reqs = nullptr;  // pinned, device-visible
@@ -74,6 +75,9 @@ struct Slot {
 struct devirt_server {
     devirt_ctx *ctx = nullptr;
     devirt_server_cfg cfg{};
+    uint32_t mode = 0;          // DEVIRT_SERVE_POLL / NOTIFY / BLOCKING
+    bool device_times = false;  // DEVIRT_SERVE_DEVICE_TIMES
+    hipEvent_t t_ref = nullptr; // device-time origin, recorded at start
     std::thread th;
     std::atomic<bool> stop{false};
     std::atomic<int> err{0};
@@ -134,15 +138,19 @@ static int launch_slot(devirt_server *s, Slot &sl) {
     }
     const bool direct = n <= kDirectOps && total <= kDirectBytes && largest <= kDirectMaxOp;
     const uint64_t t0 = now_ns();
+    if (s->device_times && hipEventRecord(sl.t_start, sl.stream) != hipSuccess)
+        return dv_fail(-EIO, "server: event record failed");
     int rc = dv_submit(s->ctx, sl.h_reqs, n, nullptr, 0, sl.h_res, nullptr, nullptr, nullptr, sl.stream, false,
                        direct);
     if (rc) return rc;
+    if (s->device_times && hipEventRecord(sl.t_end, sl.stream) != hipSuccess)
+        return dv_fail(-EIO, "server: event record failed");
     if (direct) s->st_direct++;
     if (hipEventRecord(sl.ev, sl.stream) != hipSuccess) return dv_fail(-EIO, "server: event record failed");
-    if (s->cfg.flags == DEVIRT_SERVE_NOTIFY &&
+    if (s->mode == DEVIRT_SERVE_NOTIFY &&
         hipLaunchHostFunc(sl.stream, on_batch_done, &sl) != hipSuccess)
         return dv_fail(-EIO, "server: cannot enqueue the completion function");
-    if (s->cfg.flags == DEVIRT_SERVE_BLOCKING && hipStreamSynchronize(sl.stream) != hipSuccess)
+    if (s->mode == DEVIRT_SERVE_BLOCKING && hipStreamSynchronize(sl.stream) != hipSuccess)
         return dv_fail(-EIO, "server: batch failed");
     s->ns_launch += now_ns() - t0;
     sl.busy = true;
@@ -186,7 +194,7 @@ static void server_loop(devirt_server *s) {
         // completions
         for (auto &sl : s->slots) {
             if (!sl.busy) continue;
-            if (s->cfg.flags == DEVIRT_SERVE_NOTIFY) {
+            if (s->mode == DEVIRT_SERVE_NOTIFY) {
                 const uint32_t bit = 1u << sl.idx;
                 if (!(s->done_bits.load(std::memory_order_acquire) & bit)) continue;
                 s->done_bits.fetch_and(~bit, std::memory_order_relaxed);
@@ -200,6 +208,15 @@ static void server_loop(devirt_server *s) {
                 continue;
             }
             const uint64_t t = now_ns();
+            uint64_t d0 = 0, d1 = 0;
+            if (s->device_times) {
+                float a = 0, b = 0;
+                if (hipEventElapsedTime(&a, s->t_ref, sl.t_start) == hipSuccess &&
+                    hipEventElapsedTime(&b, s->t_ref, sl.t_end) == hipSuccess) {
+                    d0 = (uint64_t)((double)a * 1e6);
+                    d1 = (uint64_t)((double)b * 1e6);
+                }
+            }
             std::vector<devirt_completion> &out = s->outbuf;
             out.resize(sl.ops.size());
             for (size_t i = 0; i < sl.ops.size(); ++i) {
@@ -209,6 +226,8 @@ static void server_loop(devirt_server *s) {
                 out[i].t_submit_ns = op.t_submit;
                 out[i].t_admit_ns = sl.t_admit[i];
                 out[i].t_done_ns = t;
+                out[i].dev_start_ns = d0;
+                out[i].dev_end_ns = d1;
                 GThread &g = s->threads[op.th];
                 g.busy = false;
                 if (!g.q.empty()) s->ready.push_back(op.th);
@@ -262,7 +281,7 @@ static void server_loop(devirt_server *s) {
         if (!progress) {
             bool inflight = false;
             for (auto &sl : s->slots) inflight = inflight || sl.busy;
-            if ((inflight && s->cfg.flags != DEVIRT_SERVE_NOTIFY) || !s->ready.empty()) {
+            if ((inflight && s->mode != DEVIRT_SERVE_NOTIFY) || !s->ready.empty()) {
                 // batches on the GPU: poll again soon, without hogging the core
                 for (int k = 0; k < 64; ++k) __builtin_ia32_pause();
                 std::this_thread::yield();
@@ -286,6 +305,8 @@ static void free_server(devirt_server *s) {
         hipHostFree(sl.h_reqs);
         hipHostFree(sl.h_res);
         if (sl.ev) hipEventDestroy(sl.ev);
+        if (sl.t_start) hipEventDestroy(sl.t_start);
+        if (sl.t_end) hipEventDestroy(sl.t_end);
         if (sl.stream) {
             auto it = s->ctx->ws.find(sl.stream);
             if (it != s->ctx->ws.end()) {
@@ -295,6 +316,7 @@ static void free_server(devirt_server *s) {
             hipStreamDestroy(sl.stream);
         }
     }
+    if (s->t_ref) hipEventDestroy(s->t_ref);
     s->ctx->server = nullptr;
     delete s;
 }
@@ -305,11 +327,15 @@ extern "C" int devirt_server_start(devirt_ctx *c, const devirt_server_cfg *cfg, 
     if (c->server) return dv_fail(-EBUSY, "a server is already running on this context");
     if (cfg->max_inflight == 0 || cfg->pool_bytes == 0) return dv_fail(-EINVAL, "max_inflight and pool_bytes must be > 0");
     if (cfg->streams < 1 || cfg->streams > 8) return dv_fail(-EINVAL, "streams must be 1..8");
-    if (cfg->flags > DEVIRT_SERVE_BLOCKING) return dv_fail(-EINVAL, "flags must be one DEVIRT_SERVE_* mode");
+    const uint32_t mode = cfg->flags & ~DEVIRT_SERVE_DEVICE_TIMES;
+    if (mode > DEVIRT_SERVE_BLOCKING)
+        return dv_fail(-EINVAL, "flags must be one DEVIRT_SERVE_* mode, optionally with DEVIRT_SERVE_DEVICE_TIMES");
     if (hipSetDevice(c->device) != hipSuccess) return dv_fail(-EIO, "hipSetDevice");
     devirt_server *s = new devirt_server();
     s->ctx = c;
     s->cfg = *cfg;
+    s->mode = mode;
+    s->device_times = (cfg->flags & DEVIRT_SERVE_DEVICE_TIMES) != 0;
     c->server = s;
     const uint32_t max_batch = cfg->max_batch ? cfg->max_batch : cfg->max_inflight;
     s->slots.resize(cfg->streams);  // never resized again: host functions keep slot addresses
@@ -321,7 +347,9 @@ extern "C" int devirt_server_start(devirt_ctx *c, const devirt_server_cfg *cfg, 
                   hipHostMalloc(&sl.h_reqs, (size_t)max_batch * sizeof(devirt_request),
                                 hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
                   hipHostMalloc(&sl.h_res, (size_t)max_batch * sizeof(devirt_result),
-                                hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+                                hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+                  (!s->device_times || (hipEventCreateWithFlags(&sl.t_start, hipEventDisableSystemFence) == hipSuccess &&
+                                        hipEventCreateWithFlags(&sl.t_end, hipEventDisableSystemFence) == hipSuccess));
         if (!ok) {
             free_server(s);
             return dv_fail(-ENOMEM, "server: cannot allocate launch slots");
@@ -333,6 +361,14 @@ extern "C" int devirt_server_start(devirt_ctx *c, const devirt_server_cfg *cfg, 
             return rc;
         }
         sl.ops.reserve(max_batch);
+    }
+    if (s->device_times) {
+        // the origin of device times: recorded on a slot stream and waited for
+        if (hipEventCreate(&s->t_ref) != hipSuccess || hipEventRecord(s->t_ref, s->slots[0].stream) != hipSuccess ||
+            hipEventSynchronize(s->t_ref) != hipSuccess) {
+            free_server(s);
+            return dv_fail(-EIO, "server: cannot record the device-time origin");
+        }
     }
     s->th = std::thread(server_loop, s);
     *out = s;

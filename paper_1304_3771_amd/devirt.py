@@ -45,12 +45,13 @@ class DevirtError(RuntimeError):
 
 PROF_TIMING, PROF_COUNTERS = 1, 2  # devirt_set_profiling flags
 SERVE_MODES = {"poll": 0, "notify": 1, "blocking": 2}  # devirt_server_cfg.flags
+SERVE_DEVICE_TIMES = 0x100
 
 
 class Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "group", "seg_chunks", "xlat_wg", "xlat_wgs_per_cu", "copy_wg", "copy_wgs_per_cu", "nontemporal",
-        "inline_bytes", "use_graph", "overlap")]
+        "inline_bytes", "use_graph", "overlap", "fifo_entries")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -88,12 +89,13 @@ class Result(ctypes.Structure):
 
 class Completion(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("res", Result), ("t_submit_ns", ctypes.c_uint64),
-                ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+                ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64), ("dev_start_ns", ctypes.c_uint64),
+                ("dev_end_ns", ctypes.c_uint64)]
 
 
 COMPLETION_DTYPE = np.dtype([("ticket", "<u8"), ("bytes_done", "<u8"), ("fault_gva", "<u8"), ("code", "<u4"),
                              ("level", "<u2"), ("pad", "<u2"), ("t_submit_ns", "<u8"), ("t_admit_ns", "<u8"),
-                             ("t_done_ns", "<u8")])
+                             ("t_done_ns", "<u8"), ("dev_start_ns", "<u8"), ("dev_end_ns", "<u8")])
 assert COMPLETION_DTYPE.itemsize == ctypes.sizeof(Completion)
 
 _lib = None
@@ -120,6 +122,8 @@ _SIGS = {
                          ctypes.POINTER(ctypes.c_double)]),
     "devirt_autotune_cached": ([vp, ctypes.c_char_p, ctypes.c_char_p, vp, u64, vp, u32, vp, vp, vp, vp, u32,
                                 ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]),
+    "devirt_fifo_counts": ([vp, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+    "devirt_fifo_flush": ([vp]),
     "devirt_set_profiling": ([vp, i32]),
     "devirt_get_stats": ([vp, ctypes.POINTER(Stats)]),
     "devirt_reset_stats": ([vp]),
@@ -331,10 +335,22 @@ class Context:
     def reset_stats(self):
         _check("devirt_reset_stats", lib().devirt_reset_stats(self._h))
 
+    def fifo_counts(self, asid: int):
+        """(hits, misses) of the process's translation cache since the last flush."""
+        h, m = u64(), u64()
+        _check("devirt_fifo_counts", lib().devirt_fifo_counts(self._h, asid, ctypes.byref(h), ctypes.byref(m)))
+        return int(h.value), int(m.value)
+
+    def fifo_flush(self):
+        _check("devirt_fifo_flush", lib().devirt_fifo_flush(self._h))
+
     # ---- serving
-    def server_start(self, max_inflight=4096, pool_bytes=1 << 30, max_batch=0, streams=2, completion="poll"):
-        """completion: "poll", "notify" or "blocking" (the DEVIRT_SERVE_* modes)."""
-        cfg = ServerCfg(max_inflight, pool_bytes, max_batch, streams, SERVE_MODES[completion])
+    def server_start(self, max_inflight=4096, pool_bytes=1 << 30, max_batch=0, streams=2, completion="poll",
+                     device_times=False):
+        """completion: "poll", "notify" or "blocking" (the DEVIRT_SERVE_* modes);
+        device_times: completions carry their batch's device window."""
+        cfg = ServerCfg(max_inflight, pool_bytes, max_batch, streams,
+                        SERVE_MODES[completion] | (SERVE_DEVICE_TIMES if device_times else 0))
         h = vp()
         _check("devirt_server_start", lib().devirt_server_start(self._h, ctypes.byref(cfg), ctypes.byref(h)))
         return Server(h)

@@ -1,7 +1,9 @@
 """Serving loop: every operation's result, and all memory, are the same alone
 (one operation at a time through the plain per-request path) and in the mix
 (continuous batching over several streams, each completion mode), and both
-equal the oracle.  Tolerance: none (bit-exact)."""
+equal the oracle.  Tolerance: none (bit-exact).  Device-side batch windows
+show that batches of the non-blocking modes ran on the GPU at the same time,
+and that the blocking mode ran one at a time."""
 import time
 
 import numpy as np
@@ -18,13 +20,22 @@ CLASSES = ((0.60, "uniform", 24, 24, 1), (0.25, "uniform", 4096, 4096, 0),
            (0.14, "loguniform", 16 << 10, 256 << 10, 0), (0.01, "uniform", 1 << 20, 1 << 20, 1))
 
 
-@pytest.fixture(scope="module", params=["memslots", "ept"])
+@pytest.fixture(scope="module", params=["memslots", "ept", "c4"])
 def trace(request):
     """Two VMs translated through their memslots, or through EPTs with some
-    leaves not present, read-only or misconfigured."""
+    leaves not present, read-only or misconfigured (256 MiB each, 1 MiB
+    frames); or two of the serving configuration's VMs at its own shape (4 GiB
+    each, 4 processes, 16 memslots, 6 MiB thread windows) with its own class
+    mix, 4,147,200-byte camera frames included."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    if request.param == "c4":
+        wl = gen.make_workload(gen.spec("C4", n_vms=2, seed=46), requests=False)
+        tr = gen.make_serving_trace(wl, 3000, 2e5, threads_per_proc=8, classes=gen.C4_CLASSES,
+                                    host_mode="unique", seed=47)
+        assert np.count_nonzero(tr.requests["len"] == 4147200) >= 10
+        return wl, tr
     sp = gen.spec("C4", n_vms=2, procs_per_vm=2, mem_bytes=256 * MiB, seed=44)
     if request.param == "ept":
         sp = sp.replace(ept=True, ept_np=0.02, ept_ro=0.03, ept_mis=0.01)
@@ -32,6 +43,18 @@ def trace(request):
     tr = gen.make_serving_trace(wl, 3000, 2e5, threads_per_proc=8, window=2 * MiB, classes=CLASSES,
                                 host_mode="unique", seed=45)
     return wl, tr
+
+
+@pytest.fixture(scope="module")
+def expected(trace):
+    """The oracle applied to the operations in submission order."""
+    wl, tr = trace
+    arenas = [wl.arena_image(v) for v in range(len(wl.vms))]
+    opool = gen.fill_bytes(np.empty(tr.pool_bytes, np.uint8), wl.seed, gen.POOL_KEY)
+    o = Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], opool,
+               ept=[v.ept_root for v in wl.vms])
+    er, _ = o.batch(tr.requests)
+    return er, o.arenas, o.pool
 
 
 def _load(ctx, wl, tr):
@@ -67,8 +90,21 @@ def alone(trace):
         ctx.close()
 
 
+def _overlapping_windows(c):
+    """Pairs of distinct batches whose device windows overlap."""
+    w = np.unique(np.stack([c["dev_start_ns"], c["dev_end_ns"]], axis=1), axis=0)
+    w = w[np.argsort(w[:, 0], kind="stable")]
+    pairs = 0
+    ends = []  # ends of the windows still open at the current start
+    for a, b in w:
+        ends = [e for e in ends if e > a]
+        pairs += len(ends)
+        ends.append(b)
+    return pairs, len(w)
+
+
 @pytest.mark.parametrize("completion", ["poll", "notify", "blocking"])
-def test_alone_vs_mix(trace, alone, completion):
+def test_alone_vs_mix(trace, alone, expected, completion):
     wl, tr = trace
     n = len(tr.requests)
     alone_res, alone_arenas, alone_pool = alone
@@ -77,8 +113,9 @@ def test_alone_vs_mix(trace, alone, completion):
     ctx = new_ctx()
     try:
         dw, pool, reqs = _load(ctx, wl, tr)
-        srv = ctx.server_start(max_inflight=256, pool_bytes=4 * MiB, max_batch=64, streams=3,
-                               completion=completion)
+        budget = max(4 * MiB, int(tr.requests["len"].max()))
+        srv = ctx.server_start(max_inflight=256, pool_bytes=budget, max_batch=64, streams=3,
+                               completion=completion, device_times=True)
         comps = []
         try:
             t0 = time.monotonic_ns()
@@ -109,6 +146,14 @@ def test_alone_vs_mix(trace, alone, completion):
     for a, b in zip(mix_arenas, alone_arenas):
         assert np.array_equal(a, b)
     assert np.array_equal(mix_pool, alone_pool)
+    # batches on the device: windows from timing events around each launch
+    assert np.all(c["dev_end_ns"] > c["dev_start_ns"])
+    pairs, batches = _overlapping_windows(c)
+    log(f"serving {completion}: {batches} batches, {pairs} pairs ran on the GPU at the same time")
+    if completion == "blocking":
+        assert pairs == 0, "blocking mode ran two batches at once"
+    else:
+        assert pairs > 0, "no two batches were on the GPU at the same time"
     # one operation in flight per guest thread; admitted ones overlap in time
     key = reqs["asid"].astype(np.uint64) << np.uint64(32) | reqs["tag"].astype(np.uint64)
     for k in np.unique(key):
@@ -121,18 +166,14 @@ def test_alone_vs_mix(trace, alone, completion):
     for t, kind, b in ev:
         cur += b
         peak = max(peak, cur)
-    assert peak <= 4 * MiB or peak <= int(reqs["len"].max())
+    assert peak <= budget or peak <= int(reqs["len"].max())
     # both equal the oracle applied in submission order
-    arenas = [wl.arena_image(v) for v in range(len(wl.vms))]
-    opool = gen.fill_bytes(np.empty(tr.pool_bytes, np.uint8), wl.seed, gen.POOL_KEY)
-    o = Oracle(arenas, [v.slots for v in wl.vms], [(p.vm, p.cr3, p.levels) for p in wl.procs], opool,
-               ept=[v.ept_root for v in wl.vms])
-    er, _ = o.batch(tr.requests)
+    er, oarenas, opool = expected
     for f in ("bytes_done", "fault_gva", "code", "level"):
         assert np.array_equal(c[f], er[f]), f
-    for a, b in zip(mix_arenas, o.arenas):
+    for a, b in zip(mix_arenas, oarenas):
         assert np.array_equal(a, b)
-    assert np.array_equal(mix_pool, o.pool)
+    assert np.array_equal(mix_pool, opool)
 
 
 def test_server_refuses_misuse(trace):
