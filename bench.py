@@ -579,6 +579,56 @@ class Batched:
                 "counters": cnt, "launch": ctx.get_config()}
 
 
+def fifo_leg(ctx, wl, args):
+    """Per-request launches of a locality trace (each process revisits a few
+    buffers) with the per-process FIFO translation cache of `args.fifo_entries`
+    entries and without it: hit rate, throughput and latency."""
+    import torch
+    import paper_1304_3771_amd as dv
+    from workload import gen
+    reqs, pool_bytes = gen.make_locality_trace(wl, args.fifo_ops)
+    pool = torch.zeros(pool_bytes, dtype=torch.uint8, device="cuda")
+    reqs["host"] += np.uint64(pool.data_ptr())
+    res = torch.zeros(len(reqs) * 24, dtype=torch.uint8, device="cuda")
+    base = res.data_ptr()
+    stream = torch.cuda.current_stream()
+    calls = [(ctx.copy_to_guest if int(q["dir"]) == 1 else ctx.copy_from_guest, int(q["asid"]), int(q["gva"]),
+              int(q["host"]), int(q["len"])) for q in reqs]
+    tuned = ctx.get_config()
+    out = {"trace": f"{len(reqs)} operations, 4 hot buffers of 16 B-4 KiB per process hit with p=0.95, "
+                    "else 16 B-16 KiB anywhere in the process's VMAs", "entries": args.fifo_entries}
+    for label, entries in (("cache", args.fifo_entries), ("no_cache", 0)):
+        ctx.set_config(**{**tuned, "fifo_entries": entries})
+        ctx.fifo_flush()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, (f, a, g, h, ln) in enumerate(calls):
+            f(a, g, h, ln, base + 24 * i, stream)
+        ctx.sync(stream)
+        dt = time.perf_counter() - t0
+        ls = min(args.lat_sample, len(calls))
+        lats = np.zeros(ls)
+        for i in range(ls):
+            f, a, g, h, ln = calls[i]
+            t1 = time.perf_counter()
+            f(a, g, h, ln, base + 24 * i, stream)
+            stream.synchronize()
+            lats[i] = (time.perf_counter() - t1) * 1e6
+        d = {"req_per_s": round(len(calls) / dt, 1), "latency_us": {"p50_us": pct(lats, 50), "p99_us": pct(lats, 99)}}
+        if entries:
+            hm = np.array([ctx.fifo_counts(p.asid) for p in wl.procs], np.float64).sum(axis=0)
+            d["hits"], d["misses"] = int(hm[0]), int(hm[1])
+            d["hit_rate"] = round(hm[0] / max(1.0, hm.sum()), 4)
+        out[label] = d
+    ctx.set_config(**tuned)
+    r = res.cpu().numpy().view(dv.RESULT_DTYPE)
+    out["bytes_copied"] = int(r["bytes_done"].sum())
+    log(f"per-request with a {args.fifo_entries}-entry FIFO translation cache: hit rate {out['cache']['hit_rate']}, "
+        f"{out['cache']['req_per_s']:.0f} req/s (without: {out['no_cache']['req_per_s']:.0f}); p50 "
+        f"{out['cache']['latency_us']['p50_us']:.1f} us (without: {out['no_cache']['latency_us']['p50_us']:.1f})")
+    return out
+
+
 def extra_workload(name, args):
     """Another batched workload measured in the same run (its own context):
     tuned launch, timed steps, copy-kernel roofline and counters."""
@@ -618,6 +668,8 @@ def main():
     ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
     ap.add_argument("--plain-sample", type=int, default=20000, help="requests timed on the per-request path")
     ap.add_argument("--lat-sample", type=int, default=2000, help="per-request latencies sampled")
+    ap.add_argument("--fifo-ops", type=int, default=20000, help="operations of the translation-cache trace")
+    ap.add_argument("--fifo-entries", type=int, default=10, help="entries of the per-process FIFO cache")
     ap.add_argument("--xlat-n", type=int, default=16_000_000, help="addresses for the translate-only rate")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -749,6 +801,9 @@ def main():
     log(f"plain: {plain['req_per_s']:.0f} req/s, {plain['gbs']:.2f} GB/s; latency p50 {lat_plain['p50_us']:.1f} "
         f"p99 {lat_plain['p99_us']:.1f} us")
 
+    # ---- the per-request path with the paper's per-process FIFO translation cache
+    fifo = fifo_leg(ctx, wl, args)
+
     # ---- translate-only rate (Mreq/s), READ, no A/D
     rng = np.random.default_rng(7)
     p0 = wl.procs[0]
@@ -810,6 +865,7 @@ def main():
         "translate_mreq_s": round(mreq, 2),
         "batched": {"req_per_s": round(batched_req_s, 1), "latency_us": lat_batched,
                     "latency_clock": "device wall clock, from the start of the submission"},
+        "per_request_fifo": fifo,
         "per_request": {**{k: round(v, 3) for k, v in plain.items()}, "latency_us": lat_plain,
                         "latency_clock": "host, launch to stream sync"},
         "roofline": roof,

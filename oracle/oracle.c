@@ -125,6 +125,16 @@ typedef struct {
     uint64_t cr3;
 } orc_proc;
 
+/* A process's translation cache (see "translation cache" below). */
+#define ORC_FIFO_MAX 64
+typedef struct {
+    uint64_t vpn[ORC_FIFO_MAX];   /* slot i holds virtual page vpn[i]           */
+    uint8_t writable[ORC_FIFO_MAX];
+    uint32_t n;                   /* entries held                               */
+    uint32_t head;                /* slot of the oldest entry                   */
+    uint64_t hits, misses;
+} orc_fifo;
+
 typedef struct {
     orc_vm *vms;
     uint32_t nvm;
@@ -133,6 +143,8 @@ typedef struct {
     uint8_t *pool;
     uint64_t pool_bytes;
     uint64_t n_ad_sets;      /* entries whose A or D bit this oracle turned on */
+    orc_fifo *fifo;          /* per process; NULL while the cache is off        */
+    uint32_t fifo_entries;
 } orc_state;
 
 /* 32-byte request, same field order as the library's descriptor. */
@@ -184,6 +196,7 @@ orc_state *orc_new(uint32_t nvm, uint32_t nproc) {
 
 void orc_free(orc_state *s) {
     if (!s) return;
+    free(s->fifo);
     free(s->vms);
     free(s->procs);
     free(s);
@@ -492,6 +505,79 @@ void orc_translate(orc_state *s, uint32_t asid, const uint64_t *gvas, uint64_t n
     }
 }
 
+/* ---------------------------------------------------- translation cache -- */
+/* Section 4.2: the backend caches the translations it makes, per guest
+ * process, in a FIFO of 10 entries, the way a TLB caches page-table walks.
+ * The cache changes no result (a hit gives the translation a walk would give:
+ * the tables change only in A/D bits during a run); what it adds is the count
+ * of translations served from it.  Readings:
+ *   - an entry is one 4 KiB virtual page of the process, and records whether
+ *     the walk that filled or last refreshed it was a write;
+ *   - every page a copy translates (in order, up to and including its first
+ *     faulting page) is one lookup; it hits when the page is held and, for a
+ *     write into the guest, its entry records a write;
+ *   - a miss walks; if the walk succeeds the page is inserted at the tail,
+ *     evicting the oldest entry when the FIFO is full, or, if the page is
+ *     already held (a write after reads), its entry is marked written in
+ *     place; a hit changes nothing (FIFO, not LRU); a failed walk inserts
+ *     nothing.
+ * orc_fifo_reset turns the cache on with `entries` slots per process (0: off)
+ * and empties it, as a change to the tables must. */
+int orc_fifo_reset(orc_state *s, uint32_t entries) {
+    if (entries > ORC_FIFO_MAX) return -1;
+    free(s->fifo);
+    s->fifo = NULL;
+    s->fifo_entries = entries;
+    if (entries) {
+        s->fifo = (orc_fifo *)calloc(s->nproc ? s->nproc : 1, sizeof(orc_fifo));
+        if (!s->fifo) return -1;
+    }
+    return 0;
+}
+
+void orc_fifo_counts(const orc_state *s, uint32_t asid, uint64_t *hits, uint64_t *misses) {
+    *hits = *misses = 0;
+    if (!s->fifo || asid >= s->nproc) return;
+    *hits = s->fifo[asid].hits;
+    *misses = s->fifo[asid].misses;
+}
+
+/* Slot holding `vpn`, or -1. */
+static int fifo_find(const orc_fifo *f, uint32_t entries, uint64_t vpn) {
+    for (uint32_t k = 0; k < f->n; k++) {
+        uint32_t slot = (f->head + k) % entries;
+        if (f->vpn[slot] == vpn) return (int)slot;
+    }
+    return -1;
+}
+
+/* One lookup; ok: the page's walk succeeded.  Returns 1 on a hit. */
+static int fifo_lookup(orc_state *s, uint32_t asid, uint64_t vpn, int write, int ok) {
+    orc_fifo *f = &s->fifo[asid];
+    const uint32_t cap = s->fifo_entries;
+    int slot = fifo_find(f, cap, vpn);
+    if (slot >= 0 && (!write || f->writable[slot])) {
+        f->hits++;
+        return 1;
+    }
+    f->misses++;
+    if (!ok) return 0;
+    if (slot >= 0) {
+        f->writable[slot] = 1;
+        return 0;
+    }
+    uint32_t tail = (f->head + f->n) % cap;
+    if (f->n == cap) {
+        tail = f->head;  /* the oldest entry leaves */
+        f->head = (f->head + 1) % cap;
+    } else {
+        f->n++;
+    }
+    f->vpn[tail] = vpn;
+    f->writable[tail] = (uint8_t)(write != 0);
+    return 0;
+}
+
 /* ----------------------------------------------------------------- copy -- */
 /* What a copy does besides computing its result. */
 enum {
@@ -530,6 +616,7 @@ static int copy_req(orc_state *s, const orc_req *req, orc_result *res, int move)
         uint64_t hi = page + 4096 < end ? page + 4096 : end;
         walk_t w;
         walk(s, p, lo, to_guest, &w);
+        if (s->fifo) fifo_lookup(s, req->asid, lo >> 12, to_guest, w.code == ORC_OK);
         if (w.code != ORC_OK) {
             res->bytes_done = lo - req->gva;
             res->fault_gva = lo;
@@ -600,8 +687,8 @@ int64_t orc_batch_ad(orc_state *s, const orc_req *reqs, uint64_t n, orc_result *
  * batch precondition the final state equals orc_batch's (move = 1) or
  * orc_batch_ad's (move = 2).  epoch_end: n_epochs ascending exclusive ends,
  * the last == n.  Returns the number of faults, -1 on a pool error, -3 if
- * the epoch ends do not finish at n.  A slice no thread can be started for
- * runs on the calling thread. */
+ * the epoch ends do not finish at n, -4 while the translation cache is on.
+ * A slice no thread can be started for runs on the calling thread. */
 typedef struct {
     orc_state *s;
     const orc_req *reqs;
@@ -619,6 +706,7 @@ static void *run_slice(void *arg) {
 
 int64_t orc_batch_mt(orc_state *s, const orc_req *reqs, uint64_t n, const uint64_t *epoch_end, uint32_t n_epochs,
                      uint32_t nthreads, int move, orc_result *res, orc_fault *faults) {
+    if (s->fifo) return -4;  /* the translation cache is defined in request order only */
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     slice_t t[256];

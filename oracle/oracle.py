@@ -71,6 +71,9 @@ def _load(path: str | None = None):
         lib.orc_batch_ad.restype = ctypes.c_int64
         lib.orc_batch_mt.argtypes = [vp, vp, u64, vp, u32, u32, ctypes.c_int, vp, vp]
         lib.orc_batch_mt.restype = ctypes.c_int64
+        lib.orc_fifo_reset.argtypes = [vp, u32]
+        lib.orc_fifo_reset.restype = ctypes.c_int
+        lib.orc_fifo_counts.argtypes = [vp, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         lib.orc_check_conflicts.argtypes = [vp, vp, u64, vp, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         lib.orc_check_conflicts.restype = ctypes.c_int
         lib.orc_map_pages.argtypes = [vp, u32, vp, u64, vp, u64, vp]
@@ -173,9 +176,22 @@ class Oracle:
         faults = np.zeros(n, FAULT_DTYPE)
         nf = self._lib.orc_batch_mt(self._h, r.ctypes.data, n, e.ctypes.data, len(e), int(threads),
                                     2 if ad_only else 1, res.ctypes.data, faults.ctypes.data)
+        if nf == -4:
+            raise ValueError("the threaded batch is not defined with the translation cache on")
         if nf < 0:
             raise ValueError("request names pool bytes outside the pool")
         return res, faults[:nf].copy()
+
+    def fifo_reset(self, entries: int = 10):
+        """Turn the per-process translation cache on with `entries` slots (0: off) and empty it."""
+        if self._lib.orc_fifo_reset(self._h, entries) != 0:
+            raise ValueError("entries must be <= 64")
+
+    def fifo_counts(self, asid: int):
+        """(hits, misses) of a process's translation cache since the last reset."""
+        h, m = ctypes.c_uint64(), ctypes.c_uint64()
+        self._lib.orc_fifo_counts(self._h, asid, ctypes.byref(h), ctypes.byref(m))
+        return int(h.value), int(m.value)
 
     def batch_results(self, reqs):
         """Results and fault list only (no byte moves, no A/D updates)."""

@@ -93,6 +93,28 @@ struct DEpochCtr {
 };
 static_assert(2 * kQParts == 64, "one counter per lane of a wavefront");
 
+// A process's translation cache on the per-request path (section 4.2: the
+// backend caches translations per guest process in a small FIFO).  Slot i
+// holds virtual page vpn[i] at arena offset hpa[i]; bit i of `written` marks
+// an entry filled or refreshed by a write.  Entries are valid only while
+// `gen` equals the context's translation generation, which every change to
+// guest memory or the translation setup advances (A/D bits a hit relies on
+// may have been cleared).  hits/misses count lookups since the last flush.
+constexpr uint32_t kFifoMax = 16;
+struct DFifo {
+    uint64_t vpn[kFifoMax];
+    uint64_t hpa[kFifoMax];
+    uint32_t written;
+    uint32_t n;
+    uint32_t head;
+    uint32_t pad;
+    uint64_t gen;
+    unsigned long long hits;
+    unsigned long long misses;
+    uint64_t pad2[3];
+};
+static_assert(sizeof(DFifo) == 320, "DFifo layout");
+
 // Device counters gathered while profiling.
 struct DCounters {
     unsigned long long pages_walked;
@@ -133,6 +155,11 @@ struct DBatch {
     uint32_t seg_chunks;
     uint32_t inline_bytes;
     uint32_t nontemporal;
+    // per-request path only: the processes' translation caches (null: off)
+    DFifo *fifo;
+    uint64_t xlat_gen;
+    uint32_t fifo_entries;
+    uint32_t pad1;
 };
 
 // ---- launchers (kernels.hip) ------------------------------------------------

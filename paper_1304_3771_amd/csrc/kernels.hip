@@ -504,6 +504,32 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
     const uint32_t start = incl - nch;
     const uint32_t total = shfl32(incl, 63);
 
+    // ---- per-request path: the process's translation cache, a FIFO whose
+    // slots live in lanes 0..cap-1 (section 4.2).  A page held in it (and,
+    // for a write into the guest, held from a write) is not walked: its
+    // translation comes from the slot, and the bits a walk would set are
+    // already set.  Lookups are replayed in page order after each pass, so
+    // hits, misses and evictions are those of a sequential FIFO.
+    const uint32_t cap = B.fifo_entries;
+    const bool use_fifo = kPlain && B.fifo != nullptr && cap != 0 && total > 0;
+    DFifo *fifo = nullptr;
+    uint64_t fv = ~0ull, fh = 0;
+    uint32_t f_occ = 0, f_wr = 0, f_n = 0, f_head = 0;
+    unsigned long long f_hits = 0, f_miss = 0;
+    if (use_fifo) {
+        fifo = B.fifo + uniform_u32(asid);  // kPlain: lane 0 holds the request
+        if (uniform_u64(*gp<const g_u64>(&fifo->gen)) == B.xlat_gen) {
+            f_n = uniform_u32(*gp<const g_u32>(&fifo->n));
+            f_head = uniform_u32(*gp<const g_u32>(&fifo->head));
+            f_wr = uniform_u32(*gp<const g_u32>(&fifo->written));
+            if ((uint32_t)lane < cap) {
+                fv = gp<const g_u64>(fifo->vpn)[lane];
+                fh = gp<const g_u64>(fifo->hpa)[lane];
+            }
+            for (uint32_t k = 0; k < f_n; ++k) f_occ |= 1u << ((f_head + k) % cap);
+        }
+    }
+
     // per-request (owner lane) state
     uint32_t ff = kNone, fcode = 0, flevel = 0, queued = 0;
     uint64_t flo = 0;
@@ -538,12 +564,27 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         const uint64_t end = j_gva + j_len;
         const uint64_t hi = page + 4096 < end ? page + 4096 : end;
 
-        // ---- heads: first lane of each (request, 2 MiB region) run
+        // pages the translation cache holds (as of the start of this pass) skip the walk
+        bool fhit = false;
+        uint64_t fhpa = 0;
+        if (use_fifo) {
+            for (uint32_t e = 0; e < cap; ++e) {
+                const uint64_t ve = uniform_u64(shfl64(fv, (int)e));
+                const uint64_t he = uniform_u64(shfl64(fh, (int)e));
+                if (work && ((f_occ >> e) & 1u) && ve == (lo >> 12) && (!j_dir || ((f_wr >> e) & 1u))) {
+                    fhit = true;
+                    fhpa = he;
+                }
+            }
+        }
+        const bool walkl = work && !fhit;
+
+        // ---- heads: first lane of each (request, 2 MiB region) run of walking lanes
         const int prev = lane > 0 ? lane - 1 : 0;
-        const uint32_t p_work = shfl32(work ? 1u : 0u, prev);
+        const uint32_t p_work = shfl32(walkl ? 1u : 0u, prev);
         const uint32_t p_j = shfl32((uint32_t)j, prev);
         const uint64_t p_lo = shfl64(lo, prev);
-        const bool head = work && (lane == 0 || !p_work || p_j != (uint32_t)j || (p_lo >> 21) != (lo >> 21));
+        const bool head = walkl && (lane == 0 || !p_work || p_j != (uint32_t)j || (p_lo >> 21) != (lo >> 21));
         const uint64_t head_mask = __ballot(head);
 
         DVm vmv;
@@ -626,10 +667,11 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
             shfl32(rcode | (rlevel << 4) | (rkind << 8) | (ru << 10) | (rw << 11) | (rhas << 12), hsrc);
         const uint64_t r_base = shfl64(rbase, hsrc);
 
-        // ---- leaf step (every working lane)
+        // ---- leaf step (every walking lane)
         uint32_t code = 0, level = 0, shift = 0;
         uint64_t gpa = 0, hpa = 0, leaf_off = 0, leaf_e = 0;
-        if (work) {
+        if (fhit) hpa = fhpa + (lo & 0xFFFull);
+        if (walkl) {
             code = r_packed & 15u;
             level = (r_packed >> 4) & 15u;
             const uint32_t kind = (r_packed >> 8) & 3u;
@@ -683,8 +725,9 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         const uint32_t jfirst = j_start > base ? j_start - base : 0u;  // first lane of request j
         const uint64_t jmask = mask_le(lane) & ~mask_lt((int)jfirst);
         const bool copied = work && code == 0 && (fmask & jmask) == 0;
-        const uint64_t cmask = __ballot(copied);
-        const uint64_t cto_mask = __ballot(copied && j_dir);
+        // (pages served by the translation cache need no A/D: their filling walk set them)
+        const uint64_t cmask = __ballot(copied && !fhit);
+        const uint64_t cto_mask = __ballot(copied && !fhit && j_dir);
 
         // owner lanes pick up their request's first fault in this pass
         {
@@ -707,6 +750,48 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                 fcode = f_code;
                 flevel = f_level;
                 flo = f_lo;
+            }
+        }
+
+        // ---- translation cache: this pass's lookups in page order, up to and
+        // including the request's first faulting page (kPlain: one request)
+        if (use_fifo) {
+            uint64_t lk = __ballot(work);
+            if (fmask) lk &= mask_le(__ffsll((unsigned long long)fmask) - 1);
+            const uint64_t okm = __ballot(work && code == 0);
+            const uint64_t pg = hpa - (lo & 0xFFFull);  // the page's arena offset (lanes that translated)
+            while (lk) {
+                const int jl = __ffsll((unsigned long long)lk) - 1;
+                lk &= lk - 1;
+                const uint64_t v = uniform_u64(shfl64(lo >> 12, jl));
+                const uint64_t hp = uniform_u64(shfl64(pg, jl));
+                const bool wrj = uniform_u32(shfl32(j_dir, jl)) != 0;
+                const uint64_t em = __ballot((uint32_t)lane < cap && ((f_occ >> lane) & 1u) && fv == v);
+                const int slot = em ? __ffsll((unsigned long long)em) - 1 : -1;
+                if (slot >= 0 && (!wrj || ((f_wr >> slot) & 1u))) {
+                    f_hits++;
+                    continue;
+                }
+                f_miss++;
+                if (!((okm >> jl) & 1ull)) continue;  // a failed walk inserts nothing
+                if (slot >= 0) {                      // held from reads: now written
+                    f_wr |= 1u << slot;
+                    continue;
+                }
+                uint32_t tail;
+                if (f_n == cap) {  // full: the oldest entry leaves
+                    tail = f_head;
+                    f_head = (f_head + 1) % cap;
+                } else {
+                    tail = (f_head + f_n) % cap;
+                    f_n++;
+                }
+                if ((uint32_t)lane == tail) {
+                    fv = v;
+                    fh = hp;
+                }
+                f_occ |= 1u << tail;
+                f_wr = (f_wr & ~(1u << tail)) | ((wrj ? 1u : 0u) << tail);
             }
         }
 
@@ -863,6 +948,20 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         if (!kPlain && B.t_done) {
             B.pending[r0 + lane] = queued;
             if (queued == 0) B.t_done[r0 + lane] = now_ns(B);
+        }
+    }
+    if (use_fifo) {
+        if ((uint32_t)lane < cap) {
+            gp<g_u64>(fifo->vpn)[lane] = fv;
+            gp<g_u64>(fifo->hpa)[lane] = fh;
+        }
+        if (lane == 0) {
+            *gp<g_u32>(&fifo->written) = f_wr;
+            *gp<g_u32>(&fifo->n) = f_n;
+            *gp<g_u32>(&fifo->head) = f_head;
+            *gp<g_u64>(&fifo->gen) = B.xlat_gen;
+            *gp<DV_GLOBAL unsigned long long>(&fifo->hits) += f_hits;
+            *gp<DV_GLOBAL unsigned long long>(&fifo->misses) += f_miss;
         }
     }
     return __ballot(spilled) != 0;

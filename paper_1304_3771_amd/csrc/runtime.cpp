@@ -51,6 +51,7 @@ static devirt_config default_config() {
     c.inline_bytes = 0;
     c.use_graph = 1;
     c.overlap = 1;
+    c.fifo_entries = 0;
     return c;
 }
 
@@ -64,6 +65,7 @@ static int check_config(const devirt_config &c) {
     if (c.nontemporal > 1 || c.use_graph > 1) return dv_fail(-EINVAL, "nontemporal/use_graph must be 0 or 1");
     if (c.inline_bytes > 256) return dv_fail(-EINVAL, "inline_bytes must be <= 256");
     if (c.overlap > 1) return dv_fail(-EINVAL, "overlap must be 0 or 1");
+    if (c.fifo_entries > kFifoMax) return dv_fail(-EINVAL, "fifo_entries must be <= %u", kFifoMax);
     return 0;
 }
 
@@ -139,6 +141,7 @@ extern "C" int devirt_close(devirt_ctx *c) {
     }
     hipFree(c->d_vms);
     hipFree(c->d_procs);
+    hipFree(c->d_fifo);
     hipFree(c->d_counters);
     for (auto &p : c->prof) {
         hipEventDestroy(p.a);
@@ -174,6 +177,7 @@ static int upload_vms(devirt_ctx *c) {
     }
     if (!h.empty()) HIPCHK(hipMemcpy(c->d_vms, h.data(), h.size() * sizeof(DVm), hipMemcpyHostToDevice));
     c->tables_version++;
+    c->xlat_gen++;
     return 0;
 }
 
@@ -182,8 +186,18 @@ static int upload_procs(devirt_ctx *c) {
         size_t cap = std::max<size_t>(64, c->procs.size() * 2);
         DProc *p = nullptr;
         HIPCHK(hipMalloc(&p, cap * sizeof(DProc)));
+        DFifo *f = nullptr;
+        if (hipMalloc(&f, cap * sizeof(DFifo)) != hipSuccess) {
+            hipFree(p);
+            return dv_fail(-ENOMEM, "hipMalloc translation caches");
+        }
+        // new processes start with an empty cache and zero counts (gen 0 never matches)
+        HIPCHK(hipMemset(f, 0, cap * sizeof(DFifo)));
+        if (c->d_fifo) HIPCHK(hipMemcpy(f, c->d_fifo, c->d_procs_cap * sizeof(DFifo), hipMemcpyDeviceToDevice));
         hipFree(c->d_procs);
+        hipFree(c->d_fifo);
         c->d_procs = p;
+        c->d_fifo = f;
         c->d_procs_cap = cap;
     }
     if (!c->procs.empty())
@@ -232,9 +246,10 @@ static int vm_copy(devirt_ctx *c, uint32_t vm, uint64_t off, void *host_or_dev, 
     if (off > v.bytes || bytes > v.bytes - off) return dv_fail(-EINVAL, "range leaves the arena");
     if (set_dev(c)) return -EIO;
     HIPCHK(hipDeviceSynchronize());
-    if (write)
+    if (write) {
         HIPCHK(hipMemcpy(v.arena + off, host_or_dev, bytes, hipMemcpyDefault));
-    else
+        c->xlat_gen++;  // the bytes may be page tables (A/D bits a cached translation relies on)
+    } else
         HIPCHK(hipMemcpy(host_or_dev, v.arena + off, bytes, hipMemcpyDefault));
     return 0;
 }
@@ -646,6 +661,7 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
         HIPCHK(hipEventRecord(w->map_ev, s));
     }
     HIPCHK(launch_map(s, a));  // only arena bytes change: captured batch graphs stay valid
+    c->xlat_gen++;             // but cached translations may be stale
     return 0;
 }
 
@@ -695,6 +711,11 @@ static int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host,
     // one request: part 0 spans the whole queue, which holds at least one
     // segment per page, so no run overflows it
     b.part_cap = std::min(w->seg_cap, w->short_cap);
+    if (c->cfg.fifo_entries) {
+        b.fifo = c->d_fifo;
+        b.fifo_entries = c->cfg.fifo_entries;
+        b.xlat_gen = c->xlat_gen;
+    }
     devirt_request rq;
     memset(&rq, 0, sizeof rq);
     rq.gva = gva;
@@ -1056,6 +1077,7 @@ static const CfgField kCfgFields[] = {
     {"inline_bytes", &devirt_config::inline_bytes},
     {"use_graph", &devirt_config::use_graph},
     {"overlap", &devirt_config::overlap},
+    {"fifo_entries", &devirt_config::fifo_entries},
 };
 
 static std::string device_key(devirt_ctx *c) {
@@ -1077,13 +1099,11 @@ static bool parse_tune_line(const std::string &line, const std::string &key, dev
     size_t m = line.find("\"ms\": ", b);
     if (m == std::string::npos) return false;
     *ms = strtod(line.c_str() + m + 6, nullptr);
-    devirt_config k;
-    memset(&k, 0, sizeof k);
+    devirt_config k = default_config();  // a field the line lacks (written before it existed) keeps its default
     for (const CfgField &f : kCfgFields) {
         const std::string name = std::string("\"") + f.name + "\": ";
         size_t p = line.find(name, m);
-        if (p == std::string::npos) return false;
-        k.*(f.field) = (uint32_t)strtoul(line.c_str() + p + name.size(), nullptr, 10);
+        if (p != std::string::npos) k.*(f.field) = (uint32_t)strtoul(line.c_str() + p + name.size(), nullptr, 10);
     }
     if (check_config(k)) return false;
     *cfg = k;
@@ -1147,5 +1167,29 @@ extern "C" int devirt_autotune_cached(devirt_ctx *c, const char *cache_path, con
     if (!f) return dv_fail(-EIO, "cannot append to the tuning cache %s", cache_path);
     const bool ok = fputs(line.c_str(), f) >= 0;
     if (fclose(f) != 0 || !ok) return dv_fail(-EIO, "cannot write the tuning cache %s", cache_path);
+    return 0;
+}
+
+// ------------------------------------------------- translation caches
+extern "C" int devirt_fifo_counts(devirt_ctx *c, uint32_t asid, uint64_t *hits, uint64_t *misses) {
+    if (!c || !hits || !misses) return dv_fail(-EINVAL, "NULL argument");
+    if (asid >= c->procs.size()) return dv_fail(-ENOENT, "no process %u", asid);
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipDeviceSynchronize());
+    DFifo f;
+    HIPCHK(hipMemcpy(&f, c->d_fifo + asid, sizeof f, hipMemcpyDeviceToHost));
+    *hits = f.hits;
+    *misses = f.misses;
+    return 0;
+}
+
+extern "C" int devirt_fifo_flush(devirt_ctx *c) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
+    if (set_dev(c)) return -EIO;
+    HIPCHK(hipDeviceSynchronize());
+    if (c->d_fifo) HIPCHK(hipMemset(c->d_fifo, 0, c->d_procs_cap * sizeof(DFifo)));
+    c->xlat_gen++;
     return 0;
 }

@@ -75,7 +75,9 @@ struct devirt_ctx {
     size_t d_vms_cap = 0;
     dv::DProc *d_procs = nullptr;
     size_t d_procs_cap = 0;
+    dv::DFifo *d_fifo = nullptr;  // per process: the per-request path's translation cache
     uint64_t tables_version = 0;
+    uint64_t xlat_gen = 1;        // advanced by every change to guest memory or translation setup
     devirt_config cfg;
     uint64_t cfg_version = 0;
     std::map<hipStream_t, Workspace *> ws;

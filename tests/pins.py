@@ -637,6 +637,90 @@ def check_invariants(wl, lib_path=None):
     return fails
 
 
+def check_golden_fifo(lib_path=None):
+    """The per-process FIFO translation cache (section 4.2) on a hand-derived
+    sequence of copies in the 4-level golden world: cumulative hits and misses
+    after every copy, as worked out by hand in the golden file."""
+    fails = []
+    for w in golden_worlds():
+        if "fifo" not in w:
+            continue
+        o, arena, pool = build_golden(w, lib_path)
+        o.fifo_reset(w["fifo"]["entries"])
+        for i, st in enumerate(w["fifo"]["steps"]):
+            req = np.zeros(1, REQ_DTYPE)
+            req[0] = (H(st["gva"]), 0, H(st["len"]), 0, st["dir"], (0, 0, 0), 0)
+            o.copy(req[0])
+            got = o.fifo_counts(0)
+            if got != (st["hits"], st["misses"]):
+                fails.append(f"{w['name']} fifo step {i}: (hits, misses) {got}, expected "
+                             f"{(st['hits'], st['misses'])} ({st['why']})")
+                break
+    return fails
+
+
+def check_fifo_properties(wl, lib_path=None, entries=10):
+    """The translation cache changes no result, no arena and no pool byte; its
+    lookups per process are exactly the pages the copies translate (up to and
+    including each first faulting page); a cache as large as every page a
+    process touches misses exactly once per distinct successfully translated
+    page plus once per failed walk and per write to a page first held for
+    reading."""
+    fails = []
+    reqs = wl.requests
+    base = Oracle.from_workload(wl, lib_path=lib_path)
+    br, bf = base.batch(reqs)
+    o = Oracle.from_workload(wl, lib_path=lib_path)
+    o.fifo_reset(entries)
+    r, f = o.batch(reqs)
+    if not (np.array_equal(r, br) and np.array_equal(f, bf)):
+        fails.append("the cache changed results")
+    if not all(np.array_equal(a, b) for a, b in zip(o.arenas, base.arenas)) or not np.array_equal(o.pool, base.pool):
+        fails.append("the cache changed memory")
+    # lookups = pages translated: every page of a request that copied everything,
+    # else the pages up to and including the faulting one
+    g = reqs["gva"].astype(np.uint64)
+    ln = reqs["len"].astype(np.uint64)
+    valid = (r["code"] != CODES["INVALID"]) & (r["code"] != CODES["NONCANONICAL"]) & (ln > 0)
+    last = np.where(r["code"] == 0, g + ln - np.uint64(1), r["fault_gva"].astype(np.uint64))
+    pages = np.where(valid, (last >> np.uint64(12)) - (g >> np.uint64(12)) + np.uint64(1), np.uint64(0))
+    for p in wl.procs:
+        m = reqs["asid"] == p.asid
+        h, mi = o.fifo_counts(p.asid)
+        if h + mi != int(pages[m].sum()):
+            fails.append(f"asid {p.asid}: {h + mi} lookups, {int(pages[m].sum())} pages translated")
+            break
+    # an unbounded cache: misses = first successful translation of each page, each
+    # later write to a page held only for reads, and every failed walk
+    big = Oracle.from_workload(wl, lib_path=lib_path)
+    big.fifo_reset(64)
+    sel = np.nonzero(valid & (pages <= 2))[0][:3000]
+    held = {}
+    exp_miss = {}
+    for i in sel:
+        q = reqs[i]
+        a = int(q["asid"])
+        rr = big.copy(q)
+        first, npg = int(q["gva"]) >> 12, int(pages[i])
+        for k in range(npg):
+            vpn = first + k
+            ok = not (int(rr["code"]) != 0 and k == npg - 1)
+            wr = int(q["dir"]) == 1
+            st = held.setdefault(a, {})
+            hit = vpn in st and (not wr or st[vpn])
+            if not hit:
+                exp_miss[a] = exp_miss.get(a, 0) + 1
+                if ok:
+                    st[vpn] = st.get(vpn, False) or wr
+        if sum(len(v) for v in held.values()) > 60 * len(held):
+            break
+    for a, n in exp_miss.items():
+        if len(held[a]) <= 64 and big.fifo_counts(a)[1] != n:
+            fails.append(f"asid {a}: a 64-entry cache missed {big.fifo_counts(a)[1]} times, expected {n}")
+            break
+    return fails
+
+
 def table_pages(wl, vm):
     """Arena page numbers of every table frame of a VM: its guest page tables
     (through the memslots) and its EPT tables, if it has an EPT."""

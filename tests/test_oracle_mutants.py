@@ -99,6 +99,21 @@ MUTANTS = {
                               "        if (w.code != ORC_OK) {\n            res->bytes_done"),
     "cr3_low_bits_used": ("uint64_t table = p->cr3 & ORC_ADDR_MASK;", "uint64_t table = p->cr3 & ~0x7ull;"),
     "copy_whole_page": ("            memcpy(h, g, hi - lo);", "            memcpy(h, g, hi - lo + (hi - lo < 4096));"),
+    # the per-process FIFO translation cache
+    "fifo_is_lru": ("    if (slot >= 0 && (!write || f->writable[slot])) {\n        f->hits++;\n        return 1;",
+                    "    if (slot >= 0 && (!write || f->writable[slot])) {\n        f->hits++;\n"
+                    "        uint64_t v = f->vpn[slot];\n        uint8_t wr = f->writable[slot];\n"
+                    "        for (uint32_t k = (slot + cap - f->head) % cap; k + 1 < f->n; k++) {\n"
+                    "            f->vpn[(f->head + k) % cap] = f->vpn[(f->head + k + 1) % cap];\n"
+                    "            f->writable[(f->head + k) % cap] = f->writable[(f->head + k + 1) % cap];\n        }\n"
+                    "        f->vpn[(f->head + f->n - 1) % cap] = v;\n        f->writable[(f->head + f->n - 1) % cap] = wr;\n"
+                    "        return 1;"),
+    "fifo_nine_entries": ("    const uint32_t cap = s->fifo_entries;", "    const uint32_t cap = s->fifo_entries - 1;"),
+    "fifo_inserts_failed_walks": ("    f->misses++;\n    if (!ok) return 0;", "    f->misses++;"),
+    "fifo_ignores_write_rights": ("if (slot >= 0 && (!write || f->writable[slot])) {", "if (slot >= 0) {"),
+    "fifo_looks_past_fault": ("        if (s->fifo) fifo_lookup(s, req->asid, lo >> 12, to_guest, w.code == ORC_OK);\n",
+                              "        if (s->fifo) fifo_lookup(s, req->asid, lo >> 12, to_guest, w.code == ORC_OK);\n"
+                              "        if (s->fifo && w.code != ORC_OK && hi < end) fifo_lookup(s, req->asid, hi >> 12, 0, 0);\n"),
 }
 
 _SMALL = {}
@@ -140,6 +155,7 @@ def test_pins_catch_mutant(tmp_path, name):
         lambda: pins.check_ept_faults(_small("ept_faults"), lib),
         lambda: pins.check_ept_map_bad_pool(_small("ept_faults"), lib),
         lambda: pins.check_conflict_plants(lib),
+        lambda: pins.check_golden_fifo(lib),
     ]
     for c in checks:
         if c():

@@ -23,6 +23,15 @@ def test_golden_maps():
     assert pins.check_golden_maps() == []
 
 
+def test_golden_fifo_cache():
+    assert pins.check_golden_fifo() == []
+
+
+@pytest.mark.parametrize("name", ["c1", "mix2m", "multi_vm", "prot", "pae_prot", "ept_faults"])
+def test_fifo_cache_properties(name):
+    assert pins.check_fifo_properties(wl(name)) == []
+
+
 # worlds whose encoded tables are all reachable (no not-present upper entries)
 @pytest.mark.parametrize("name", ["c1", "mix2m", "lvl5", "lvl5_1g", "pae"])
 def test_map_properties(name):

@@ -742,6 +742,53 @@ def _make_requests(rng, sp: Spec, wl: Workload) -> None:
 
 
 # ---------------------------------------------------------------------------
+# locality traces (the per-process translation cache)
+# ---------------------------------------------------------------------------
+def make_locality_trace(wl: Workload, n_ops: int, hot_buffers: int = 4, p_hot: float = 0.95,
+                        max_hot_len: int = 4 * KiB, cold_hi: int = 16 * KiB, seed: int | None = None):
+    """Operations, one at a time per process, that revisit a few buffers: each
+    process owns `hot_buffers` buffers of 16 B - max_hot_len at random places
+    of its VMAs (a driver's command, status and staging buffers); an operation
+    touches one of them with probability p_hot (a random stretch inside it),
+    else a random place of the process's VMAs (log-uniform 16 B - cold_hi).
+    Processes are uniform, directions Bernoulli(0.5); host bytes are unique
+    per operation.  Returns (requests, pool_bytes)."""
+    rng = np.random.default_rng(wl.seed * 11 + 3 if seed is None else seed)
+    bufs = []
+    for p in wl.procs:
+        vm = p.vmas[rng.integers(0, len(p.vmas), hot_buffers)]
+        blen = draw_lengths(rng, "loguniform", 16, max_hot_len, hot_buffers)
+        off = (rng.random(hot_buffers) * (vm[:, 1] - blen).astype(np.float64)).astype(np.uint64)
+        bufs.append(np.stack([vm[:, 0] + off, blen], axis=1))
+    bufs = np.array(bufs, np.uint64)                       # (procs, hot, 2)
+    asid = rng.integers(0, len(wl.procs), n_ops)
+    hot = rng.random(n_ops) < p_hot
+    which = rng.integers(0, hot_buffers, n_ops)
+    b = bufs[asid, which]
+    u = rng.random(n_ops)
+    hlen = np.maximum(1, np.floor(b[:, 1].astype(np.float64) * np.maximum(u, 1e-3))).astype(np.uint64)
+    hoff = (rng.random(n_ops) * (b[:, 1] - hlen + np.uint64(1)).astype(np.float64)).astype(np.uint64)
+    clen = draw_lengths(rng, "loguniform", 16, cold_hi, n_ops)
+    gva = np.zeros(n_ops, np.uint64)
+    length = np.where(hot, hlen, clen).astype(np.uint64)
+    for a, p in enumerate(wl.procs):
+        m = (asid == a) & ~hot
+        if not m.any():
+            continue
+        v = p.vmas[rng.integers(0, len(p.vmas), int(m.sum()))]
+        ln = np.minimum(length[m], v[:, 1])
+        length[m] = ln
+        gva[m] = v[:, 0] + (rng.random(int(m.sum())) * (v[:, 1] - ln + np.uint64(1)).astype(np.float64)).astype(np.uint64)
+    gva[hot] = b[hot, 0] + hoff[hot]
+    host = np.cumsum(length + np.uint64(64)) - length
+    req = np.zeros(n_ops, REQ_DTYPE)
+    req["gva"], req["host"], req["len"] = gva, host, length.astype(np.uint32)
+    req["asid"], req["dir"] = asid.astype(np.uint32), (rng.random(n_ops) < 0.5).astype(np.uint8)
+    pool = int(host[-1] + length[-1]) if n_ops else 0
+    return req, (pool + 4095) & ~4095
+
+
+# ---------------------------------------------------------------------------
 # serving traces
 # ---------------------------------------------------------------------------
 # Operation classes of the device classes the paper devirtualizes (input,
