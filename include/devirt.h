@@ -209,6 +209,21 @@ int devirt_copy_from_guest(devirt_ctx *ctx, uint32_t asid, uint64_t gva, void *d
 int devirt_copy_to_guest(devirt_ctx *ctx, uint32_t asid, uint64_t gva, const void *src_dev, uint64_t len,
                          devirt_result *res_dev, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call the allocator): the same copy as
+ * devirt_copy_from_guest (dir = DEVIRT_FROM_GUEST, host_dev is the
+ * destination) or devirt_copy_to_guest (dir = DEVIRT_TO_GUEST, host_dev is
+ * the source), same results and effects, but its scratch (one request's queue
+ * counters, clock origin and copy-segment queues) lives in a static device
+ * array of about 1 MiB per device, looked up at devirt_open, and the call
+ * allocates nothing.  The request may touch at most 16,384 4 KiB pages
+ * (-EINVAL beyond, nothing done).  Every call on one device shares that
+ * array: calls that overlap on one device (two streams, two contexts) race
+ * and give undefined results; calls ordered on one stream do not.  Not
+ * profiled (no timing events). */
+int devirt_copy_static(devirt_ctx *ctx, uint32_t asid, uint64_t gva, void *host_dev, uint64_t len, uint32_t dir,
+                       devirt_result *res_dev, void *hip_stream);
+
 /* Map guest virtual pages by writing the guest's own page tables: the
  * second kind of routine of the software hybrid address space (section 4.2;
  * insert_pfn and kin), where the backend maps a page into the process

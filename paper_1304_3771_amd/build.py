@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdevirt.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "server.cpp", "static_copy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DEVIRT_ARCH", "gfx950")
 

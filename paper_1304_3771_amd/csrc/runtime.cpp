@@ -108,6 +108,8 @@ extern "C" int devirt_open(int hip_device, devirt_ctx **out) {
     HIPCHK(hipGetDeviceCount(&ndev));
     if (hip_device < 0 || hip_device >= ndev) return dv_fail(-EINVAL, "no HIP device %d (%d present)", hip_device, ndev);
     HIPCHK(hipSetDevice(hip_device));
+    int rc = static_scratch_init(hip_device);
+    if (rc) return rc;
     devirt_ctx *c = new devirt_ctx();
     c->device = hip_device;
     int v = 0;
@@ -447,13 +449,15 @@ int ensure_ws(devirt_ctx *c, Workspace *w, uint64_t n_req, uint64_t n_epochs, bo
 DBatch make_batch(devirt_ctx *c, Workspace *w) {
     DBatch b;
     memset(&b, 0, sizeof b);
-    b.segs = w->segs;
-    b.shorts = w->shorts;
-    b.part_cap = std::min(w->seg_cap, w->short_cap) / kQParts;
-    b.spill = w->spill;
-    b.ctr = w->ctr;
-    b.pending = w->pending;
-    b.t0 = w->t0;
+    if (w) {
+        b.segs = w->segs;
+        b.shorts = w->shorts;
+        b.part_cap = std::min(w->seg_cap, w->short_cap) / kQParts;
+        b.spill = w->spill;
+        b.ctr = w->ctr;
+        b.pending = w->pending;
+        b.t0 = w->t0;
+    }
     b.counters = (c->profiling & DEVIRT_PROF_COUNTERS) ? c->d_counters : nullptr;
     b.ns_num = 1000000ull;
     b.ns_den = c->wall_khz;
@@ -692,8 +696,8 @@ static uint64_t pages_of(uint64_t gva, uint64_t len) {
 
 static const uint64_t kPlainInlinePages = 16;
 
-static int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host, uint64_t len, uint32_t dir,
-                      devirt_result *res, void *stream) {
+int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host, uint64_t len, uint32_t dir,
+               devirt_result *res, void *stream, const StaticScratch *st) {
     if (!c) return dv_fail(-EINVAL, "ctx is NULL");
     if (!res) return dv_fail(-EINVAL, "res_dev is NULL");
     if (len >= (1ull << 32)) return dv_fail(-EINVAL, "len must be < 2^32");
@@ -701,16 +705,30 @@ static int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host,
     if (len && !host) return dv_fail(-EINVAL, "NULL host buffer");
     if (set_dev(c)) return -EIO;
     hipStream_t s = (hipStream_t)stream;
-    Workspace *w = get_ws(c, s);
     const uint64_t pages = pages_of(gva, len);
     const bool inl = pages <= kPlainInlinePages;
-    int rc = ensure_ws(c, w, 1, 1, false, inl ? 0 : pages);
-    if (rc) return rc;
-    DBatch b = make_batch(c, w);
+    int rc;
+    DBatch b;
+    if (st) {
+        // the caller's static scratch: nothing is allocated
+        if (pages > st->cap)
+            return dv_fail(-EINVAL, "the request touches %llu pages; this entry point takes at most %llu",
+                           (unsigned long long)pages, (unsigned long long)st->cap);
+        b = make_batch(c, nullptr);
+        b.segs = st->segs;
+        b.shorts = st->shorts;
+        b.ctr = st->ctr;
+        b.t0 = st->t0;
+        b.part_cap = st->cap;
+    } else {
+        Workspace *w = get_ws(c, s);
+        if ((rc = ensure_ws(c, w, 1, 1, false, inl ? 0 : pages))) return rc;
+        b = make_batch(c, w);
+        // one request: part 0 spans the whole queue, which holds at least one
+        // segment per page, so no run overflows it
+        b.part_cap = std::min(w->seg_cap, w->short_cap);
+    }
     b.res = res;
-    // one request: part 0 spans the whole queue, which holds at least one
-    // segment per page, so no run overflows it
-    b.part_cap = std::min(w->seg_cap, w->short_cap);
     if (c->cfg.fifo_entries) {
         b.fifo = c->d_fifo;
         b.fifo_entries = c->cfg.fifo_entries;
@@ -726,8 +744,8 @@ static int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host,
     c->stats.plain_calls++;
     HIPCHK(launch_plain(s, view_of(c), b, rq, inl ? 1 : 0));
     if (!inl) {
-        ProfEv *pe;
-        if ((rc = prof_begin(c, s, 0, &pe))) return rc;
+        ProfEv *pe = nullptr;
+        if (!st && (rc = prof_begin(c, s, 0, &pe))) return rc;
         HIPCHK(launch_copy(s, grid_for(c, pages, c->cfg.copy_wg, c->cfg.copy_wgs_per_cu), c->cfg.copy_wg, b, 0));
         if ((rc = prof_end(c, s, pe))) return rc;
     }
@@ -736,11 +754,11 @@ static int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host,
 
 extern "C" int devirt_copy_from_guest(devirt_ctx *c, uint32_t asid, uint64_t gva, void *dst, uint64_t len,
                                       devirt_result *res, void *stream) {
-    return plain_copy(c, asid, gva, (uint64_t)(uintptr_t)dst, len, DEVIRT_FROM_GUEST, res, stream);
+    return plain_copy(c, asid, gva, (uint64_t)(uintptr_t)dst, len, DEVIRT_FROM_GUEST, res, stream, nullptr);
 }
 extern "C" int devirt_copy_to_guest(devirt_ctx *c, uint32_t asid, uint64_t gva, const void *src, uint64_t len,
                                     devirt_result *res, void *stream) {
-    return plain_copy(c, asid, gva, (uint64_t)(uintptr_t)src, len, DEVIRT_TO_GUEST, res, stream);
+    return plain_copy(c, asid, gva, (uint64_t)(uintptr_t)src, len, DEVIRT_TO_GUEST, res, stream, nullptr);
 }
 
 // Enqueue one batch on stream `s` using workspace `w` (no capture logic here).

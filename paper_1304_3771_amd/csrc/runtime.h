@@ -100,6 +100,22 @@ struct BatchArgs {
     bool direct = false;  // one translate launch that also copies (small batches)
 };
 
+// Device memory of the per-request copy that allocates nothing: one
+// request's epoch counters, clock origin and segment queues (cap segments
+// each), inside a static device array (static_copy.hip).
+struct StaticScratch {
+    dv::DEpochCtr *ctr;
+    uint64_t *t0;
+    dv::DSeg *segs;
+    dv::DSeg *shorts;
+    uint64_t cap;
+};
+// Looks the array up on `device` (current) once per process; devirt_open calls it.
+int static_scratch_init(int device);
+// The per-request copy; with st, into that scratch instead of the stream's workspace.
+int plain_copy(devirt_ctx *c, uint32_t asid, uint64_t gva, uint64_t host, uint64_t len, uint32_t dir,
+               devirt_result *res, void *stream, const StaticScratch *st);
+
 int dv_fail(int code, const char *fmt, ...);
 dv::DView view_of(const devirt_ctx *c);
 Workspace *get_ws(devirt_ctx *c, hipStream_t s);

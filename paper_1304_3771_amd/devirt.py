@@ -113,6 +113,7 @@ _SIGS = {
     "devirt_translate": ([vp, u32, vp, u64, u32, vp, vp]),
     "devirt_copy_from_guest": ([vp, u32, u64, vp, u64, vp, vp]),
     "devirt_copy_to_guest": ([vp, u32, u64, vp, u64, vp, vp]),
+    "devirt_copy_static": ([vp, u32, u64, vp, u64, u32, vp, vp]),
     "devirt_submit_batch": ([vp, vp, u64, vp, u32, vp, vp, vp, vp, vp]),
     "devirt_map_pages": ([vp, u32, vp, u64, vp, u64, vp, vp, vp]),
     "devirt_sync": ([vp, vp]),
@@ -259,6 +260,11 @@ class Context:
     def copy_to_guest(self, asid: int, gva: int, src, nbytes: int, res, stream=None):
         _check("devirt_copy_to_guest", lib().devirt_copy_to_guest(self._h, asid, gva, _ptr(src), nbytes,
                                                                   _ptr(res), _stream(stream)))
+
+    def copy_static(self, asid: int, gva: int, host, nbytes: int, direction: int, res, stream=None):
+        """The per-request copy with its scratch in a static device array (allocates nothing)."""
+        _check("devirt_copy_static", lib().devirt_copy_static(self._h, asid, gva, _ptr(host), nbytes, direction,
+                                                              _ptr(res), _stream(stream)))
 
     def map_pages(self, asid: int, maps, n: int, pool_gpa, res, n_used, stream=None):
         """maps: device array of MAP_DTYPE records; pool_gpa: host sequence of
