@@ -1106,3 +1106,152 @@ int64_t orc_map_pages(orc_state *s, uint32_t asid, const orc_map *maps, uint64_t
     free(pool_hpa);
     return (int64_t)nt;
 }
+
+/* ------------------------------------------------------- EPT map pages -- */
+/* The other half of the second kind of routine (section 4.2): the backend
+ * creates the mapping in the guest page tables and also in the EPT, which
+ * the hypervisor maintains.  Here the EPT half, batched, for a VM whose
+ * guest-physical space is described by an EPT:
+ *   - map i puts the guest-physical page at gpa (aligned, below 2^48) on the
+ *     arena page at hpa (aligned, inside the arena), with the permissions in
+ *     flags bits 2:0 (R, W, X; not empty, no write without read): leaf =
+ *     hpa | perms | WB memory type (6 << 3); a 4 KiB leaf, replacing whatever
+ *     entry was there; when two maps name one page, the later one wins;
+ *   - anything else (other flag bits included) is NONCANONICAL;
+ *   - every walk runs on the tables as they were before the call.  A present
+ *     1 GiB or 2 MiB leaf on the path fails the map (RESERVED at its level:
+ *     nothing is split); a misconfigured table entry on the path (write
+ *     without read, bits 7:3 set, a table outside the arena) fails it with
+ *     EPT_MISCONFIG at that level;
+ *   - the tables the successful maps lack are created once each, in order of
+ *     level from the top down and ascending index within a level, on the pool
+ *     pages (arena offsets) in order; each is zeroed and linked from its
+ *     parent entry with R, W and X;
+ *   - if the pool is too small nothing is written and every map that would
+ *     have succeeded reports NO_POOL.
+ * Returns the number of pool pages used; -1 if the VM has no EPT or a pool
+ * page is unaligned, outside the arena or repeated. */
+typedef struct {
+    uint64_t gpa, hpa;
+    uint32_t flags, pad;
+} orc_ept_map;
+
+#define ORC_EPT_RWX 7ull
+#define ORC_EPT_WB (6ull << 3)
+
+static uint64_t ept_entry_off(uint64_t table, uint32_t level, uint64_t gpa) {
+    return table + 8 * ((gpa >> (12 + 9 * (level - 1))) & 511);
+}
+
+/* Walk for an EPT map.  On success *missing is the highest level whose entry
+ * is not present (the tables below it are lacking), 0 if the page table
+ * exists. */
+static uint32_t ept_map_walk(const orc_vm *v, uint64_t gpa, uint32_t *level, uint32_t *missing) {
+    uint64_t table = v->ept_root;
+    *missing = 0;
+    for (uint32_t lvl = 4; lvl >= 2; lvl--) {
+        uint64_t e = load64(v->arena + ept_entry_off(table, lvl, gpa));
+        if ((e & 7) == 0) {
+            *missing = lvl;
+            return ORC_OK;
+        }
+        *level = lvl;
+        if ((e & 3u) == 2u) return ORC_EPT_MISCONFIG;          /* write without read */
+        if (lvl <= 3 && (e & 0x80)) return ORC_RESERVED;      /* a large leaf on the path */
+        if (e & 0xF8u) return ORC_EPT_MISCONFIG;               /* bits 7:3 of a table entry */
+        table = e & ORC_ADDR_MASK;
+        if (!in_arena(v, table)) return ORC_EPT_MISCONFIG;     /* a table outside the arena */
+    }
+    *level = 0;
+    return ORC_OK;
+}
+
+/* Arena offset of the existing EPT table at `level` on gpa's path (the path
+ * to it is known to be present). */
+static uint64_t existing_ept_table(const orc_vm *v, uint64_t gpa, uint32_t level) {
+    uint64_t table = v->ept_root;
+    for (uint32_t lvl = 4; lvl > level; lvl--) table = load64(v->arena + ept_entry_off(table, lvl, gpa)) & ORC_ADDR_MASK;
+    return table;
+}
+
+int64_t orc_ept_map_pages(orc_state *s, uint32_t vm, const orc_ept_map *maps, uint64_t n, const uint64_t *pool,
+                          uint64_t n_pool, orc_result *res) {
+    if (vm >= s->nvm || !s->vms[vm].has_ept) return -1;
+    orc_vm *v = &s->vms[vm];
+    for (uint64_t k = 0; k < n_pool; k++) {
+        if ((pool[k] & 0xFFF) || !in_arena(v, pool[k])) return -1;
+        for (uint64_t j = 0; j < k; j++)
+            if (pool[j] == pool[k]) return -1;
+    }
+    /* 1. walk every map on the initial EPT; gather the lacking tables */
+    uint64_t *keys = (uint64_t *)malloc((3 * n + 1) * sizeof(uint64_t));
+    uint64_t nk = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        const orc_ept_map *m = &maps[i];
+        orc_result *r = &res[i];
+        memset(r, 0, sizeof(*r));
+        const uint32_t perms = m->flags & 7u;
+        if ((m->gpa & 0xFFF) || (m->gpa >> 48) || (m->hpa & 0xFFF) || !in_arena(v, m->hpa) || (m->flags & ~7u) ||
+            perms == 0 || (perms & 3u) == 2u) {
+            r->code = ORC_NONCANONICAL;
+            r->fault_gva = m->gpa;
+            continue;
+        }
+        uint32_t level = 0, missing = 0;
+        uint32_t code = ept_map_walk(v, m->gpa, &level, &missing);
+        if (code != ORC_OK) {
+            r->code = code;
+            r->level = (uint16_t)level;
+            r->fault_gva = m->gpa;
+            continue;
+        }
+        r->bytes_done = 4096;
+        for (uint32_t l = missing ? missing - 1 : 0; l >= 1; l--) keys[nk++] = map_key(l, m->gpa);
+    }
+    qsort(keys, nk, sizeof(uint64_t), cmp_u64);
+    uint64_t nt = 0;
+    for (uint64_t k = 0; k < nk; k++)
+        if (nt == 0 || keys[nt - 1] != keys[k]) keys[nt++] = keys[k];
+    if (nt > n_pool) {   /* 2. not enough pool pages: nothing is written */
+        for (uint64_t i = 0; i < n; i++)
+            if (res[i].code == ORC_OK) {
+                res[i].code = (uint32_t)ORC_NO_POOL;   /* would have succeeded */
+                res[i].bytes_done = 0;
+                res[i].fault_gva = maps[i].gpa;
+            }
+        free(keys);
+        return 0;
+    }
+    /* 3. new tables: zeroed, then linked from their parents */
+    for (uint64_t k = 0; k < nt; k++) memset(v->arena + pool[k], 0, 4096);
+    for (uint64_t k = 0; k < nt; k++) {
+        uint32_t l = 8 - (uint32_t)(keys[k] >> 56);
+        uint64_t id = keys[k] & ((1ull << 56) - 1);
+        uint64_t gpa = id << (12 + 9 * l);
+        uint64_t parent_key = map_key(l + 1, gpa), parent;
+        /* the parent is new unless it is the level-4 table */
+        uint64_t *hit = l + 1 < 4 ? (uint64_t *)bsearch(&parent_key, keys, nt, sizeof(uint64_t), cmp_u64) : NULL;
+        parent = hit ? pool[hit - keys] : existing_ept_table(v, gpa, l + 1);
+        store64(v->arena + ept_entry_off(parent, l + 1, gpa), pool[k] | ORC_EPT_RWX);
+    }
+    /* 4. leaves, in index order */
+    for (uint64_t i = 0; i < n; i++) {
+        if (res[i].code != ORC_OK) continue;
+        const orc_ept_map *m = &maps[i];
+        uint64_t key = map_key(1, m->gpa);
+        uint64_t *hit = nt ? (uint64_t *)bsearch(&key, keys, nt, sizeof(uint64_t), cmp_u64) : NULL;
+        uint64_t pt = hit ? pool[hit - keys] : existing_ept_table(v, m->gpa, 1);
+        store64(v->arena + ept_entry_off(pt, 1, m->gpa), m->hpa | (m->flags & 7u) | ORC_EPT_WB);
+    }
+    free(keys);
+    return (int64_t)nt;
+}
+
+/* GPA -> arena offset through VM vm's EPT for an access that needs `need`
+ * (bit 0 read, bit 1 write; 0: any present leaf), read-only: the walk the
+ * copies use, exposed so that the effect of EPT maps can be checked. */
+uint32_t orc_ept_xlat(const orc_state *s, uint32_t vm, uint64_t gpa, uint32_t need, uint64_t *hpa) {
+    if (vm >= s->nvm || !s->vms[vm].has_ept) return ORC_INVALID;
+    *hpa = 0;
+    return ept_walk(&s->vms[vm], gpa, need, hpa, NULL);
+}

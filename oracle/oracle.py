@@ -27,6 +27,7 @@ XLAT_DTYPE = np.dtype([("gpa", "<u8"), ("hpa", "<u8"), ("code", "<u4"), ("level"
                        ("vm", "<u2")])
 SLOT_DTYPE = np.dtype([("gpa", "<u8"), ("bytes", "<u8"), ("arena_off", "<u8")])
 MAP_DTYPE = np.dtype([("gva", "<u8"), ("gpa", "<u8"), ("flags", "<u4"), ("pad", "<u4")])
+EPT_MAP_DTYPE = np.dtype([("gpa", "<u8"), ("hpa", "<u8"), ("flags", "<u4"), ("pad", "<u4")])
 XLAT_WRITE = 1
 XLAT_SET_AD = 2
 
@@ -78,6 +79,10 @@ def _load(path: str | None = None):
         lib.orc_check_conflicts.restype = ctypes.c_int
         lib.orc_map_pages.argtypes = [vp, u32, vp, u64, vp, u64, vp]
         lib.orc_map_pages.restype = ctypes.c_int64
+        lib.orc_ept_map_pages.argtypes = [vp, u32, vp, u64, vp, u64, vp]
+        lib.orc_ept_map_pages.restype = ctypes.c_int64
+        lib.orc_ept_xlat.argtypes = [vp, u32, u64, u32, ctypes.POINTER(u64)]
+        lib.orc_ept_xlat.restype = u32
         _libs[key] = lib
     return _libs[key]
 
@@ -213,6 +218,24 @@ class Oracle:
         if used < 0:
             raise ValueError("a pool frame is unaligned or outside every memslot")
         return res, int(used)
+
+    def ept_map_pages(self, vm: int, maps, pool_off):
+        """Map guest-physical pages by writing VM vm's EPT (see orc_ept_map_pages);
+        returns (per-map results, pool pages used)."""
+        m = np.ascontiguousarray(maps, dtype=EPT_MAP_DTYPE)
+        pool = np.ascontiguousarray(np.asarray(pool_off, np.uint64).reshape(-1))
+        res = np.zeros(len(m), RESULT_DTYPE)
+        used = self._lib.orc_ept_map_pages(self._h, vm, m.ctypes.data, len(m),
+                                           pool.ctypes.data if len(pool) else None, len(pool), res.ctypes.data)
+        if used < 0:
+            raise ValueError("the VM has no EPT, or a pool page is unaligned, outside the arena or repeated")
+        return res, int(used)
+
+    def ept_xlat(self, vm: int, gpa: int, need: int = 0):
+        """(code, arena offset) of gpa through VM vm's EPT; need: bit 0 read, bit 1 write."""
+        h = ctypes.c_uint64()
+        code = self._lib.orc_ept_xlat(self._h, vm, gpa, need, ctypes.byref(h))
+        return int(code), int(h.value)
 
     def check_conflicts(self, reqs, epoch_end=None):
         """Return None if every epoch is conflict-free, else the offending (i, j)."""

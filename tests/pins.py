@@ -760,6 +760,9 @@ def small_specs():
                             ept=True, ept_np=0.03, ept_ro=0.05, ept_mis=0.02),
         "ept_1g": gen.spec("C5", n_vms=1, mem_bytes=3 * GiB // 2, n_slots=1, mapped_frac=0.7,
                            mix=(0.02, 0.02, 0.96), n_requests=200, len_hi=100000, seed=25, ept=True, ept_align=GiB),
+        # long requests (up to 512 pages) over several epochs, for the workgroup walk of large requests
+        "large": gen.spec("C3", n_vms=2, procs_per_vm=2, mem_bytes=64 * MiB, n_requests=400, len_hi=2 * MiB,
+                          seed=32),
         # many epochs (each fills at most 10% of a VMA) that reuse guest and pool bytes across epochs
         "epochs": gen.spec("C3", n_vms=2, procs_per_vm=2, mem_bytes=32 * MiB, n_requests=3000, len_hi=64 * KiB,
                            rho=0.1, seed=31),
@@ -1077,4 +1080,162 @@ def check_conflict_plants(lib_path=None):
         o6 = Oracle([a], [ve.slots], [(0, pe.cr3, pe.levels)], we.pool_image(), lib_path=lib_path,
                     ept=[ve.ept_root])
         check("EPT: write onto the EPT root table", o6, reqs, [1, 2], True)
+    return fails
+
+
+# ------------------------------------------------------------ EPT maps --
+def check_golden_ept_maps(lib_path=None):
+    """The hand-derived EPT map batch on the EPT golden world: per-map results,
+    pool pages used, every entry written, new tables zeroed, no other arena
+    byte changed; with the pool one page short, nothing written."""
+    from oracle.oracle import EPT_MAP_DTYPE
+    fails = []
+    for w in golden_worlds():
+        if "ept_maps" not in w:
+            continue
+        gm = w["ept_maps"]
+        m = np.zeros(len(gm["batch"]), EPT_MAP_DTYPE)
+        for i, b in enumerate(gm["batch"]):
+            m[i] = (H(b["gpa"]), H(b["hpa"]), b["flags"], 0)
+        o, arena, pool = build_golden(w, lib_path)
+        a0 = arena.copy()
+        res, used = o.ept_map_pages(0, m, [H(x) for x in gm["pool"]])
+        if used != gm["used"]:
+            fails.append(f"{w['name']} EPT maps: {used} pool pages used, expected {gm['used']}")
+        for i, b in enumerate(gm["batch"]):
+            got = (int(res[i]["code"]), int(res[i]["level"]), int(res[i]["bytes_done"]))
+            exp = (b["code"], b["level"], 4096 if b["code"] == 0 else 0)
+            if got != exp:
+                fails.append(f"{w['name']} EPT map {i} {b['gpa']}: got {got} expected {exp} ({b['why']})")
+        a_exp = a0.copy()
+        for z in gm["zeroed"]:
+            a_exp[H(z):H(z) + 4096] = 0
+        for e in gm["expect"]:
+            a_exp[H(e["arena_off"]):H(e["arena_off"]) + 8] = np.frombuffer(H(e["value"]).to_bytes(8, "little"), np.uint8)
+        if not np.array_equal(arena, a_exp):
+            bad = np.nonzero(arena != a_exp)[0]
+            fails.append(f"{w['name']} EPT maps: {len(bad)} arena bytes differ, first {hex(int(bad[0]))}")
+        # one pool page short: every map that would succeed reports NO_POOL, nothing is written
+        o, arena, pool = build_golden(w, lib_path)
+        a0 = arena.copy()
+        res, used = o.ept_map_pages(0, m, [H(x) for x in gm["short_pool"]])
+        want = [CODES["NO_POOL"] if b["code"] == 0 else b["code"] for b in gm["batch"]]
+        if used != 0 or list(res["code"]) != want or not np.array_equal(arena, a0):
+            fails.append(f"{w['name']} EPT maps, short pool: used {used}, codes {list(res['code'])}")
+    return fails
+
+
+def ept_map_batch(wl, vm, n, rng):
+    """A mixed EPT map batch for a generated EPT world: GPAs inside the mapped
+    guest memory (existing 4 KiB leaves and 2 MiB / 1 GiB regions), GPAs in
+    unmapped space far above it (new tables at every level), repeats, and a
+    few invalid maps; targets are random arena pages; the pool is arena pages
+    no EPT or guest table uses."""
+    from oracle.oracle import EPT_MAP_DTYPE
+    v = wl.vms[vm]
+    pages = v.arena_bytes >> 12
+    inside = rng.integers(0, v.mem_bytes >> 12, n).astype(np.uint64) << np.uint64(12)
+    far = (np.uint64(1) << np.uint64(40)) + (rng.integers(0, 1 << 20, n).astype(np.uint64) << np.uint64(12))
+    gpa = np.where(rng.random(n) < 0.5, inside, far)
+    gpa[n // 3: n // 3 + n // 10] = gpa[:n // 10]                        # repeats: the later map wins
+    m = np.zeros(n, EPT_MAP_DTYPE)
+    m["gpa"] = gpa
+    m["hpa"] = rng.integers(0, pages, n).astype(np.uint64) << np.uint64(12)
+    m["flags"] = rng.choice(np.array([1, 3, 5, 7], np.uint32), n)
+    m["flags"][n - 4] = 2                                                  # write without read
+    m["hpa"][n - 3] = np.uint64(v.arena_bytes)                             # outside the arena
+    m["gpa"][n - 2] |= np.uint64(8)                                        # unaligned
+    m["gpa"][n - 1] = np.uint64(1) << np.uint64(48)                        # past the EPT's reach
+    used = set(int(x) >> 12 for x in v.ept_off)
+    used.update(int(x) >> 12 for x in gen.gpa_to_arena(v.slots, v.pt_gfn << np.uint64(12)))
+    cand = np.setdiff1d(np.arange(pages, dtype=np.int64), np.fromiter(used, np.int64))
+    pool = rng.choice(cand, min(len(cand), 4 * n), replace=False).astype(np.uint64) << np.uint64(12)
+    return m, pool
+
+
+def check_ept_map_properties(wl, lib_path=None, n=400, seed=5):
+    """On a generated EPT world: each map's outcome and the number of new
+    tables follow from the generator's EPT leaf list without a walk; after the
+    batch, the oracle's EPT walker takes every mapped GPA to its target page
+    with the map's rights and every other sampled GPA where it went before; a
+    pool one page short writes nothing."""
+    from oracle.oracle import CODES as OC
+    fails = []
+    rng = np.random.default_rng(seed)
+    vm = 0
+    v = wl.vms[vm]
+    m, pool = ept_map_batch(wl, vm, n, rng)
+    from workload.gen import EPT_LEAF_MIS, EPT_LEAF_NP
+    lf = v.ept_leaf
+    g = lf["gpa"].astype(np.uint64)
+    sh = lf["shift"].astype(np.uint64)
+    kind = lf["kind"]
+    # large leaves that are present (a not-present one is a missing entry);
+    # a misconfigured one may be write-without-read (EPT_MISCONFIG) or of a
+    # reserved memory type (a large leaf: RESERVED), which the list does not tell
+    big1 = {a >> 30: k for a, k in ((int(x), int(k)) for x, s2, k in zip(g, sh, kind)
+                                     if s2 == 30 and k != EPT_LEAF_NP)}
+    big2 = {a >> 21: k for a, k in ((int(x), int(k)) for x, s2, k in zip(g, sh, kind)
+                                     if s2 == 21 and k != EPT_LEAF_NP)}
+    pts = set(int(x) >> 21 for x, s2 in zip(g, sh) if s2 == 12)
+    pds = set(int(x) >> 30 for x, s2 in zip(g, sh) if s2 <= 21)
+    pdpts = set(int(x) >> 39 for x in g)
+    need = set()
+    allowed = []   # per map: the codes the leaf list allows, and the level
+    for i, (a, h, f) in enumerate(zip(m["gpa"], m["hpa"], m["flags"])):
+        a, h, f = int(a), int(h), int(f)
+        if a & 0xFFF or a >> 48 or h & 0xFFF or h + 4096 > v.arena_bytes or f & ~7 or f == 0 or f & 3 == 2:
+            allowed.append(({OC["NONCANONICAL"]}, 0))
+        elif a >> 30 in big1:
+            mis = big1[a >> 30] == EPT_LEAF_MIS
+            allowed.append(({OC["RESERVED"], OC["EPT_MISCONFIG"]} if mis else {OC["RESERVED"]}, 3))
+        elif a >> 21 in big2:
+            mis = big2[a >> 21] == EPT_LEAF_MIS
+            allowed.append(({OC["RESERVED"], OC["EPT_MISCONFIG"]} if mis else {OC["RESERVED"]}, 2))
+        else:
+            allowed.append(({0}, 0))
+            if a >> 39 not in pdpts:
+                need.add((3, a >> 39))
+            if a >> 30 not in pds:
+                need.add((2, a >> 30))
+            if a >> 21 not in pts:
+                need.add((1, a >> 21))
+    exp_code = np.array([0 if c == {0} else -1 for c, _ in allowed])
+    o = Oracle.from_workload(wl, lib_path=lib_path)
+    sample = np.concatenate([rng.integers(0, v.mem_bytes >> 12, 2000).astype(np.uint64) << np.uint64(12),
+                             m["gpa"][exp_code == 0]])
+    sample = np.setdiff1d(sample, m["gpa"])
+    x0 = [o.ept_xlat(vm, int(a), 0) for a in sample]
+    res, used = o.ept_map_pages(vm, m, pool)
+    bad = [i for i, (c, lv) in enumerate(allowed) if int(res["code"][i]) not in c or int(res["level"][i]) != lv]
+    if bad:
+        fails.append(f"EPT maps: {len(bad)} results differ from the leaf list, first map {bad[0]}: "
+                     f"{res[bad[0]]} vs codes {allowed[bad[0]]}")
+    if used != len(need):
+        fails.append(f"EPT maps: {used} new tables, {len(need)} needed by the leaf list")
+    last = {}
+    for i in range(n):
+        if exp_code[i] == 0:
+            last[int(m["gpa"][i])] = i
+    for a, i in last.items():
+        f = int(m["flags"][i])
+        for need_bits, ok in ((1, f & 1), (2, f & 2)):
+            code, hpa = o.ept_xlat(vm, a, need_bits)
+            if ok and (code != 0 or hpa != int(m["hpa"][i])):
+                fails.append(f"EPT maps: GPA {a:#x} -> {code}, {hpa:#x}; expected {int(m['hpa'][i]):#x}")
+                break
+            if not ok and code != OC["EPT_VIOLATION"]:
+                fails.append(f"EPT maps: GPA {a:#x} without right {need_bits} gave code {code}")
+                break
+    x1 = [o.ept_xlat(vm, int(a), 0) for a in sample]
+    if x0 != x1:
+        k = next(j for j in range(len(x0)) if x0[j] != x1[j])
+        fails.append(f"EPT maps: GPA {int(sample[k]):#x} outside the batch moved: {x0[k]} -> {x1[k]}")
+    # one pool page short: nothing written
+    o2 = Oracle.from_workload(wl, lib_path=lib_path)
+    a0 = o2.arenas[vm].copy()
+    res2, used2 = o2.ept_map_pages(vm, m, pool[:max(0, len(need) - 1)])
+    want = np.where(res["code"] == 0, OC["NO_POOL"], res["code"])
+    if len(need) and (used2 != 0 or list(res2["code"]) != list(want) or not np.array_equal(o2.arenas[vm], a0)):
+        fails.append("EPT maps: a pool one page short wrote something")
     return fails

@@ -114,6 +114,18 @@ MUTANTS = {
     "fifo_looks_past_fault": ("        if (s->fifo) fifo_lookup(s, req->asid, lo >> 12, to_guest, w.code == ORC_OK);\n",
                               "        if (s->fifo) fifo_lookup(s, req->asid, lo >> 12, to_guest, w.code == ORC_OK);\n"
                               "        if (s->fifo && w.code != ORC_OK && hi < end) fifo_lookup(s, req->asid, hi >> 12, 0, 0);\n"),
+    # mapping pages in the EPT (the other half of the mapping routine)
+    "ept_map_link_rw_only": ("parent, l + 1, gpa), pool[k] | ORC_EPT_RWX);", "parent, l + 1, gpa), pool[k] | 3ull);"),
+    "ept_map_leaf_no_memtype": ("m->hpa | (m->flags & 7u) | ORC_EPT_WB);", "m->hpa | (m->flags & 7u));"),
+    "ept_map_earlier_wins": ("    /* 4. leaves, in index order */\n    for (uint64_t i = 0; i < n; i++) {\n"
+                             "        if (res[i].code != ORC_OK) continue;\n        const orc_ept_map *m",
+                             "    /* 4. leaves, in index order */\n    for (uint64_t i = n; i-- > 0;) {\n"
+                             "        if (res[i].code != ORC_OK) continue;\n        const orc_ept_map *m"),
+    "ept_map_large_leaf_split": ("        if (lvl <= 3 && (e & 0x80)) return ORC_RESERVED;      /* a large leaf on the path */\n",
+                                 "        if (lvl <= 3 && (e & 0x80)) { *missing = lvl; return ORC_OK; }\n"),
+    "ept_map_write_only_ok": ("perms == 0 || (perms & 3u) == 2u) {", "perms == 0) {"),
+    "ept_map_short_pool_unreported": ("    if (nt > n_pool) {   /* 2. not enough pool pages: nothing is written */",
+                                      "    if (nt > n_pool + 1) {   /* 2. not enough pool pages: nothing is written */"),
 }
 
 _SMALL = {}
@@ -156,6 +168,8 @@ def test_pins_catch_mutant(tmp_path, name):
         lambda: pins.check_ept_map_bad_pool(_small("ept_faults"), lib),
         lambda: pins.check_conflict_plants(lib),
         lambda: pins.check_golden_fifo(lib),
+        lambda: pins.check_golden_ept_maps(lib),
+        lambda: pins.check_ept_map_properties(_small("ept_faults"), lib),
     ]
     for c in checks:
         if c():

@@ -23,6 +23,15 @@ def test_golden_maps():
     assert pins.check_golden_maps() == []
 
 
+def test_golden_ept_maps():
+    assert pins.check_golden_ept_maps() == []
+
+
+@pytest.mark.parametrize("name", ["ept", "ept_faults", "ept_lvl5", "ept_pae", "ept_1g"])
+def test_ept_map_properties(name):
+    assert pins.check_ept_map_properties(wl(name)) == []
+
+
 def test_golden_fifo_cache():
     assert pins.check_golden_fifo() == []
 
