@@ -266,6 +266,46 @@ int devirt_map_pages(devirt_ctx *ctx, uint32_t asid, const devirt_map *maps_dev,
                      const uint64_t *pool_gpa_host, uint64_t n_pool, devirt_result *res_dev, uint64_t *n_used_dev,
                      void *hip_stream);
 
+/* The other half of mapping a page (section 4.2: the backend creates the
+ * mapping in the guest page tables and also in the EPT, which the hypervisor
+ * maintains): map guest-physical pages of VM `vm`, which must have an EPT
+ * (devirt_vm_set_ept), by writing that EPT.
+ *
+ * maps_dev: n devirt_ept_map (n <= 2^19).  Map i puts the guest-physical
+ * page at gpa (4 KiB-aligned, below 2^48) on the arena page at hpa (4 KiB-
+ * aligned, inside the arena) with the rights in flags bits 2:0 (bit 0 read,
+ * 1 write, 2 execute; not empty, no write without read, no other bit): a
+ * 4 KiB EPT leaf = hpa | rights | memory type WB (6 << 3), replacing whatever
+ * entry was there.  When two maps name one page, the later one wins.  Every
+ * walk sees the EPT as it was before the call.  Per map, res_dev (n
+ * devirt_result): OK with bytes_done = 4096; NONCANONICAL (bad gpa, hpa or
+ * rights); RESERVED (a present 2 MiB / 1 GiB EPT leaf on the path: nothing is
+ * split; `level` names it); EPT_MISCONFIG (a misconfigured EPT table entry on
+ * the path, or a table outside the arena); NO_POOL.  fault_gva holds gpa for
+ * a map that fails.
+ * New EPT tables: each table the successful maps need and the EPT lacks is
+ * created once, in order of level from the top down and ascending index
+ * within a level, on pool_host[0], [1], ... (arena offsets): zeroed, then
+ * linked from its parent entry with read, write and execute.  If n_pool is
+ * too small, nothing is written and every map that would have succeeded
+ * reports NO_POOL.  *n_used_dev (device) receives the pool pages used.
+ * -EINVAL (nothing done): no such VM, a VM without an EPT, more than 2^19
+ * maps, a pool page unaligned, outside the arena or repeated.  The pool pages
+ * must not hold anything the guest or the EPT still uses (not checked).
+ * Stream-ordered; the per-process translation caches are emptied. */
+typedef struct {
+    uint64_t gpa;
+    uint64_t hpa;
+    uint32_t flags; /* DEVIRT_EPT_R | DEVIRT_EPT_W | DEVIRT_EPT_X */
+    uint32_t pad;
+} devirt_ept_map;
+#define DEVIRT_EPT_R 1u
+#define DEVIRT_EPT_W 2u
+#define DEVIRT_EPT_X 4u
+int devirt_ept_map_pages(devirt_ctx *ctx, uint32_t vm, const devirt_ept_map *maps_dev, uint64_t n,
+                         const uint64_t *pool_host, uint64_t n_pool, devirt_result *res_dev, uint64_t *n_used_dev,
+                         void *hip_stream);
+
 /* Many operations from many guests in one submission.  The paper forwards
  * one operation, a handful of scalar arguments, per hypercall (section 6.1),
  * and with dual threads the operations of different guest threads proceed
@@ -313,6 +353,10 @@ typedef struct {
     uint32_t fifo_entries;    /* per-request path: entries of each process's FIFO
                                  translation cache (section 4.2 uses 10), 0..16;
                                  0 = no cache (see devirt_fifo_counts)             */
+    uint32_t large_pages;     /* batched path: a request of more pages than this is
+                                 walked by the 4 wavefronts of a workgroup
+                                 together; 0 (the default) = every request by
+                                 one wavefront; else >= 64                         */
 } devirt_config;
 
 int devirt_get_config(devirt_ctx *ctx, devirt_config *cfg);
@@ -386,6 +430,7 @@ typedef struct {
                                 queue while an earlier epoch was being copied:
                                 translated again and copied after that epoch's
                                 copy (the spill pass)                              */
+    uint64_t large_requests; /* requests walked by a workgroup (large_pages)      */
 } devirt_stats;
 
 /* Profiling flags.  While any is set, data-path calls run without graphs.

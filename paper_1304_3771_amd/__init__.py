@@ -6,6 +6,10 @@ include/devirt.h); this package only marshals arguments to it.
 from .devirt import (  # noqa: F401
     CODES,
     COMPLETION_DTYPE,
+    EPT_MAP_DTYPE,
+    EPT_R,
+    EPT_W,
+    EPT_X,
     FAULT_DTYPE,
     FROM_GUEST,
     MAP_DTYPE,

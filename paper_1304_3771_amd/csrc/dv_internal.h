@@ -37,9 +37,10 @@ struct DVm {
     uint32_t index_len;
     uint32_t nslots;
     uint32_t index_complete;
-    uint32_t pad;
+    uint32_t lds_base;  // kernels: this VM's first slot in the workgroup's LDS copy (kLdsNone: use HBM)
     uint64_t ept_root;  // arena offset of the EPT's level-4 table; kNoEpt: memslots translate
 };
+constexpr uint32_t kLdsNone = 0xFFFFFFFFu;
 constexpr uint64_t kNoEpt = ~0ull;
 
 struct DProc {
@@ -53,6 +54,8 @@ struct DView {
     const DProc *procs;
     uint32_t nvm;
     uint32_t nproc;
+    uint32_t lds;  // kernels: the VMs' memslots are in the workgroup's LDS (set by the kernel)
+    uint32_t pad;
 };
 
 // One queued copy segment (32 B): a run of pages of one request whose guest
@@ -90,7 +93,11 @@ struct DEpochCtr {
     uint32_t q[2 * kQParts][kLineWords];
     uint32_t spill_n;  // groups on the epoch's spill list
     uint32_t pad2[kLineWords - 1];
+    uint32_t large_n;  // requests on the epoch's large list
+    uint32_t pad3[kLineWords - 1];
 };
+// A spill-list entry naming one (large) request rather than a group.
+constexpr uint64_t kSpillOne = 1ull << 63;
 static_assert(2 * kQParts == 64, "one counter per lane of a wavefront");
 
 // A process's translation cache on the per-request path (section 4.2: the
@@ -124,6 +131,7 @@ struct DCounters {
     unsigned long long inline_segments;
     unsigned long long ad_atomics;
     unsigned long long spilled_groups;
+    unsigned long long large_requests;
 };
 
 // Everything one batch launch needs besides the view.
@@ -145,7 +153,11 @@ struct DBatch {
     // all of their runs.  Without spill_mode the wavefront copies them itself.
     uint64_t *spill;
     uint32_t spill_mode;
-    uint32_t pad0;
+    // Requests of more than large_pages pages (0: none) are walked by a
+    // workgroup in k_translate_large; k_translate_groups lists them in slots
+    // [r0, r1) of `large` (the epoch's requests).
+    uint32_t large_pages;
+    uint64_t *large;
     DEpochCtr *ctr;           // per epoch
     DCounters *counters;      // null unless profiling
     uint64_t *t0;             // device wall clock at batch start
@@ -166,6 +178,8 @@ struct DBatch {
 hipError_t launch_reset(hipStream_t s, DBatch b, uint32_t n_epochs);
 hipError_t launch_translate_groups(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0,
                                    uint64_t r1, uint32_t epoch, int direct);
+hipError_t launch_translate_large(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0,
+                                  uint32_t epoch);
 hipError_t launch_copy(hipStream_t s, int grid, int block, DBatch b, uint32_t epoch);
 hipError_t launch_spill(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0, uint64_t r1,
                         uint32_t epoch);
@@ -193,6 +207,11 @@ struct MapArgs {
     const uint64_t *pool_gpa;             // device, n_pool
     uint64_t *pool_hpa;                   // device, n_pool: from the host, or (ept_pool) from k_map_pool
     int ept_pool;                         // the VM has an EPT: pool frames are translated on the device
+    // EPT maps (devirt_ept_map_pages): the maps name guest-physical pages of
+    // VM `vm` and the arena pages behind them, and the writes go to its EPT;
+    // the pool holds arena offsets (pool_gpa == pool_hpa)
+    int ept_map;
+    uint32_t vm;
     // the tables the batch lacks: a hash set of their keys (tset_log2 slots),
     // the distinct keys in insertion order (m = min(4n, n_pool) slots), sorted
     uint64_t *tset;

@@ -109,9 +109,86 @@ __device__ __forceinline__ uint64_t now_ns(const DBatch &b) {
 }
 
 // ------------------------------------------------------------------ memslots
+// The translate kernels keep a copy of every VM's sorted memslots in LDS when
+// they fit (at most kLdsVms VMs, kLdsSlots slots in all: 12 KiB).  A walk looks
+// a memslot up for every table it reads and for the data page; from LDS that
+// is a few LDS reads instead of a dependent load of the 2 MiB index.
+constexpr uint32_t kLdsSlots = 512;
+constexpr uint32_t kLdsVms = 64;
+__shared__ DSlot g_lds_slot[kLdsSlots];
+__shared__ uint32_t g_lds_off[kLdsVms + 1];
+
+// Fills the workgroup's copy with VM `one`'s slots only (at LDS slot 0);
+// entered by every thread.  Returns (uniformly) whether they are in LDS.
+__device__ bool lds_slots_load_one(const DView &V, uint32_t one) {
+    if (one >= V.nvm) return false;
+    typedef DV_GLOBAL DVm g_vm;
+    typedef DV_GLOBAL DSlot g_slot;
+    const g_vm *vm = gp<const g_vm>(V.vms) + one;
+    const uint32_t ns = vm->nslots;
+    if (ns > kLdsSlots || one > kLdsVms) return false;
+    if (threadIdx.x == 0) g_lds_off[one] = 0;
+    for (uint32_t t = threadIdx.x; t < ns; t += blockDim.x) g_lds_slot[t] = gp<const g_slot>(vm->slots)[t];
+    __syncthreads();
+    return true;
+}
+
+// Fills the workgroup's copy; entered by every thread.  Returns (uniformly)
+// whether the slots are in LDS.
+__device__ bool lds_slots_load(const DView &V) {
+    if (V.nvm > kLdsVms) return false;
+    typedef DV_GLOBAL DVm g_vm;
+    typedef DV_GLOBAL DSlot g_slot;
+    const g_vm *vms = gp<const g_vm>(V.vms);
+    if (threadIdx.x < 64) {  // one wavefront: exclusive prefix sum of the slot counts
+        const uint32_t lane = threadIdx.x;
+        const uint32_t cnt = lane < V.nvm ? vms[lane].nslots : 0u;
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = (uint32_t)__shfl((int)incl, lane >= (uint32_t)d ? (int)lane - d : (int)lane);
+            if (lane >= (uint32_t)d) incl += t;
+        }
+        if (lane < V.nvm) g_lds_off[lane] = incl - cnt;
+        if (lane == V.nvm - 1) g_lds_off[V.nvm] = incl;
+        if (V.nvm == 0 && lane == 0) g_lds_off[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t total = g_lds_off[V.nvm];
+    if (total > kLdsSlots) return false;
+    for (uint32_t t = threadIdx.x; t < total; t += blockDim.x) {
+        uint32_t vm = 0;
+        while (vm + 1 < V.nvm && g_lds_off[vm + 1] <= t) ++vm;
+        g_lds_slot[t] = gp<const g_slot>(vms[vm].slots)[t - g_lds_off[vm]];
+    }
+    __syncthreads();
+    return true;
+}
+
+// A VM's table entry as a translate kernel uses it (lds: its slots are in LDS).
+__device__ __forceinline__ DVm load_vm(const DView &V, uint32_t vm, bool lds) {
+    DVm v = gp<const DV_GLOBAL DVm>(V.vms)[vm];
+    v.lds_base = lds ? g_lds_off[vm] : kLdsNone;
+    return v;
+}
+
 // GPA -> arena offset (section 4.2: the guest-physical address is turned into
 // the host address backing it, as KVM does with its memslots).
 __device__ __forceinline__ bool slot_lookup(const DVm &v, uint64_t gpa, uint64_t &hpa) {
+    if (v.lds_base != kLdsNone) {  // binary search of the LDS copy
+        const DSlot *sl = g_lds_slot + v.lds_base;
+        uint32_t lo = 0, hi = v.nslots;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (sl[mid].gpa <= gpa)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo == 0 || gpa >= sl[lo - 1].end) return false;
+        hpa = sl[lo - 1].arena_off + (gpa - sl[lo - 1].gpa);
+        return true;
+    }
     uint64_t blk = gpa >> 21;
     if (blk < v.index_len) {
         uint64_t e = gp<const g_u64>(v.index)[blk];
@@ -446,14 +523,43 @@ struct GroupOut {
     unsigned long long pages, hits, misses, segs, inl, atomics, spills;
 };
 
+// Requests of more than B.large_pages pages ("large"): in the batched path a
+// group leaves them to k_translate_large, where the wavefronts of a workgroup
+// walk one large request together.
+enum : uint32_t {
+    kLargeKeep = 0,   // walk them here
+    kLargeDefer = 1,  // put them on the epoch's large list; their results come later
+    kLargeSkip = 2,   // leave them alone (spill pass: a large request spills on its own)
+};
+
+// Workgroup-shared state of a large request walked by several wavefronts.
+struct CoopShared {
+    uint32_t ff[3];   // per round, rotating: the request's first faulting page (kNone: none)
+    uint32_t fcode, flevel;
+    uint64_t flo;     // that page's first byte in the request
+    uint32_t queued;  // segments queued
+    uint32_t spilled;
+};
+
 // Returns (wave-uniformly) true when some run of the group found its queue
 // part full while B.spill_mode is set: such runs are neither queued nor
 // copied, and the caller puts the group on the epoch's spill list.
-template <bool kPlain>
+//
+// kCoop: the wavefronts of a workgroup walk one large request (gn = 1)
+// together, round by round: in each round wavefront w takes pages
+// [64 w, 64 w + 64) of the round's 64 W.  The walk of a round has no side
+// effects; the request's first faulting page is then agreed in LDS (cs), and
+// only pages before it get A/D bits and copies, as in the one-wavefront walk.
+// All wavefronts run the same rounds (barriers inside); the result is written
+// by wavefront 0.  e0: the epoch's first request (slot of the large list).
+template <bool kPlain, bool kCoop>
 __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint32_t gn,
                               const devirt_request &preq, uint32_t epoch, CEnt *cache, uint32_t *owner,
-                              bool coop_all, DEpochCtr *ctr, GroupOut &st) {
+                              bool coop_all, uint32_t large_mode, uint64_t e0, DEpochCtr *ctr, GroupOut &st,
+                              CoopShared *cs) {
     const int lane = lane_id();
+    const uint32_t nw = kCoop ? (blockDim.x >> 6) : 1u;    // wavefronts walking the request
+    const uint32_t wv = kCoop ? (threadIdx.x >> 6) : 0u;   // this one
     // this wavefront's part of the segment queues
     const uint32_t qpart = kPlain ? 0u : (uint32_t)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kQParts);
     const uint64_t pcap = B.part_cap;
@@ -492,6 +598,21 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
                 else
                     nch = (uint32_t)(((gva + len - 1) >> 12) - (gva >> 12) + 1);
             }
+        }
+    }
+    // large requests left to k_translate_large (or to their own spill entry)
+    bool large = false;
+    if (!kPlain && !kCoop && large_mode != kLargeKeep && B.large_pages && nch > B.large_pages) {
+        large = true;
+        nch = 0;
+    }
+    if (!kPlain && !kCoop && large_mode == kLargeDefer) {
+        const uint64_t lm = __ballot(large);
+        if (lm) {
+            uint32_t lb = 0;
+            if (lane == 0) lb = atomicAdd(&ctr[epoch].large_n, (uint32_t)__popcll(lm));
+            lb = shfl32(lb, 0);
+            if (large) gp<g_u64>(B.large)[e0 + lb + (uint32_t)__popcll(lm & mask_lt(lane))] = r0 + (uint64_t)lane;
         }
     }
     // ---- wave exclusive prefix sum of page counts
@@ -535,9 +656,15 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
     uint64_t flo = 0;
     bool spilled = false;
 
-    for (uint32_t base = 0; base < total; base += 64) {
+    // kCoop: round r is walked by min(nw, 2^r) wavefronts, so that a request
+    // faulting early is walked little past its fault (as by one wavefront),
+    // and one that keeps going soon has every wavefront on it
+    uint32_t round = 0, nr = 1;
+    for (uint32_t rb = 0; rb < total; rb += 64 * nr, ++round) {
+        nr = kCoop ? (round < 5 && (1u << round) < nw ? (1u << round) : nw) : 1u;  // wavefronts this round
+        const uint32_t base = rb + 64 * wv;
         const uint32_t c = base + (uint32_t)lane;
-        const bool active = c < total;
+        const bool active = wv < nr && c < total;
         // owner of page c: the last request whose start <= c
         int j = 0;
 #pragma unroll
@@ -554,7 +681,7 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         const uint32_t j_meta = shfl32(dir | (levels << 1) | (vm << 4), j);
         const uint32_t j_asid = shfl32(asid, j);
         const uint32_t j_start = shfl32(start, j);
-        const uint32_t j_ff = shfl32(ff, j);
+        const uint32_t j_ff = kCoop ? kNone : shfl32(ff, j);  // kCoop: rounds end at the first fault
         const uint32_t j_dir = j_meta & 1u, j_levels = (j_meta >> 1) & 7u, j_vm = j_meta >> 4;
         const bool work = active && j_ff == kNone;
 
@@ -588,7 +715,7 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         const uint64_t head_mask = __ballot(head);
 
         DVm vmv;
-        if (work) vmv = gp<const DV_GLOBAL DVm>(V.vms)[j_vm];
+        if (work) vmv = load_vm(V, j_vm, V.lds != 0);
         // upper levels through the cache (heads only)
         CEnt ce;
         ce.info = 0;
@@ -724,13 +851,26 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
         const uint64_t fmask = __ballot(work && code != 0);
         const uint32_t jfirst = j_start > base ? j_start - base : 0u;  // first lane of request j
         const uint64_t jmask = mask_le(lane) & ~mask_lt((int)jfirst);
-        const bool copied = work && code == 0 && (fmask & jmask) == 0;
+        uint32_t ffr = kNone;  // kCoop: the request's first faulting page, agreed by the workgroup
+        if (kCoop) {
+            if (lane == 0 && fmask)
+                atomicMin(&cs->ff[round % 3], base + (uint32_t)(__ffsll((unsigned long long)fmask) - 1));
+            __syncthreads();
+            ffr = uniform_u32(*(volatile uint32_t *)&cs->ff[round % 3]);
+            if (threadIdx.x == 0) cs->ff[(round + 2) % 3] = kNone;  // every wave is done reading it
+            if (work && c == ffr) {
+                cs->fcode = code;
+                cs->flevel = level;
+                cs->flo = lo;
+            }
+        }
+        const bool copied = kCoop ? (work && code == 0 && c < ffr) : (work && code == 0 && (fmask & jmask) == 0);
         // (pages served by the translation cache need no A/D: their filling walk set them)
         const uint64_t cmask = __ballot(copied && !fhit);
         const uint64_t cto_mask = __ballot(copied && !fhit && j_dir);
 
         // owner lanes pick up their request's first fault in this pass
-        {
+        if (!kCoop) {
             const bool own = (uint32_t)lane < gn && nch > 0 && ff == kNone;
             uint64_t my = 0;
             if (own) {
@@ -922,10 +1062,30 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
             copy_wave((uint8_t *)d, (const uint8_t *)s, n, B.nontemporal != 0);
             cm &= cm - 1;
         }
+        if (kCoop && ffr != kNone) {  // workgroup-uniform
+            ff = ffr;
+            break;
+        }
+    }
+    bool any_spill = __ballot(spilled) != 0;
+    if (kCoop) {
+        // the request's outcome, from the workgroup's shared state
+        if (lane == 0) {
+            if (queued) atomicAdd(&cs->queued, queued);
+            if (any_spill) atomicOr(&cs->spilled, 1u);
+        }
+        __syncthreads();
+        any_spill = *(volatile uint32_t *)&cs->spilled != 0;
+        queued = *(volatile uint32_t *)&cs->queued;
+        if (ff != kNone) {
+            fcode = *(volatile uint32_t *)&cs->fcode;
+            flevel = *(volatile uint32_t *)&cs->flevel;
+            flo = *(volatile uint64_t *)&cs->flo;
+        }
     }
 
-    // ---- results (owner lanes)
-    if ((uint32_t)lane < gn) {
+    // ---- results (owner lanes; a large request's come from k_translate_large)
+    if ((uint32_t)lane < gn && !large && wv == 0) {
         devirt_result r;
         r.pad = 0;
         if (code0) {
@@ -964,20 +1124,22 @@ __device__ bool process_group(const DView &V, const DBatch &B, uint64_t r0, uint
             *gp<DV_GLOBAL unsigned long long>(&fifo->misses) += f_miss;
         }
     }
-    return __ballot(spilled) != 0;
+    return any_spill;
 }
 
 // ------------------------------------------------------------------ kernels
 __global__ void k_reset(DBatch b, uint32_t n_epochs) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *b.t0 = wall_clock64();
-    constexpr uint32_t per = 2 + 2 * kQParts;  // counters per epoch
+    constexpr uint32_t per = 3 + 2 * kQParts;  // counters per epoch
     for (; i < n_epochs * per; i += gridDim.x * blockDim.x) {
         const uint32_t e = i / per, k = i % per;
         if (k == 0)
             b.ctr[e].group_cursor = 0;
-        else if (k == per - 1)
+        else if (k == per - 2)
             b.ctr[e].spill_n = 0;
+        else if (k == per - 1)
+            b.ctr[e].large_n = 0;
         else
             b.ctr[e].q[k - 1][0] = 0;
     }
@@ -1006,9 +1168,10 @@ __device__ __forceinline__ void flush_counters(DCounters *c, const GroupOut &st)
 
 // direct != 0: the translating wavefronts copy their runs themselves and
 // nothing is queued (one launch for a small batch).
-__global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uint64_t r0, uint64_t r1,
-                                                           uint32_t epoch, int direct) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_translate_groups(DView v, DBatch b, uint64_t r0, uint64_t r1, uint32_t epoch, int direct) {
     extern __shared__ uint8_t smem[];
+    v.lds = lds_slots_load(v) ? 1u : 0u;
     const int wave = threadIdx.x >> 6;
     CEnt *cache = (CEnt *)smem + wave * kCacheWays;
     uint32_t *owner = (uint32_t *)((CEnt *)smem + (blockDim.x >> 6) * kCacheWays) + wave * kCacheWays;
@@ -1033,7 +1196,8 @@ __global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uin
         if (claim && lane_id() == 0) g = atomicAdd(&b.ctr[epoch].group_cursor, 1u);
         const uint64_t gs = r0 + gi * G;
         const uint32_t gn = (uint32_t)((r1 - gs) < G ? (r1 - gs) : G);
-        if (process_group<false>(v, b, gs, gn, dummy, epoch, cache, owner, direct != 0, b.ctr, st)) {
+        if (process_group<false, false>(v, b, gs, gn, dummy, epoch, cache, owner, direct != 0,
+                                        direct ? kLargeKeep : kLargeDefer, r0, b.ctr, st, nullptr)) {
             st.spills++;
             if (lane_id() == 0) {
                 const uint32_t k = atomicAdd(&b.ctr[epoch].spill_n, 1u);
@@ -1042,6 +1206,47 @@ __global__ void __launch_bounds__(256) k_translate_groups(DView v, DBatch b, uin
         }
         if (!claim) break;
         gi = nwaves + uniform_u32(shfl32(g, 0));
+    }
+    flush_counters(b.counters, st);
+}
+
+// The epoch's large requests (listed by k_translate_groups), one per
+// workgroup at a time: its wavefronts walk the request's pages together (see
+// process_group), so a request of thousands of pages takes a few rounds
+// instead of one wavefront's many passes.  Queue overflow is handled as in
+// k_translate_groups; a request that spills goes on the spill list alone.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_translate_large(DView v, DBatch b, uint64_t r0, uint32_t epoch) {
+    extern __shared__ uint8_t smem[];
+    __shared__ CoopShared cs;
+    const int wave = threadIdx.x >> 6;
+    CEnt *cache = (CEnt *)smem + wave * kCacheWays;
+    uint32_t *owner = (uint32_t *)((CEnt *)smem + (blockDim.x >> 6) * kCacheWays) + wave * kCacheWays;
+    const uint32_t n = uniform_u32(*gp<const g_u32>(&b.ctr[epoch].large_n));
+    if (n == 0) return;
+    v.lds = lds_slots_load(v) ? 1u : 0u;
+    if ((threadIdx.x & 63) < kCacheWays) cache[threadIdx.x & 63].key = ~0ull;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    GroupOut st = {0, 0, 0, 0, 0, 0, 0};
+    devirt_request dummy = {};
+    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const uint64_t r = uniform_u64(gp<const g_u64>(b.large)[r0 + k]);
+        if (threadIdx.x == 0) {
+            cs.ff[0] = cs.ff[1] = cs.ff[2] = kNone;
+            cs.queued = 0;
+            cs.spilled = 0;
+        }
+        __syncthreads();
+        const bool sp = process_group<false, true>(v, b, r, 1, dummy, epoch, cache, owner, false, kLargeKeep, r0,
+                                                   b.ctr, st, &cs);
+        if (b.counters && threadIdx.x == 0) atomicAdd(&b.counters->large_requests, 1ull);
+        if (sp && threadIdx.x == 0) {
+            st.spills++;
+            const uint32_t i = atomicAdd(&b.ctr[epoch].spill_n, 1u);
+            gp<g_u64>(b.spill)[r0 + i] = r | kSpillOne;
+        }
+        __syncthreads();  // cs is reused for the next request
     }
     flush_counters(b.counters, st);
 }
@@ -1135,9 +1340,15 @@ __global__ void __launch_bounds__(256) k_spill(DView v, DBatch b, uint64_t r0, u
     GroupOut st = {0, 0, 0, 0, 0, 0, 0};
     devirt_request dummy = {};
     for (uint64_t i = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (uint64_t)wave; i < n; i += nwaves) {
-        const uint64_t gs = uniform_u64(gp<const g_u64>(b.spill)[r0 + i]);
-        const uint32_t gn = (uint32_t)((r1 - gs) < b.group ? (r1 - gs) : b.group);
-        process_group<false>(v, b, gs, gn, dummy, epoch, cache, owner, true, b.ctr, st);
+        const uint64_t e = uniform_u64(gp<const g_u64>(b.spill)[r0 + i]);
+        if (e & kSpillOne) {  // a large request, alone
+            process_group<false, false>(v, b, e & ~kSpillOne, 1, dummy, epoch, cache, owner, true, kLargeKeep, r0,
+                                        b.ctr, st, nullptr);
+        } else {  // a group; its large requests spill on their own
+            const uint32_t gn = (uint32_t)((r1 - e) < b.group ? (r1 - e) : b.group);
+            process_group<false, false>(v, b, e, gn, dummy, epoch, cache, owner, true, kLargeSkip, r0, b.ctr, st,
+                                        nullptr);
+        }
     }
     flush_counters(b.counters, st);
 }
@@ -1153,7 +1364,7 @@ __global__ void __launch_bounds__(64) k_plain(DView v, DBatch b, devirt_request 
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     GroupOut st = {0, 0, 0, 0, 0, 0, 0};
-    process_group<true>(v, b, 0, 1, req, 0, cache, owner, inline_copy != 0, b.ctr, st);
+    process_group<true, false>(v, b, 0, 1, req, 0, cache, owner, inline_copy != 0, kLargeKeep, 0, b.ctr, st, nullptr);
     flush_counters(b.counters, st);
 }
 
@@ -1172,10 +1383,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     const bool valid_asid = asid < v.nproc;
     DProc p = {0, 0, 4};
     DVm vmv = {};
-    if (valid_asid) {
-        p = gp<const DV_GLOBAL DProc>(v.procs)[asid];
-        vmv = gp<const DV_GLOBAL DVm>(v.vms)[p.vm];
-    }
+    vmv.lds_base = kLdsNone;
+    if (valid_asid) p = gp<const DV_GLOBAL DProc>(v.procs)[asid];
+    const bool lds = valid_asid && lds_slots_load_one(v, p.vm);  // one process: its VM's slots only
+    if (valid_asid) vmv = load_vm(v, p.vm, lds);
     const uint64_t lim = user_limit(p.levels);
     const bool write = (flags & DEVIRT_XLAT_WRITE) != 0;
     const bool set_ad = (flags & DEVIRT_XLAT_SET_AD) != 0;
@@ -1436,6 +1647,12 @@ hipError_t launch_translate_groups(hipStream_t s, int grid, int block, DView v, 
     return hipGetLastError();
 }
 
+hipError_t launch_translate_large(hipStream_t s, int grid, int block, DView v, DBatch b, uint64_t r0,
+                                  uint32_t epoch) {
+    hipLaunchKernelGGL(k_translate_large, dim3(grid), dim3(block), wave_lds(block), s, v, b, r0, epoch);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(hipStream_t s, int grid, int block, DBatch b, uint32_t epoch) {
     hipLaunchKernelGGL(k_copy, dim3(grid), dim3(block), 0, s, b, epoch);
     return hipGetLastError();
@@ -1545,6 +1762,50 @@ __device__ bool existing_table(const DVm &v, const DProc &p, uint64_t gva, uint3
         table = load_entry(v.arena, th + 8 * entry_index(p.levels, (uint32_t)lvl, gva)) & kAddrMask;
     }
     return gpa_xlat(v, table, kNeedTable, th) == DEVIRT_OK;
+}
+
+// ---- the EPT half of mapping a page (section 4.2: the backend creates the
+// mapping in the guest tables and also in the EPT), devirt_ept_map_pages.
+// The maps name guest-physical pages and the arena pages behind them; new EPT
+// tables are linked with R, W and X, leaves carry the map's R/W/X bits and
+// memory type WB.
+constexpr uint64_t kEptRwx = 7ull, kEptWb = 6ull << 3;
+
+__device__ __forceinline__ uint64_t ept_slot(uint64_t table, uint32_t level, uint64_t gpa) {
+    return table + 8 * ((gpa >> (12 + 9 * (level - 1))) & 511);
+}
+
+// Walk of the EPT as it is, for a map of gpa.  On success `missing` is the
+// highest level whose entry is not present (its child tables are lacking), 0
+// when the EPT page table exists.  A present large leaf on the path fails the
+// map (RESERVED: nothing is split), a misconfigured table entry or a table
+// outside the arena fails it with EPT_MISCONFIG; `level` names the entry.
+__device__ uint32_t ept_map_walk(const DVm &v, uint64_t gpa, uint32_t &level, uint32_t &missing) {
+    uint64_t table = v.ept_root;
+    missing = 0;
+    for (uint32_t lvl = 4; lvl >= 2; --lvl) {
+        const uint64_t e = load_entry(v.arena, ept_slot(table, lvl, gpa));
+        if (!(e & 7)) {
+            missing = lvl;
+            level = 0;
+            return DEVIRT_OK;
+        }
+        level = lvl;
+        if ((e & 3) == 2) return DEVIRT_EPT_MISCONFIG;  // write without read
+        if (lvl <= 3 && (e & 0x80)) return DEVIRT_RESERVED;
+        if (e & 0xF8) return DEVIRT_EPT_MISCONFIG;  // bits 7:3 of a table entry
+        table = e & kAddrMask;
+        if (table >= v.arena_bytes || v.arena_bytes - table < 4096) return DEVIRT_EPT_MISCONFIG;
+    }
+    level = 0;
+    return DEVIRT_OK;
+}
+
+// Arena offset of the existing EPT table at `level` on gpa's path (known present).
+__device__ uint64_t existing_ept_table(const DVm &v, uint64_t gpa, uint32_t level) {
+    uint64_t table = v.ept_root;
+    for (uint32_t lvl = 4; lvl > level; --lvl) table = load_entry(v.arena, ept_slot(table, lvl, gpa)) & kAddrMask;
+    return table;
 }
 
 // Position of key in the sorted keys[0, n), or -1.
@@ -1663,7 +1924,25 @@ __global__ void __launch_bounds__(256) k_map_walk(MapArgs a) {
         r.code = DEVIRT_OK;
         r.level = 0;
         r.pad = 0;
-        if (a.asid >= a.v.nproc) {
+        if (a.ept_map) {  // gva: the guest-physical page; gpa: the arena page behind it
+            const DVm vm = a.v.vms[a.vm];
+            const uint32_t perms = m.flags & 7u;
+            if ((m.gva & 0xFFFull) || (m.gva >> 48) || (m.gpa & 0xFFFull) || m.gpa >= vm.arena_bytes ||
+                vm.arena_bytes - m.gpa < 4096 || (m.flags & ~7u) || perms == 0 || (perms & 3u) == 2u) {
+                r.code = DEVIRT_NONCANONICAL;
+            } else {
+                uint32_t level = 0, missing = 0;
+                r.code = ept_map_walk(vm, m.gva, level, missing);
+                r.level = (uint16_t)level;
+                if (r.code == DEVIRT_OK) {
+                    r.bytes_done = 4096;
+                    r.fault_gva = 0;
+                    ok = true;
+                    int j = 0;
+                    for (uint32_t l = missing ? missing - 1 : 0; l >= 1 && j < 4; --l) k[j++] = map_key(l, m.gva);
+                }
+            }
+        } else if (a.asid >= a.v.nproc) {
             r.code = DEVIRT_INVALID;
         } else {
             const DProc p = a.v.procs[a.asid];
@@ -1711,6 +1990,17 @@ __global__ void __launch_bounds__(256) k_map_pool(const MapArgs a) {
         __hip_atomic_store(&a.sc[3], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The VM whose tables a map call writes (false: an unknown asid).
+__device__ __forceinline__ bool map_vm(const MapArgs &a, DVm &vm) {
+    if (a.ept_map) {
+        vm = a.v.vms[a.vm];
+        return true;
+    }
+    if (a.asid >= a.v.nproc) return false;
+    vm = a.v.vms[a.v.procs[a.asid].vm];
+    return true;
+}
+
 // Tables to create: 0 when the pool is too small (then nothing is written).
 __device__ __forceinline__ uint64_t new_tables(const MapArgs &a) {
     const uint64_t u = a.sc[0];
@@ -1725,8 +2015,9 @@ __global__ void __launch_bounds__(256) k_map_rank_zero(const MapArgs a) {
     __shared__ uint64_t tile[256];
     const uint64_t nt = new_tables(a);
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (nt && a.asid < a.v.nproc) {
-        uint8_t *arena = a.v.vms[a.v.procs[a.asid].vm].arena;
+    DVm zvm;
+    if (nt && map_vm(a, zvm)) {
+        uint8_t *arena = zvm.arena;
         const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
         for (uint64_t z = t; z < nt * 256; z += stride)
             *gp<g_u32x4>(arena + a.pool_hpa[z >> 8] + 16 * (z & 255)) = (u32x4){0u, 0u, 0u, 0u};
@@ -1747,8 +2038,9 @@ __global__ void __launch_bounds__(256) k_map_rank_zero(const MapArgs a) {
 // Zero the new tables (after a library sort).
 __global__ void __launch_bounds__(256) k_map_zero(const MapArgs a) {
     const uint64_t nt = new_tables(a);
-    if (!nt || a.asid >= a.v.nproc) return;
-    uint8_t *arena = a.v.vms[a.v.procs[a.asid].vm].arena;
+    DVm zvm;
+    if (!nt || !map_vm(a, zvm)) return;
+    uint8_t *arena = zvm.arena;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt * 256; t += stride)
         *gp<g_u32x4>(arena + a.pool_hpa[t >> 8] + 16 * (t & 255)) = (u32x4){0u, 0u, 0u, 0u};
@@ -1765,10 +2057,38 @@ __global__ void __launch_bounds__(256) k_map_write(const MapArgs a) {
     const bool short_pool = pool_short(a);
     const uint64_t nt = short_pool ? 0 : a.sc[0];
     if (t == 0) *a.n_used = nt;
+    const uint64_t *uniq = a.tkeys_sorted;
+    if (a.ept_map) {
+        const DVm vm = a.v.vms[a.vm];
+        if (t < nt) {  // link new EPT table t from its parent (new, or existing above it)
+            const uint64_t key = uniq[t];
+            const uint32_t l = 8u - (uint32_t)(key >> 56);
+            const uint64_t gpa = (key & ((1ull << 56) - 1)) << (12 + 9 * l);
+            const int64_t j = l + 1 < 4 ? find_key(uniq, nt, map_key(l + 1, gpa)) : -1;
+            const uint64_t parent = j >= 0 ? a.pool_hpa[j] : existing_ept_table(vm, gpa, l + 1);
+            store_entry(vm.arena, ept_slot(parent, l + 1, gpa), a.pool_hpa[t] | kEptRwx);
+        }
+        if (t >= a.n || a.res[t].code != DEVIRT_OK) return;
+        const devirt_map m = a.maps[t];
+        if (short_pool) {
+            a.res[t].code = DEVIRT_NO_POOL;
+            a.res[t].bytes_done = 0;
+            a.res[t].fault_gva = m.gva;
+            return;
+        }
+        const uint64_t page = m.gva >> 12;
+        const uint64_t mask = (1ull << a.pset_log2) - 1;
+        uint64_t h = hash_slot(page, a.pset_log2);
+        for (uint64_t probe = 0; probe <= mask && (a.pset[h] >> kMapIdxBits) != page; ++probe) h = (h + 1) & mask;
+        if (a.pset[h] != ((page << kMapIdxBits) | t)) return;  // not the page's last map
+        const int64_t j = find_key(uniq, nt, map_key(1, m.gva));
+        const uint64_t pt = j >= 0 ? a.pool_hpa[j] : existing_ept_table(vm, m.gva, 1);
+        store_entry(vm.arena, ept_slot(pt, 1, m.gva), m.gpa | (m.flags & 7u) | kEptWb);
+        return;
+    }
     if (a.asid >= a.v.nproc) return;
     const DProc p = a.v.procs[a.asid];
     const DVm vm = a.v.vms[p.vm];
-    const uint64_t *uniq = a.tkeys_sorted;
     if (t < nt) {
         const uint64_t key = uniq[t];
         const uint32_t l = 8u - (uint32_t)(key >> 56);

@@ -52,6 +52,7 @@ static devirt_config default_config() {
     c.use_graph = 1;
     c.overlap = 1;
     c.fifo_entries = 0;
+    c.large_pages = 0;
     return c;
 }
 
@@ -66,6 +67,7 @@ static int check_config(const devirt_config &c) {
     if (c.inline_bytes > 256) return dv_fail(-EINVAL, "inline_bytes must be <= 256");
     if (c.overlap > 1) return dv_fail(-EINVAL, "overlap must be 0 or 1");
     if (c.fifo_entries > kFifoMax) return dv_fail(-EINVAL, "fifo_entries must be <= %u", kFifoMax);
+    if (c.large_pages != 0 && c.large_pages < 64) return dv_fail(-EINVAL, "large_pages must be 0 or >= 64");
     return 0;
 }
 
@@ -84,6 +86,7 @@ Workspace::~Workspace() {
     hipFree(tiles);
     hipFree(t0);
     hipFree(spill);
+    hipFree(large);
     if (map_ev) {
         hipEventSynchronize(map_ev);
         hipEventDestroy(map_ev);
@@ -166,7 +169,7 @@ static int upload_vms(devirt_ctx *c) {
         h[i].index_len = v.index_len;
         h[i].nslots = v.nsorted;
         h[i].index_complete = v.index_complete;
-        h[i].pad = 0;
+        h[i].lds_base = kLdsNone;
         h[i].ept_root = v.ept_root;
     }
     if (c->vms.size() > c->d_vms_cap) {
@@ -383,6 +386,8 @@ DView view_of(const devirt_ctx *c) {
     v.procs = c->d_procs;
     v.nvm = (uint32_t)c->vms.size();
     v.nproc = (uint32_t)c->procs.size();
+    v.lds = 0;
+    v.pad = 0;
     return v;
 }
 
@@ -439,6 +444,7 @@ int ensure_ws(devirt_ctx *c, Workspace *w, uint64_t n_req, uint64_t n_epochs, bo
     if ((rc = grow(c, w, w->ctr, w->ctr_cap, std::max<uint64_t>(n_epochs, 1), "epoch counters"))) return rc;
     if ((rc = grow(c, w, w->t0, w->t0_cap, 1, "clock"))) return rc;
     if ((rc = grow(c, w, w->spill, w->spill_cap, std::max<uint64_t>(n_req, 1), "spill list"))) return rc;
+    if ((rc = grow(c, w, w->large, w->large_cap, std::max<uint64_t>(n_req, 1), "large list"))) return rc;
     uint64_t tiles = (n_req + kFaultTile - 1) / kFaultTile;
     if ((rc = grow(c, w, w->tiles, w->tiles_cap, std::max<uint64_t>(tiles, 1), "fault tiles"))) return rc;
     if (need_pending && (rc = grow(c, w, w->pending, w->pending_cap, std::max<uint64_t>(n_req, 1), "pending")))
@@ -454,6 +460,7 @@ DBatch make_batch(devirt_ctx *c, Workspace *w) {
         b.shorts = w->shorts;
         b.part_cap = std::min(w->seg_cap, w->short_cap) / kQParts;
         b.spill = w->spill;
+        b.large = w->large;
         b.ctr = w->ctr;
         b.pending = w->pending;
         b.t0 = w->t0;
@@ -465,6 +472,7 @@ DBatch make_batch(devirt_ctx *c, Workspace *w) {
     b.seg_chunks = c->cfg.seg_chunks;
     b.inline_bytes = c->cfg.inline_bytes;
     b.nontemporal = c->cfg.nontemporal;
+    b.large_pages = c->cfg.large_pages;
     return b;
 }
 
@@ -533,6 +541,7 @@ extern "C" int devirt_get_stats(devirt_ctx *c, devirt_stats *out) {
     out->inline_segments = h.inline_segments;
     out->ad_atomics = h.ad_atomics;
     out->spilled_groups = h.spilled_groups;
+    out->large_requests = h.large_requests;
     return 0;
 }
 
@@ -556,6 +565,9 @@ static int grid_for(devirt_ctx *c, uint64_t waves_needed, uint32_t block, uint32
     if (g < 1) g = 1;
     return (int)g;
 }
+
+static int map_run(devirt_ctx *c, MapArgs &a, const devirt_map *maps, uint64_t n, const uint64_t *pool_gpa,
+                   const std::vector<uint64_t> &hpa, devirt_result *res, uint64_t *n_used, hipStream_t s);
 
 extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *maps, uint64_t n,
                                 const uint64_t *pool_gpa, uint64_t n_pool, devirt_result *res, uint64_t *n_used,
@@ -606,6 +618,20 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
             hpa[k] = q->off + (g - q->gpa);
         }
     }
+    MapArgs a;
+    a.asid = asid;
+    a.ept_pool = ept ? 1 : 0;
+    a.ept_map = 0;
+    a.vm = 0;
+    return map_run(c, a, maps, n, pool_gpa, hpa, res, n_used, s);
+}
+
+// The map launches of devirt_map_pages and devirt_ept_map_pages: workspace,
+// pool upload (pool_gpa: the frames as the caller named them; hpa: their
+// arena offsets, or zeros for frames the device translates), kernels.
+static int map_run(devirt_ctx *c, MapArgs &a, const devirt_map *maps, uint64_t n, const uint64_t *pool_gpa,
+                   const std::vector<uint64_t> &hpa, devirt_result *res, uint64_t *n_used, hipStream_t s) {
+    const uint64_t n_pool = hpa.size();
     Workspace *w = get_ws(c, s);
     // hash sets of at least twice the entries they can hold
     const uint64_t m = std::min<uint64_t>(4 * n, n_pool);
@@ -620,9 +646,7 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     int rc;
     if ((rc = grow(c, w, w->map_buf, w->map_cap, words, "map buffers"))) return rc;
     uint64_t *b = w->map_buf;
-    MapArgs a;
     a.v = view_of(c);
-    a.asid = asid;
     a.maps = maps;
     a.n = n;
     a.res = res;
@@ -639,7 +663,6 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     a.tkeys_sorted = b + T + m + P + 4;
     a.pool_gpa = b + T + 2 * m + P + 4;
     a.pool_hpa = b + T + 2 * m + P + 4 + n_pool;
-    a.ept_pool = ept ? 1 : 0;
     a.temp = nullptr;
     size_t need = 0;
     a.temp_query = &need;
@@ -667,6 +690,36 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     HIPCHK(launch_map(s, a));  // only arena bytes change: captured batch graphs stay valid
     c->xlat_gen++;             // but cached translations may be stale
     return 0;
+}
+
+extern "C" int devirt_ept_map_pages(devirt_ctx *c, uint32_t vm, const devirt_ept_map *maps, uint64_t n,
+                                    const uint64_t *pool_host, uint64_t n_pool, devirt_result *res,
+                                    uint64_t *n_used, void *stream) {
+    if (!c) return dv_fail(-EINVAL, "ctx is NULL");
+    if (server_owns(c)) return dv_fail(-EBUSY, "a serving loop owns this context");
+    if (vm >= c->vms.size()) return dv_fail(-EINVAL, "no VM %u", vm);
+    const VmHost &v = c->vms[vm];
+    if (v.ept_root == ~0ull) return dv_fail(-EINVAL, "VM %u has no EPT", vm);
+    if (n > kMapMax) return dv_fail(-EINVAL, "at most %llu maps per call", (unsigned long long)kMapMax);
+    if (!n_used || (n && (!maps || !res)) || (n_pool && !pool_host)) return dv_fail(-EINVAL, "NULL argument");
+    if (((uintptr_t)maps & 7) || ((uintptr_t)res & 7)) return dv_fail(-EINVAL, "maps and res must be 8-byte aligned");
+    if (set_dev(c)) return -EIO;
+    // the pool: aligned, distinct arena pages inside the arena
+    std::vector<uint64_t> hpa(pool_host, pool_host + n_pool);
+    for (uint64_t k = 0; k < n_pool; ++k)
+        if ((hpa[k] & 0xFFF) || hpa[k] >= v.bytes || v.bytes - hpa[k] < 4096)
+            return dv_fail(-EINVAL, "pool page %#llx is unaligned or outside the arena", (unsigned long long)hpa[k]);
+    std::vector<uint64_t> sorted(hpa);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return dv_fail(-EINVAL, "pool pages must be distinct");
+    static_assert(sizeof(devirt_ept_map) == sizeof(devirt_map), "one record layout for both kinds of map");
+    MapArgs a;
+    a.asid = 0;
+    a.ept_pool = 0;
+    a.ept_map = 1;
+    a.vm = vm;
+    return map_run(c, a, (const devirt_map *)maps, n, pool_host, hpa, res, n_used, (hipStream_t)stream);
 }
 
 extern "C" int devirt_translate(devirt_ctx *c, uint32_t asid, const uint64_t *gva_dev, uint64_t n, uint32_t flags,
@@ -836,6 +889,9 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
             if ((rc = prof_begin(c, side, 1, &pe))) return rc;
             HIPCHK(launch_translate_groups(side, grid_for(c, groups, c->cfg.xlat_wg, c->cfg.xlat_wgs_per_cu),
                                            (int)c->cfg.xlat_wg, v, be, r0, r1, (uint32_t)e, 0));
+            // the epoch's large requests, a workgroup each (returns at once when there are none)
+            if (be.large_pages)
+                HIPCHK(launch_translate_large(side, (int)(2ull * c->cus), 256, v, be, r0, (uint32_t)e));
             if ((rc = prof_end(c, side, pe))) return rc;
             if (overlap) {
                 HIPCHK(hipEventRecord(t_done, side));
@@ -1044,6 +1100,7 @@ extern "C" int devirt_autotune(devirt_ctx *c, const devirt_request *reqs, uint64
         {[](devirt_config &k, uint32_t v) { k.copy_wg = v; }, {256, 512, 1024}},
         {[](devirt_config &k, uint32_t v) { k.copy_wgs_per_cu = v; }, {4, 8, 16}},
         {[](devirt_config &k, uint32_t v) { k.seg_chunks = v; }, {1, 2, 4, 16, 64}},
+        {[](devirt_config &k, uint32_t v) { k.large_pages = v; }, {0, 64, 128, 256, 1024}},
     };
     for (const auto &kn : knobs) {
         if (rc) break;
@@ -1096,6 +1153,7 @@ static const CfgField kCfgFields[] = {
     {"use_graph", &devirt_config::use_graph},
     {"overlap", &devirt_config::overlap},
     {"fifo_entries", &devirt_config::fifo_entries},
+    {"large_pages", &devirt_config::large_pages},
 };
 
 static std::string device_key(devirt_ctx *c) {

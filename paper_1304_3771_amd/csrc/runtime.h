@@ -46,6 +46,8 @@ struct Workspace {
     uint64_t t0_cap = 0;
     uint64_t *spill = nullptr;          // per request slot: groups left to the spill pass
     uint64_t spill_cap = 0;
+    uint64_t *large = nullptr;          // per request slot: the epoch's large requests
+    uint64_t large_cap = 0;
     std::vector<GraphEntry> graphs;
     hipStream_t side = nullptr;         // translate launches run here, ahead of the copies
     std::vector<hipEvent_t> events;     // per epoch: translate done, copy done; plus the fork

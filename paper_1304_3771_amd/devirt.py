@@ -35,6 +35,8 @@ XLAT_DTYPE = np.dtype([("gpa", "<u8"), ("hpa", "<u8"), ("code", "<u4"), ("level"
                        ("vm", "<u2")])
 MAP_DTYPE = np.dtype([("gva", "<u8"), ("gpa", "<u8"), ("flags", "<u4"), ("pad", "<u4")])
 MAP_WRITE = 1
+EPT_MAP_DTYPE = np.dtype([("gpa", "<u8"), ("hpa", "<u8"), ("flags", "<u4"), ("pad", "<u4")])
+EPT_R, EPT_W, EPT_X = 1, 2, 4
 
 
 class DevirtError(RuntimeError):
@@ -51,7 +53,7 @@ SERVE_DEVICE_TIMES = 0x100
 class Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "group", "seg_chunks", "xlat_wg", "xlat_wgs_per_cu", "copy_wg", "copy_wgs_per_cu", "nontemporal",
-        "inline_bytes", "use_graph", "overlap", "fifo_entries")]
+        "inline_bytes", "use_graph", "overlap", "fifo_entries", "large_pages")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -63,7 +65,7 @@ class Stats(ctypes.Structure):
                 ("xlat_launches", ctypes.c_uint64), ("xlat_ms", ctypes.c_double),
                 ("pages_walked", ctypes.c_uint64), ("cache_hits", ctypes.c_uint64), ("cache_misses", ctypes.c_uint64),
                 ("segments", ctypes.c_uint64), ("inline_segments", ctypes.c_uint64), ("ad_atomics", ctypes.c_uint64),
-                ("spilled_groups", ctypes.c_uint64)]
+                ("spilled_groups", ctypes.c_uint64), ("large_requests", ctypes.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -116,6 +118,7 @@ _SIGS = {
     "devirt_copy_static": ([vp, u32, u64, vp, u64, u32, vp, vp]),
     "devirt_submit_batch": ([vp, vp, u64, vp, u32, vp, vp, vp, vp, vp]),
     "devirt_map_pages": ([vp, u32, vp, u64, vp, u64, vp, vp, vp]),
+    "devirt_ept_map_pages": ([vp, u32, vp, u64, vp, u64, vp, vp, vp]),
     "devirt_sync": ([vp, vp]),
     "devirt_get_config": ([vp, ctypes.POINTER(Config)]),
     "devirt_set_config": ([vp, ctypes.POINTER(Config)]),
@@ -272,6 +275,14 @@ class Context:
         pool = np.ascontiguousarray(np.asarray(pool_gpa, dtype=np.uint64).reshape(-1))
         _check("devirt_map_pages", lib().devirt_map_pages(
             self._h, asid, _ptr(maps), n, pool.ctypes.data if len(pool) else None, len(pool), _ptr(res),
+            _ptr(n_used), _stream(stream)))
+
+    def ept_map_pages(self, vm: int, maps, n: int, pool, res, n_used, stream=None):
+        """maps: device array of EPT_MAP_DTYPE records; pool: host sequence of
+        free arena pages (offsets); res: device results; n_used: device uint64."""
+        pool = np.ascontiguousarray(np.asarray(pool, dtype=np.uint64).reshape(-1))
+        _check("devirt_ept_map_pages", lib().devirt_ept_map_pages(
+            self._h, vm, _ptr(maps), n, pool.ctypes.data if len(pool) else None, len(pool), _ptr(res),
             _ptr(n_used), _stream(stream)))
 
     def submit_batch(self, reqs, n: int, res, epoch_end=None, faults=None, n_faults=None, t_done=None,

@@ -295,3 +295,113 @@ def test_map_full_size_c2():
         log(f"map full size: bit-exact, {nxt} new tables")
     finally:
         ctx.close()
+
+
+# ------------------------------------------------------------- EPT maps --
+def _gpu_ept_map(ctx, vm, m, pool):
+    """One devirt_ept_map_pages call; returns (results, pool pages used)."""
+    import torch
+    import paper_1304_3771_amd as dv
+    n = len(m)
+    dm = torch.from_numpy(np.ascontiguousarray(m).view(np.uint8).reshape(-1).copy()).cuda() if n else \
+        torch.zeros(24, dtype=torch.uint8, device="cuda")
+    res = torch.zeros(max(n, 1) * 24, dtype=torch.uint8, device="cuda")
+    used = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    ctx.ept_map_pages(vm, dm, n, pool, res, used)
+    torch.cuda.synchronize()
+    return res.cpu().numpy()[:n * 24].view(dv.RESULT_DTYPE), int(used.item())
+
+
+def test_golden_ept_maps():
+    """The hand-derived EPT map batch (its expectations pin the oracle), then
+    the same batch with the pool one page short (nothing written)."""
+    from oracle.oracle import EPT_MAP_DTYPE
+    H = pins.H
+    w = [x for x in pins.golden_worlds() if "ept_maps" in x][0]
+    gm = w["ept_maps"]
+    m = np.zeros(len(gm["batch"]), EPT_MAP_DTYPE)
+    for i, b in enumerate(gm["batch"]):
+        m[i] = (H(b["gpa"]), H(b["hpa"]), b["flags"], 0)
+    for pool_key in ("pool", "short_pool"):
+        log(f"golden EPT maps, {pool_key}")
+        o, arena, _ = pins.build_golden(w)
+        ctx = new_ctx()
+        try:
+            vm = ctx.vm_create(H(w["arena_bytes"]))
+            ctx.vm_write(vm, 0, arena)
+            ctx.vm_set_ept(vm, H(w["ept_root"]))
+            pool = [H(x) for x in gm[pool_key]]
+            r, used = _gpu_ept_map(ctx, vm, m, pool)
+            er, eused = o.ept_map_pages(0, m, pool)
+            a = np.empty(H(w["arena_bytes"]), np.uint8)
+            ctx.vm_read(vm, 0, a)
+            _same(f"golden EPT maps {pool_key}", r, used, er, eused, [a], [arena])
+            assert used == (gm["used"] if pool_key == "pool" else 0)
+        finally:
+            ctx.close()
+
+
+@pytest.mark.parametrize("name", ["ept", "ept_faults", "ept_lvl5", "ept_pae", "ept_1g"])
+def test_ept_map_matches_oracle(name):
+    """A mixed EPT map batch (pages inside guest memory, new regions far above
+    it, pages inside 2 MiB / 1 GiB EPT leaves, repeats, invalid maps): a pool
+    one page short (nothing written), then enough, then the same batch again
+    (every table now exists), then the workload's requests through the
+    changed EPT; results, pages used and every arena byte, and the batch's
+    results, fault list, arenas and pool."""
+    from gpu_util import gpu_batch
+    w = wl(name)
+    log(f"EPT map {name}")
+    rng = np.random.default_rng(7)
+    vm = 0
+    m, pool = pins.ept_map_batch(w, vm, 400, rng)
+    o = Oracle.from_workload(w)
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        _, need = Oracle.from_workload(w).ept_map_pages(vm, m, pool)
+        assert need > 0
+        for k, p in enumerate((pool[:need - 1], pool, pool)):
+            r, used = _gpu_ept_map(ctx, vm, m, p)
+            er, eused = o.ept_map_pages(vm, m, p)
+            _same(f"{name} EPT map call {k}", r, used, er, eused, device.read_arenas(ctx, dw), o.arenas)
+            log(f"call {k}: {used} pages used, {int(np.count_nonzero(r['code'] == 0))} maps ok")
+        got = gpu_batch(w, ctx=ctx, dw=dw)
+        er, ef = o.batch(w.requests)
+        assert compare(f"{name} requests after EPT maps", got, (er, ef, o.arenas, o.pool)) == []
+    finally:
+        ctx.close()
+
+
+def test_ept_map_edge_cases():
+    """Refused with nothing done: a VM without an EPT, an unknown VM, pool
+    pages unaligned, outside the arena or repeated, too many maps; an empty
+    batch writes nothing and uses no page."""
+    import paper_1304_3771_amd as dv
+    from oracle.oracle import EPT_MAP_DTYPE
+    w = wl("ept")
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        before = device.read_arenas(ctx, dw)
+        arena = w.vms[0].arena_bytes
+        m = np.zeros(1, EPT_MAP_DTYPE)
+        m[0] = (0x1000, 0x1000, 3, 0)
+        for vm, pool in ((5, [0x10000]), (0, [0x10001]), (0, [arena]), (0, [0x10000, 0x10000])):
+            with pytest.raises(dv.DevirtError):
+                _gpu_ept_map(ctx, vm, m, pool)
+        with pytest.raises(dv.DevirtError):
+            ctx.ept_map_pages(0, 0, (1 << 19) + 1, [], 0, 0)
+        r, used = _gpu_ept_map(ctx, 0, m[:0], [0x10000])
+        assert used == 0
+        assert all(np.array_equal(a, b) for a, b in zip(device.read_arenas(ctx, dw), before))
+    finally:
+        ctx.close()
+    w2 = wl("mix2m")   # memslot VM
+    ctx = new_ctx()
+    try:
+        device.load(ctx, w2)
+        with pytest.raises(dv.DevirtError):
+            _gpu_ept_map(ctx, 0, m, [0x10000])
+    finally:
+        ctx.close()

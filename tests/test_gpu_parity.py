@@ -443,3 +443,54 @@ def test_completion_times_and_repeat():
     assert compare("t_done", got, exp) == []
     td = got[4]["t_done"]
     assert np.all(td > 0) and np.all(td < 60e9)
+
+
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_large_requests_by_workgroups(monkeypatch, overlap):
+    """Requests of more than large_pages pages are walked by the four
+    wavefronts of a workgroup together, round by round, agreeing on each
+    request's first faulting page before any A/D bit or copy.  Bit-exact
+    against the oracle with the smallest threshold, with completion times,
+    and with a 64-segment queue (overflowing large requests are copied by
+    their own wavefronts, or with overlap go to the spill pass alone)."""
+    import paper_1304_3771_amd as dv
+    w = wl("large")
+    pages = ((w.requests["gva"] + w.requests["len"] - 1) >> 12) - (w.requests["gva"] >> 12) + 1
+    n_large = int(np.count_nonzero((w.requests["len"] > 0) & (pages > 64)))
+    exp = oracle_batch(w)
+    faulted_large = int(np.count_nonzero((pages > 64) & (exp[0]["code"] != 0) & (exp[0]["bytes_done"] > 4096)))
+    log(f"large: {w.n_requests} requests, {n_large} of more than 64 pages ({faulted_large} fault past their "
+        f"first page), {len(w.epoch_end)} epochs")
+    assert n_large > 50 and faulted_large > 5
+    cfg = dict(large_pages=64, overlap=overlap, group=8)
+    got = gpu_batch(w, cfg=cfg, t_done=True)
+    assert compare(f"large overlap={overlap}", got, exp) == []
+    td = got[4]["t_done"]
+    assert np.all(td > 0) and np.all(td < 60e9)
+    # device counters: every large request went through the workgroup walk
+    ctx = new_ctx(**cfg)
+    try:
+        ctx.set_profiling(True, counters=True)
+        ctx.reset_stats()
+        got = gpu_batch(w, ctx=ctx)
+        st = ctx.get_stats()
+    finally:
+        ctx.close()
+    assert compare(f"large overlap={overlap} counters", got, exp) == []
+    assert st["large_requests"] == n_large, (st["large_requests"], n_large)
+    monkeypatch.setenv("DEVIRT_SEG_CAP", "64")
+    ctx = new_ctx(**cfg)
+    try:
+        ctx.set_profiling(True, counters=True)
+        ctx.reset_stats()
+        got = gpu_batch(w, ctx=ctx)
+        st = ctx.get_stats()
+    finally:
+        ctx.close()
+    log(f"large, 64-segment queue, overlap={overlap}: {st['spilled_groups']} spilled, "
+        f"{st['inline_segments']} runs copied by translating wavefronts")
+    assert compare(f"large overlap={overlap} tiny queue", got, exp) == []
+    if overlap:
+        assert st["spilled_groups"] > 0
+    else:
+        assert st["inline_segments"] > 0
