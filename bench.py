@@ -186,6 +186,11 @@ def cpu_baseline(wl, seconds, name, max_vms=8):
             "single_thread": one}
 
 
+def parse_set(text: str) -> dict:
+    """Launch config overrides written as key=value,key=value."""
+    return {k: int(v) for k, v in (kv.split("=") for kv in text.split(","))}
+
+
 def serving(args):
     """C4: Poisson arrivals through the serving loop, one JSON line."""
     import torch
@@ -196,6 +201,8 @@ def serving(args):
     log("serving: generating C4 (8 VMs x 4 GiB)")
     wl = gen.make_workload(sp, requests=False)
     ctx = dv.Context(0)
+    if args.set:
+        ctx.set_config(**parse_set(args.set))
     dw = device.load(ctx, wl)
     log("serving: uploaded")
     rates = [float(x) for x in args.rates.split(",")]
@@ -299,7 +306,7 @@ def serving(args):
                                              "arrivals, 60% 24B / 25% 4KiB / 14% 16-256KiB / 1% 4147200B",
                                  "max_inflight": args.max_inflight, "pool_gib": args.pool_gib,
                                  "max_batch": args.max_batch, "streams": args.streams,
-                                 "completion": args.completion},
+                                 "completion": args.completion, "launch_config": args.set or "default"},
                       "rates": out_rates}))
 
 
@@ -723,7 +730,7 @@ def main():
     log(f"generated {n} requests, {len(wl.epoch_end)} epochs in {time.time() - t_gen:.1f}s; uploading")
     ctx = dv.Context(0)
     if args.set:
-        ctx.set_config(**{k: int(v) for k, v in (kv.split("=") for kv in args.set.split(","))})
+        ctx.set_config(**parse_set(args.set))
     dw = device.load(ctx, wl)
     log(f"uploaded; launch config {ctx.get_config()}")
     res = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")

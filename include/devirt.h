@@ -502,6 +502,23 @@ int devirt_server_start(devirt_ctx *ctx, const devirt_server_cfg *cfg, devirt_se
  * device memory the caller keeps alive until completion).  Returns the
  * number queued in *n_queued; -EBUSY if the queue is full. */
 int devirt_server_submit(devirt_server *srv, const devirt_request *reqs_host, uint32_t n, uint32_t *n_queued);
+/* Queue a map batch as an operation of guest thread (asid, tag): the
+ * backend mapping pages into the process between the thread's forwarded
+ * copies (section 4.2; the batch is what devirt_map_pages does, with the same
+ * map records, pool rules and per-map results).  It runs in the thread's
+ * order, after every earlier operation of the thread has completed, and
+ * alone: once every batch already on the GPU has finished, with nothing
+ * admitted until it is done, since a table write must not race a walk.
+ * maps_host (n records, 8-byte aligned) and pool_gpa_host are copied at the
+ * call; res_host (n records, 8-byte aligned) receives every map's result when
+ * the batch completes and must stay alive until then.  Its completion
+ * summarizes the batch: bytes_done = 4096 per map that succeeded; code, level
+ * and fault_gva of the first map that failed (DEVIRT_OK if none).  *ticket
+ * (may be NULL) receives its ticket.  A bad pool (unaligned, repeated, outside
+ * every memslot) or more than 2^19 maps is refused here with -EINVAL. */
+int devirt_server_submit_map(devirt_server *srv, uint32_t asid, uint32_t tag, const devirt_map *maps_host,
+                             uint32_t n, const uint64_t *pool_gpa_host, uint32_t n_pool,
+                             devirt_result *res_host, uint64_t *ticket);
 /* Take up to max completions (any order); *n_out receives the count. */
 int devirt_server_poll(devirt_server *srv, devirt_completion *out, uint32_t max, uint32_t *n_out);
 /* Drain: wait until everything submitted has completed. */

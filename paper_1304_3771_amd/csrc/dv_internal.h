@@ -218,13 +218,11 @@ struct MapArgs {
     uint32_t tset_log2;
     uint64_t *tkeys, *tkeys_sorted;
     uint64_t m;
-    int rank;                             // sort by rank (m <= kMapRankMax), else a library radix sort
+    int rank;                             // sort by rank (m <= kMapRankMax), else tiles and merges
     // pages: a hash set of (page << kMapIdxBits | highest map index), ~0 when empty
     uint64_t *pset;
     uint32_t pset_log2;
     uint64_t *sc;                         // 4 scalars
-    void *temp;                           // sort scratch
-    size_t *temp_query;                   // non-null: only report the scratch size needed
 };
 hipError_t launch_map(hipStream_t s, const MapArgs &a);
 

@@ -36,10 +36,9 @@
 //   map pages  one lane per map walks the tables as they are; device hash
 //              sets collect the distinct tables the batch lacks and the last
 //              map of each page; the new tables are ordered by rank in LDS
-//              tiles (or a radix sort), zeroed, linked, and the leaves
-//              written -- four launches.
+//              tiles (long lists: tiles, then merge rounds), zeroed,
+//              linked, and the leaves written -- four launches.
 #include <cstring>
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "dv_internal.h"
 
@@ -2035,7 +2034,58 @@ __global__ void __launch_bounds__(256) k_map_rank_zero(const MapArgs a) {
     if (t < nt) a.tkeys_sorted[rank] = key;
 }
 
-// Zero the new tables (after a library sort).
+// Longer key lists (more than kMapRankMax keys can exist) are sorted in two
+// steps.  First tiles of kSortTile keys, each by rank in LDS; then rounds of
+// pairwise merges of sorted runs, in which a key's place in the merged run is
+// its place in its own run plus the number of smaller keys in the other run,
+// found by a binary search of that run.  Only the list's first
+// min(sc[0], m) entries are keys, all distinct, so there are no ties; the
+// rest is never read.  The steps alternate between tkeys and tkeys_sorted.
+constexpr uint32_t kSortTile = 1024;
+
+__device__ __forceinline__ uint64_t sort_count(const MapArgs &a) { return a.sc[0] < a.m ? a.sc[0] : a.m; }
+
+__global__ void __launch_bounds__(256) k_map_tile_sort(const MapArgs a, const uint64_t *src, uint64_t *dst) {
+    __shared__ uint64_t tile[kSortTile];
+    const uint64_t cnt = sort_count(a);
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    if (base >= cnt) return;  // uniform per block
+    const uint32_t len = (uint32_t)std::min<uint64_t>(kSortTile, cnt - base);
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) tile[i] = src[base + i];
+    __syncthreads();  // src may be dst: every read of the tile is done
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        const uint64_t key = tile[i];
+        uint32_t rank = 0;
+        for (uint32_t q = 0; q < len; ++q) rank += tile[q] < key;
+        dst[base + rank] = key;
+    }
+}
+
+// One merge round: runs of w keys (a power of two, at least kSortTile) are
+// merged in pairs.
+__global__ void __launch_bounds__(256) k_map_merge(const MapArgs a, const uint64_t *src, uint64_t *dst, uint64_t w) {
+    const uint64_t cnt = sort_count(a);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+        const uint64_t key = src[i];
+        const uint64_t pair = i & ~(2 * w - 1);
+        const bool second = (i & w) != 0;
+        const uint64_t own = second ? pair + w : pair;
+        const uint64_t other = second ? pair : pair + w;
+        const uint64_t olen = other >= cnt ? 0 : std::min<uint64_t>(w, cnt - other);
+        uint64_t lo = 0, hi = olen;  // smaller keys in the other run: [0, lo)
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (src[other + mid] < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        dst[pair + (i - own) + lo] = key;
+    }
+}
+
+// Zero the new tables (after a long list's sort).
 __global__ void __launch_bounds__(256) k_map_zero(const MapArgs a) {
     const uint64_t nt = new_tables(a);
     DVm zvm;
@@ -2133,15 +2183,7 @@ __global__ void __launch_bounds__(256) k_map_write(const MapArgs a) {
 static unsigned blocks_for(uint64_t n) { return (unsigned)((n + 255) / 256 ? (n + 255) / 256 : 1); }
 
 hipError_t launch_map(hipStream_t s, const MapArgs &a) {
-    size_t tsort = 0;
     hipError_t e;
-    if (!a.rank &&
-        (e = rocprim::radix_sort_keys(nullptr, tsort, a.tkeys, a.tkeys_sorted, a.m, 0, 64, s)) != hipSuccess)
-        return e;
-    if (a.temp_query) {
-        *a.temp_query = tsort;
-        return hipSuccess;
-    }
     const uint64_t nset = (1ull << a.tset_log2), npset = (1ull << a.pset_log2);
     // tset, tkeys and pset are contiguous, then sc
     const uint64_t ones = nset + a.m + npset, zeros = 4;
@@ -2155,8 +2197,19 @@ hipError_t launch_map(hipStream_t s, const MapArgs &a) {
         hipLaunchKernelGGL(k_map_rank_zero, dim3(blocks_for(std::max(a.m, std::min<uint64_t>(a.m * 256, 1ull << 22)))),
                            dim3(256), 0, s, a);
     } else {
-        if ((e = rocprim::radix_sort_keys(a.temp, tsort, a.tkeys, a.tkeys_sorted, a.m, 0, 64, s)) != hipSuccess)
-            return e;
+        // merge rounds for m keys; the tile sort's output buffer is chosen so
+        // that the last round writes tkeys_sorted
+        uint32_t rounds = 0;
+        for (uint64_t w = kSortTile; w < a.m; w *= 2) ++rounds;
+        uint64_t *buf[2] = {a.tkeys, a.tkeys_sorted};
+        uint32_t cur = (rounds & 1) ? 0 : 1;
+        hipLaunchKernelGGL(k_map_tile_sort, dim3((unsigned)((a.m + kSortTile - 1) / kSortTile)), dim3(256), 0, s, a,
+                           a.tkeys, buf[cur]);
+        const unsigned mblocks = blocks_for(std::min<uint64_t>(a.m, 1ull << 22));
+        for (uint64_t w = kSortTile; w < a.m; w *= 2) {
+            hipLaunchKernelGGL(k_map_merge, dim3(mblocks), dim3(256), 0, s, a, buf[cur], buf[cur ^ 1], w);
+            cur ^= 1;
+        }
         hipLaunchKernelGGL(k_map_zero, dim3(blocks_for(std::min<uint64_t>(a.m * 256, 1ull << 22))), dim3(256), 0, s, a);
     }
     hipLaunchKernelGGL(k_map_write, dim3(blocks_for(std::max(a.n, a.m))), dim3(256), 0, s, a);

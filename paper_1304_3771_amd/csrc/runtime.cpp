@@ -92,7 +92,6 @@ Workspace::~Workspace() {
         hipEventDestroy(map_ev);
     }
     hipFree(map_buf);
-    hipFree(map_temp);
     hipHostFree(map_pool_host);
 }
 
@@ -579,10 +578,25 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
     if (((uintptr_t)maps & 7) || ((uintptr_t)res & 7)) return dv_fail(-EINVAL, "maps and res must be 8-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     if (set_dev(c)) return -EIO;
-    // The pool: aligned, distinct frames.  For a memslot VM each must lie in a
-    // memslot, which gives its arena offset here; for a VM with an EPT the
-    // frames are translated on the device, through the EPT.
-    std::vector<uint64_t> hpa(n_pool);
+    std::vector<uint64_t> hpa;
+    int rc = dv_map_pool_check(c, asid, pool_gpa, n_pool, hpa);
+    if (rc) return rc;
+    const bool ept = asid < c->procs.size() && c->vms[c->procs[asid].vm].ept_root != ~0ull;
+    MapArgs a;
+    a.asid = asid;
+    a.ept_pool = ept ? 1 : 0;
+    a.ept_map = 0;
+    a.vm = 0;
+    return map_run(c, a, maps, n, pool_gpa, hpa, res, n_used, s);
+}
+
+// The pool of a guest-table map batch: aligned, distinct frames.  For a
+// memslot VM each must lie in a memslot, which gives its arena offset in hpa;
+// for a VM with an EPT the frames are translated on the device, through the
+// EPT (hpa holds zeros).
+int dv_map_pool_check(const devirt_ctx *c, uint32_t asid, const uint64_t *pool_gpa, uint64_t n_pool,
+                      std::vector<uint64_t> &hpa) {
+    hpa.assign(n_pool, 0);
     const bool ept = asid < c->procs.size() && c->vms[c->procs[asid].vm].ept_root != ~0ull;
     if (asid < c->procs.size() && n_pool) {
         // distinct: a strictly ascending pool (the usual case) needs no sort
@@ -618,12 +632,7 @@ extern "C" int devirt_map_pages(devirt_ctx *c, uint32_t asid, const devirt_map *
             hpa[k] = q->off + (g - q->gpa);
         }
     }
-    MapArgs a;
-    a.asid = asid;
-    a.ept_pool = ept ? 1 : 0;
-    a.ept_map = 0;
-    a.vm = 0;
-    return map_run(c, a, maps, n, pool_gpa, hpa, res, n_used, s);
+    return 0;
 }
 
 // The map launches of devirt_map_pages and devirt_ept_map_pages: workspace,
@@ -663,13 +672,6 @@ static int map_run(devirt_ctx *c, MapArgs &a, const devirt_map *maps, uint64_t n
     a.tkeys_sorted = b + T + m + P + 4;
     a.pool_gpa = b + T + 2 * m + P + 4;
     a.pool_hpa = b + T + 2 * m + P + 4 + n_pool;
-    a.temp = nullptr;
-    size_t need = 0;
-    a.temp_query = &need;
-    HIPCHK(launch_map(s, a));
-    if ((rc = grow(c, w, w->map_temp, w->map_temp_cap, std::max<uint64_t>(need, 256), "map scratch"))) return rc;
-    a.temp = w->map_temp;
-    a.temp_query = nullptr;
     if (n_pool) {
         // staged through pinned memory; the previous upload from it must be done
         if (w->map_ev) HIPCHK(hipEventSynchronize(w->map_ev));

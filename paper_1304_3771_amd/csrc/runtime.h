@@ -54,8 +54,6 @@ struct Workspace {
     // devirt_map_pages
     uint64_t *map_buf = nullptr;        // table-key set and lists, page set, scalars, pool
     uint64_t map_cap = 0;
-    uint8_t *map_temp = nullptr;        // radix-sort scratch (long key lists)
-    uint64_t map_temp_cap = 0;
     uint64_t *map_pool_host = nullptr;  // pinned staging of the pool (gpa, hpa)
     uint64_t map_pool_host_cap = 0;
     hipEvent_t map_ev = nullptr;        // the last pool upload
@@ -127,3 +125,7 @@ int dv_submit(devirt_ctx *c, const devirt_request *reqs, uint64_t n, const uint6
               devirt_result *res, devirt_fault *faults, uint64_t *n_faults, uint64_t *t_done, hipStream_t s,
               bool allow_graph, bool allow_direct = false);
 bool dv_in_server_thread();
+// Checks a guest-table map batch's pool (devirt_map_pages) and gives each
+// frame's arena offset (memslot VMs; zeros for a VM with an EPT).
+int dv_map_pool_check(const devirt_ctx *c, uint32_t asid, const uint64_t *pool_gpa, uint64_t n_pool,
+                      std::vector<uint64_t> &hpa);

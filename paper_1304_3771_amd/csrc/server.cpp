@@ -15,7 +15,12 @@
 //     are still running on the other streams (their work overlaps on the
 //     GPU);
 //   - finished batches are found by polling their events; their results
-//     become completions and their guest threads become ready again.
+//     become completions and their guest threads become ready again;
+//   - a guest thread may also queue a map batch (devirt_map_pages: the
+//     backend mapping pages into the process, section 4.2) between its
+//     copies.  It runs in the thread's order, once every batch already on the
+//     GPU has finished (a table write must not race a walk), and nothing is
+//     admitted while it waits or runs.
 // Page tables stay resident in the context throughout.
 #include <errno.h>
 #include <string.h>
@@ -25,6 +30,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -40,11 +46,28 @@ uint64_t now_ns() {
         .count();
 }
 
+// A map batch queued as an operation: its maps and results in pinned,
+// device-visible memory, the pool, and the caller's result array.
+struct MapJob {
+    uint32_t n = 0;
+    devirt_map *maps = nullptr;
+    devirt_result *res = nullptr;
+    uint64_t *used = nullptr;
+    std::vector<uint64_t> pool;
+    devirt_result *res_host = nullptr;
+    ~MapJob() {
+        hipHostFree(maps);
+        hipHostFree(res);
+        hipHostFree(used);
+    }
+};
+
 struct Op {
     uint64_t ticket;
-    devirt_request r;
+    devirt_request r;  // a map batch: asid and tag only (len 0)
     uint64_t t_submit;
     uint32_t th;  // index of its guest thread (set by the loop)
+    std::shared_ptr<MapJob> map;  // non-null: a map batch
 };
 
 // A guest thread (asid, tag): its waiting operations and whether one of its
@@ -159,6 +182,52 @@ static int launch_slot(devirt_server *s, Slot &sl) {
     return 0;
 }
 
+// Runs the map batch at the head of the ready queue (nothing is on the GPU):
+// devirt_map_pages on the first slot's stream, waited for; its completion
+// summarizes the maps (bytes_done = 4096 per map that succeeded; code, level
+// and fault_gva of the first that failed) and the caller's array receives
+// every map's result.
+static int run_map(devirt_server *s) {
+    const uint32_t ti = s->ready.front();
+    s->ready.pop_front();
+    GThread &g = s->threads[ti];
+    const Op op = g.q.front();
+    g.q.pop_front();
+    const uint64_t t_admit = now_ns();
+    MapJob &j = *op.map;
+    hipStream_t st = s->slots[0].stream;
+    int rc = devirt_map_pages(s->ctx, op.r.asid, j.maps, j.n, j.pool.empty() ? nullptr : j.pool.data(),
+                              j.pool.size(), j.res, j.used, st);
+    if (rc) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return dv_fail(-EIO, "server: map batch failed");
+    devirt_completion c;
+    memset(&c, 0, sizeof c);
+    c.ticket = op.ticket;
+    bool failed = false;
+    for (uint32_t i = 0; i < j.n; ++i) {
+        if (j.res[i].code == DEVIRT_OK) {
+            c.res.bytes_done += 4096;
+        } else if (!failed) {
+            failed = true;
+            c.res.code = j.res[i].code;
+            c.res.level = j.res[i].level;
+            c.res.fault_gva = j.res[i].fault_gva;
+        }
+    }
+    if (j.n) memcpy(j.res_host, j.res, (size_t)j.n * sizeof(devirt_result));
+    c.t_submit_ns = op.t_submit;
+    c.t_admit_ns = t_admit;
+    c.t_done_ns = now_ns();
+    if (!g.q.empty()) s->ready.push_back(ti);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->done.push_back(c);
+    }
+    s->completed += 1;
+    s->st_ops += 1;
+    return 0;
+}
+
 static void server_loop(devirt_server *s) {
     tl_server_thread = true;
     hipSetDevice(s->ctx->device);
@@ -256,6 +325,7 @@ static void server_loop(devirt_server *s) {
                 while (!s->ready.empty() && sl.ops.size() < max_batch && s->inflight_ops < s->cfg.max_inflight) {
                     GThread &g = s->threads[s->ready.front()];
                     const Op &op = g.q.front();
+                    if (op.map) break;  // a map batch runs alone (below)
                     if (s->inflight_ops > 0 && s->inflight_bytes + op.r.len > s->cfg.pool_bytes) break;
                     s->ready.pop_front();
                     sl.ops.push_back(op);
@@ -271,6 +341,19 @@ static void server_loop(devirt_server *s) {
                     s->err_msg = devirt_last_error();
                     s->err = rc;
                     break;
+                }
+                progress = true;
+            }
+        }
+        // a map batch at the head: once nothing is on the GPU
+        if (!s->err && !s->ready.empty() && s->threads[s->ready.front()].q.front().map) {
+            bool idle = true;
+            for (auto &sl : s->slots) idle = idle && !sl.busy;
+            if (idle) {
+                int rc = run_map(s);
+                if (rc) {
+                    s->err_msg = devirt_last_error();
+                    s->err = rc;
                 }
                 progress = true;
             }
@@ -383,11 +466,50 @@ extern "C" int devirt_server_submit(devirt_server *s, const devirt_request *reqs
     const size_t cap = 1u << 24;
     std::lock_guard<std::mutex> g(s->mu);
     uint32_t k = 0;
-    for (; k < n && s->inbox.size() < cap; ++k) s->inbox.push_back(Op{s->next_ticket++, reqs[k], t, 0});
+    for (; k < n && s->inbox.size() < cap; ++k) s->inbox.push_back(Op{s->next_ticket++, reqs[k], t, 0, nullptr});
     s->submitted += k;
     if (k) s->wake.notify_one();
     if (n_queued) *n_queued = k;
     if (k < n) return dv_fail(-EBUSY, "server inbox full");
+    return 0;
+}
+
+extern "C" int devirt_server_submit_map(devirt_server *s, uint32_t asid, uint32_t tag, const devirt_map *maps_host,
+                                        uint32_t n, const uint64_t *pool_gpa_host, uint32_t n_pool,
+                                        devirt_result *res_host, uint64_t *ticket) {
+    if (!s || (n && (!maps_host || !res_host)) || (n_pool && !pool_gpa_host)) return dv_fail(-EINVAL, "NULL argument");
+    if (n > dv::kMapMax) return dv_fail(-EINVAL, "at most %llu maps per call", (unsigned long long)dv::kMapMax);
+    if (s->err) return dv_fail(s->err, "server failed: %s", s->err_msg.c_str());
+    if (((uintptr_t)maps_host & 7) || ((uintptr_t)res_host & 7))
+        return dv_fail(-EINVAL, "maps and res must be 8-byte aligned");
+    {
+        // checked here, so that a bad pool is the caller's error, not the server's
+        std::vector<uint64_t> hpa;
+        int rc = dv_map_pool_check(s->ctx, asid, pool_gpa_host, n_pool, hpa);
+        if (rc) return rc;
+    }
+    auto j = std::make_shared<MapJob>();
+    j->n = n;
+    const size_t cnt = n ? n : 1;
+    if (hipHostMalloc((void **)&j->maps, cnt * sizeof(devirt_map), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&j->res, cnt * sizeof(devirt_result), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&j->used, sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        return dv_fail(-ENOMEM, "server: cannot allocate a map batch");
+    if (n) memcpy(j->maps, maps_host, (size_t)n * sizeof(devirt_map));
+    j->pool.assign(pool_gpa_host, pool_gpa_host + n_pool);
+    j->res_host = res_host;
+    devirt_request r;
+    memset(&r, 0, sizeof r);
+    r.asid = asid;
+    r.tag = tag;
+    const uint64_t t = now_ns();
+    std::lock_guard<std::mutex> g(s->mu);
+    if (ticket) *ticket = s->next_ticket;
+    s->inbox.push_back(Op{s->next_ticket++, r, t, 0, j});
+    s->submitted += 1;
+    s->wake.notify_one();
     return 0;
 }
 

@@ -133,6 +133,7 @@ _SIGS = {
     "devirt_reset_stats": ([vp]),
     "devirt_server_start": ([vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]),
     "devirt_server_submit": ([vp, vp, u32, ctypes.POINTER(u32)]),
+    "devirt_server_submit_map": ([vp, u32, u32, vp, u32, vp, u32, vp, ctypes.POINTER(u64)]),
     "devirt_server_poll": ([vp, vp, u32, ctypes.POINTER(u32)]),
     "devirt_server_drain": ([vp]),
     "devirt_server_stop": ([vp]),
@@ -376,6 +377,20 @@ class Context:
 class Server:
     def __init__(self, h):
         self._h = h
+        self._held = []  # result arrays of map batches, written at completion
+
+    def submit_map(self, asid: int, tag: int, maps: np.ndarray, pool_gpa) -> tuple:
+        """Queue a map batch for guest thread (asid, tag); returns its ticket
+        and the array that receives every map's result when it completes."""
+        m = np.ascontiguousarray(maps, dtype=MAP_DTYPE)
+        pool = np.ascontiguousarray(np.asarray(pool_gpa, dtype=np.uint64).reshape(-1))
+        res = np.zeros(max(len(m), 1), RESULT_DTYPE)
+        self._held.append(res)
+        t = u64()
+        _check("devirt_server_submit_map", lib().devirt_server_submit_map(
+            self._h, asid, tag, m.ctypes.data if len(m) else None, len(m), pool.ctypes.data if len(pool) else None,
+            len(pool), res.ctypes.data, ctypes.byref(t)))
+        return t.value, res[:len(m)]
 
     def submit(self, reqs: np.ndarray) -> int:
         r = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)

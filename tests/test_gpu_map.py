@@ -155,7 +155,7 @@ def test_map_matches_oracle(name):
 def test_map_large_batch(name, n_pool):
     """2^17 maps in one call, half into a 4 GiB region the tables do not cover
     yet, half onto mapped pages.  The small pool has the new tables ordered in
-    LDS tiles, the large one (over 2^14 frames) by the library radix sort."""
+    LDS tiles, the large one (over 2^14 frames) by LDS tiles and merge rounds."""
     w = wl(name)
     log(f"map large {name} pool {n_pool}")
     rng = np.random.default_rng(5)

@@ -196,3 +196,107 @@ def test_server_refuses_misuse(trace):
         ctx.vm_create(1 << 20)                     # usable again after stop
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("kind", ["memslots", "ept"])
+def test_map_batches_in_thread_order(kind):
+    """A guest thread's map batch (section 4.2: the backend maps pages into the
+    process between forwarded copies) runs in the thread's order: a copy into
+    a region nothing maps faults, the map batch maps it, and the next copies
+    into and out of it succeed.  Meanwhile the other threads' operations keep
+    arriving.  Every copy's result, every map's result, the map batch's
+    summary, guest memory and host bytes equal the oracle applied in
+    submission order."""
+    import torch
+    import pins
+    from oracle.oracle import MAP_DTYPE
+    sp = gen.spec("C4", n_vms=2, procs_per_vm=2, mem_bytes=256 * MiB, seed=48)
+    if kind == "ept":
+        sp = sp.replace(ept=True, ept_np=0.02, ept_ro=0.03, ept_mis=0.01)
+    wl = gen.make_workload(sp, requests=False)
+    tr = gen.make_serving_trace(wl, 1600, 2e5, threads_per_proc=8, window=2 * MiB, classes=CLASSES,
+                                host_mode="unique", seed=49)
+    p = wl.procs[1]
+    base = 0x7E00_0000_0000            # a region no VMA of the process covers
+    assert all(not (int(b) <= base < int(b) + int(s)) for b, s in p.vmas)
+    rng = np.random.default_rng(50)
+    fr = pins.usable_frames(wl, p.vm, pins.free_frames(wl, p.vm, 400, rng))
+    assert len(fr) >= 40
+    npg = 8
+    maps = np.zeros(npg + 1, MAP_DTYPE)
+    maps["gva"][:npg] = base + 4096 * np.arange(npg, dtype=np.uint64)
+    maps["gpa"][:npg] = fr[:npg]
+    maps["flags"][:npg] = 1                                   # writable
+    maps[npg] = (1 << 47, int(fr[npg]), 1, 0)   # non-canonical: fails
+    pool = [int(f) for f in fr[npg + 1:]]
+    # the thread's operations (a tag no trace thread has), host bytes after the trace's
+    extra = 64 << 10
+    h0 = tr.pool_bytes
+    mine = np.zeros(3, tr.requests.dtype)
+    mine["asid"], mine["tag"] = p.asid, 999
+    mine["gva"] = base + 100
+    mine["len"] = (12000, 20000, 20000)
+    mine["dir"] = (1, 1, 0)
+    mine["host"] = (h0, h0, h0 + 32768)
+    # submission order: trace[:a], mine[0], trace[a:b], the map, trace[b:c], mine[1:3], trace[c:]
+    n = len(tr.requests)
+    a, b, c = n // 4, n // 2, 3 * n // 4
+    hbytes = gen.fill_bytes(np.empty(tr.pool_bytes + extra, np.uint8), wl.seed, gen.POOL_KEY)
+    arenas = [wl.arena_image(v) for v in range(len(wl.vms))]
+    o = Oracle(arenas, [v.slots for v in wl.vms], [(q.vm, q.cr3, q.levels) for q in wl.procs], hbytes.copy(),
+               ept=[v.ept_root for v in wl.vms])
+    e = [o.batch(tr.requests[:a])[0], o.batch(mine[0:1])[0], o.batch(tr.requests[a:b])[0]]
+    em, eused = o.map_pages(p.asid, maps, pool)
+    e += [o.batch(tr.requests[b:c])[0], o.batch(mine[1:3])[0], o.batch(tr.requests[c:])[0]]
+    assert e[1]["code"][0] != 0 and np.all(e[4]["code"] == 0) and eused > 0
+    assert np.all(em["code"][:npg] == 0) and em["code"][npg] != 0
+    log(f"serving maps {kind}")
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, wl)
+        hb = torch.from_numpy(hbytes.copy()).cuda()
+        reqs = tr.requests.copy()
+        reqs["host"] += np.uint64(hb.data_ptr())
+        mreqs = mine.copy()
+        mreqs["host"] += np.uint64(hb.data_ptr())
+        srv = ctx.server_start(max_inflight=128, pool_bytes=4 * MiB, max_batch=32, streams=3)
+        comps = []
+        try:
+            import paper_1304_3771_amd as dv
+            with pytest.raises(dv.DevirtError):     # refused at submission, no ticket taken
+                srv.submit_map(p.asid, 999, maps, [pool[0] + 8])
+            for part in (reqs[:a], mreqs[0:1], reqs[a:b], None, reqs[b:c], mreqs[1:3], reqs[c:]):
+                if part is None:
+                    t_map, mres = srv.submit_map(p.asid, 999, maps, pool)
+                else:
+                    for k in range(0, len(part), 100):   # in bursts, completions taken between
+                        assert srv.submit(part[k:k + 100]) == len(part[k:k + 100])
+                        comps.append(srv.poll())
+            srv.drain()
+            comps.append(srv.poll(n + 8))
+        finally:
+            srv.stop()
+        got = np.concatenate(comps)
+        assert len(got) == n + 4 and np.array_equal(np.sort(got["ticket"]), np.arange(n + 4))
+        got = got[np.argsort(got["ticket"])]
+        garenas = device.read_arenas(ctx, dw)
+        ghost = hb.cpu().numpy()
+    finally:
+        ctx.close()
+    assert t_map == b + 1
+    # the results in submission order, the map batch's summary in its place
+    order = np.r_[0:a, a, a + 1:b + 1, b + 2:c + 2, c + 2, c + 3, c + 4:n + 4]
+    want = np.concatenate(e[:3] + e[3:])
+    for f in ("bytes_done", "fault_gva", "code", "level"):
+        assert np.array_equal(got[f][order], want[f]), f
+    s = got[t_map]
+    assert int(s["bytes_done"]) == 4096 * npg
+    assert (int(s["code"]), int(s["level"]), int(s["fault_gva"])) == \
+        (int(em["code"][npg]), int(em["level"][npg]), int(em["fault_gva"][npg]))
+    assert mres.tobytes() == em.tobytes()
+    for x, y in zip(garenas, o.arenas):
+        assert np.array_equal(x, y)
+    assert np.array_equal(ghost, o.pool)
+    # the thread's operations, the map batch included, ran one after another
+    mine_t = [a, t_map, c + 2, c + 3]
+    assert np.all(got["t_admit_ns"][mine_t[1:]] >= got["t_done_ns"][mine_t[:-1]])
