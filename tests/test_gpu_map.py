@@ -297,6 +297,48 @@ def test_map_full_size_c2():
         ctx.close()
 
 
+def test_map_scattered_many_tables():
+    """2^16 maps at random pages across 64 TiB of the address space: nearly
+    every map needs its own page table and page directory, so over 10^5 new
+    tables are ordered by LDS tiles and eight merge rounds.  With the pool
+    one short of that, nothing is written; with enough, results, frames used
+    and every arena byte equal the oracle."""
+    import torch
+    import os
+    import sys
+    import paper_1304_3771_amd as dv
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    log("map scattered: generating C2")
+    w = gen.make_workload(gen.spec("C2"), requests=False)
+    p = w.procs[0]
+    n = 1 << 16
+    rng = np.random.default_rng(23)
+    m = np.zeros(n, dv.MAP_DTYPE)
+    m["gva"] = (np.uint64(1 << 40) + (rng.integers(0, (1 << 46) >> 12, n).astype(np.uint64) << np.uint64(12)))
+    m["gpa"] = rng.integers(0, w.vms[p.vm].mem_bytes >> 12, n).astype(np.uint64) << np.uint64(12)
+    m["flags"] = rng.integers(0, 2, n)
+    free = bench.free_guest_frames(w, p.vm)
+    _, need = Oracle.from_workload(w).map_pages(0, m, free[:4 * n])
+    assert need > 100_000 and len(free) >= 4 * n
+    o = Oracle.from_workload(w)
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, w)
+        for pool in (free[:need - 1], free[:150_000]):
+            r, used = _gpu_map(ctx, 0, m, pool)
+            er, eused = o.map_pages(0, m, pool)
+            assert np.array_equal(r.view(np.uint8), er.view(np.uint8)), f"pool {len(pool)}: results differ"
+            assert used == eused == (need if len(pool) >= need else 0), (used, eused, need)
+        torch.cuda.synchronize()
+        a = device.read_arenas(ctx, dw)[0]
+        bad = np.count_nonzero(a != o.arenas[0])
+        assert bad == 0, f"{bad} arena bytes differ"
+        log(f"map scattered: bit-exact, {need} new tables")
+    finally:
+        ctx.close()
+
+
 # ------------------------------------------------------------- EPT maps --
 def _gpu_ept_map(ctx, vm, m, pool):
     """One devirt_ept_map_pages call; returns (results, pool pages used)."""
