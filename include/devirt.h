@@ -519,6 +519,15 @@ int devirt_server_submit(devirt_server *srv, const devirt_request *reqs_host, ui
 int devirt_server_submit_map(devirt_server *srv, uint32_t asid, uint32_t tag, const devirt_map *maps_host,
                              uint32_t n, const uint64_t *pool_gpa_host, uint32_t n_pool,
                              devirt_result *res_host, uint64_t *ticket);
+/* The same for an EPT map batch of VM vm (devirt_ept_map_pages: the mapping
+ * the hypervisor creates in the EPT, section 4.2), ordered as an operation of
+ * guest thread (asid, tag) and run alone in the same way.  The summary's
+ * fault_gva is the first failed map's guest-physical page.  An unknown VM, a
+ * VM without an EPT or a bad pool (unaligned, outside the arena, repeated) is
+ * refused here with -EINVAL. */
+int devirt_server_submit_ept_map(devirt_server *srv, uint32_t asid, uint32_t tag, uint32_t vm,
+                                 const devirt_ept_map *maps_host, uint32_t n, const uint64_t *pool_host,
+                                 uint32_t n_pool, devirt_result *res_host, uint64_t *ticket);
 /* Take up to max completions (any order); *n_out receives the count. */
 int devirt_server_poll(devirt_server *srv, devirt_completion *out, uint32_t max, uint32_t *n_out);
 /* Drain: wait until everything submitted has completed. */

@@ -694,6 +694,23 @@ static int map_run(devirt_ctx *c, MapArgs &a, const devirt_map *maps, uint64_t n
     return 0;
 }
 
+// The pool of an EPT map batch: a VM with an EPT, and aligned, distinct
+// arena pages inside its arena.
+int dv_ept_pool_check(const devirt_ctx *c, uint32_t vm, const uint64_t *pool_host, uint64_t n_pool) {
+    if (vm >= c->vms.size()) return dv_fail(-EINVAL, "no VM %u", vm);
+    const VmHost &v = c->vms[vm];
+    if (v.ept_root == ~0ull) return dv_fail(-EINVAL, "VM %u has no EPT", vm);
+    for (uint64_t k = 0; k < n_pool; ++k)
+        if ((pool_host[k] & 0xFFF) || pool_host[k] >= v.bytes || v.bytes - pool_host[k] < 4096)
+            return dv_fail(-EINVAL, "pool page %#llx is unaligned or outside the arena",
+                           (unsigned long long)pool_host[k]);
+    std::vector<uint64_t> sorted(pool_host, pool_host + n_pool);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return dv_fail(-EINVAL, "pool pages must be distinct");
+    return 0;
+}
+
 extern "C" int devirt_ept_map_pages(devirt_ctx *c, uint32_t vm, const devirt_ept_map *maps, uint64_t n,
                                     const uint64_t *pool_host, uint64_t n_pool, devirt_result *res,
                                     uint64_t *n_used, void *stream) {
@@ -706,15 +723,9 @@ extern "C" int devirt_ept_map_pages(devirt_ctx *c, uint32_t vm, const devirt_ept
     if (!n_used || (n && (!maps || !res)) || (n_pool && !pool_host)) return dv_fail(-EINVAL, "NULL argument");
     if (((uintptr_t)maps & 7) || ((uintptr_t)res & 7)) return dv_fail(-EINVAL, "maps and res must be 8-byte aligned");
     if (set_dev(c)) return -EIO;
-    // the pool: aligned, distinct arena pages inside the arena
+    int rc = dv_ept_pool_check(c, vm, pool_host, n_pool);
+    if (rc) return rc;
     std::vector<uint64_t> hpa(pool_host, pool_host + n_pool);
-    for (uint64_t k = 0; k < n_pool; ++k)
-        if ((hpa[k] & 0xFFF) || hpa[k] >= v.bytes || v.bytes - hpa[k] < 4096)
-            return dv_fail(-EINVAL, "pool page %#llx is unaligned or outside the arena", (unsigned long long)hpa[k]);
-    std::vector<uint64_t> sorted(hpa);
-    std::sort(sorted.begin(), sorted.end());
-    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
-        return dv_fail(-EINVAL, "pool pages must be distinct");
     static_assert(sizeof(devirt_ept_map) == sizeof(devirt_map), "one record layout for both kinds of map");
     MapArgs a;
     a.asid = 0;

@@ -129,3 +129,5 @@ bool dv_in_server_thread();
 // frame's arena offset (memslot VMs; zeros for a VM with an EPT).
 int dv_map_pool_check(const devirt_ctx *c, uint32_t asid, const uint64_t *pool_gpa, uint64_t n_pool,
                       std::vector<uint64_t> &hpa);
+// Checks an EPT map batch's VM and pool (devirt_ept_map_pages).
+int dv_ept_pool_check(const devirt_ctx *c, uint32_t vm, const uint64_t *pool_host, uint64_t n_pool);

@@ -47,9 +47,13 @@ uint64_t now_ns() {
 }
 
 // A map batch queued as an operation: its maps and results in pinned,
-// device-visible memory, the pool, and the caller's result array.
+// device-visible memory, the pool, and the caller's result array.  A guest
+// table batch (devirt_map_pages) or an EPT batch of VM `vm`
+// (devirt_ept_map_pages; its records have the same layout).
 struct MapJob {
     uint32_t n = 0;
+    bool ept = false;
+    uint32_t vm = 0;
     devirt_map *maps = nullptr;
     devirt_result *res = nullptr;
     uint64_t *used = nullptr;
@@ -183,10 +187,10 @@ static int launch_slot(devirt_server *s, Slot &sl) {
 }
 
 // Runs the map batch at the head of the ready queue (nothing is on the GPU):
-// devirt_map_pages on the first slot's stream, waited for; its completion
-// summarizes the maps (bytes_done = 4096 per map that succeeded; code, level
-// and fault_gva of the first that failed) and the caller's array receives
-// every map's result.
+// devirt_map_pages or devirt_ept_map_pages on the first slot's stream, waited
+// for; its completion summarizes the maps (bytes_done = 4096 per map that
+// succeeded; code, level and fault_gva of the first that failed) and the
+// caller's array receives every map's result.
 static int run_map(devirt_server *s) {
     const uint32_t ti = s->ready.front();
     s->ready.pop_front();
@@ -196,8 +200,10 @@ static int run_map(devirt_server *s) {
     const uint64_t t_admit = now_ns();
     MapJob &j = *op.map;
     hipStream_t st = s->slots[0].stream;
-    int rc = devirt_map_pages(s->ctx, op.r.asid, j.maps, j.n, j.pool.empty() ? nullptr : j.pool.data(),
-                              j.pool.size(), j.res, j.used, st);
+    const uint64_t *pool = j.pool.empty() ? nullptr : j.pool.data();
+    int rc = j.ept ? devirt_ept_map_pages(s->ctx, j.vm, (const devirt_ept_map *)j.maps, j.n, pool, j.pool.size(),
+                                          j.res, j.used, st)
+                   : devirt_map_pages(s->ctx, op.r.asid, j.maps, j.n, pool, j.pool.size(), j.res, j.used, st);
     if (rc) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) return dv_fail(-EIO, "server: map batch failed");
     devirt_completion c;
@@ -474,22 +480,28 @@ extern "C" int devirt_server_submit(devirt_server *s, const devirt_request *reqs
     return 0;
 }
 
-extern "C" int devirt_server_submit_map(devirt_server *s, uint32_t asid, uint32_t tag, const devirt_map *maps_host,
-                                        uint32_t n, const uint64_t *pool_gpa_host, uint32_t n_pool,
-                                        devirt_result *res_host, uint64_t *ticket) {
-    if (!s || (n && (!maps_host || !res_host)) || (n_pool && !pool_gpa_host)) return dv_fail(-EINVAL, "NULL argument");
+// Queues a map batch of either kind for guest thread (asid, tag).  The pool
+// is checked here, so that a bad pool is the caller's error, not the server's.
+static int submit_map_job(devirt_server *s, uint32_t asid, uint32_t tag, bool ept, uint32_t vm, const void *maps_host,
+                          uint32_t n, const uint64_t *pool_host, uint32_t n_pool, devirt_result *res_host,
+                          uint64_t *ticket) {
+    if (!s || (n && (!maps_host || !res_host)) || (n_pool && !pool_host)) return dv_fail(-EINVAL, "NULL argument");
     if (n > dv::kMapMax) return dv_fail(-EINVAL, "at most %llu maps per call", (unsigned long long)dv::kMapMax);
     if (s->err) return dv_fail(s->err, "server failed: %s", s->err_msg.c_str());
     if (((uintptr_t)maps_host & 7) || ((uintptr_t)res_host & 7))
         return dv_fail(-EINVAL, "maps and res must be 8-byte aligned");
-    {
-        // checked here, so that a bad pool is the caller's error, not the server's
+    if (ept) {
+        int rc = dv_ept_pool_check(s->ctx, vm, pool_host, n_pool);
+        if (rc) return rc;
+    } else {
         std::vector<uint64_t> hpa;
-        int rc = dv_map_pool_check(s->ctx, asid, pool_gpa_host, n_pool, hpa);
+        int rc = dv_map_pool_check(s->ctx, asid, pool_host, n_pool, hpa);
         if (rc) return rc;
     }
     auto j = std::make_shared<MapJob>();
     j->n = n;
+    j->ept = ept;
+    j->vm = vm;
     const size_t cnt = n ? n : 1;
     if (hipHostMalloc((void **)&j->maps, cnt * sizeof(devirt_map), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess ||
@@ -498,7 +510,7 @@ extern "C" int devirt_server_submit_map(devirt_server *s, uint32_t asid, uint32_
         hipHostMalloc((void **)&j->used, sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         return dv_fail(-ENOMEM, "server: cannot allocate a map batch");
     if (n) memcpy(j->maps, maps_host, (size_t)n * sizeof(devirt_map));
-    j->pool.assign(pool_gpa_host, pool_gpa_host + n_pool);
+    j->pool.assign(pool_host, pool_host + n_pool);
     j->res_host = res_host;
     devirt_request r;
     memset(&r, 0, sizeof r);
@@ -511,6 +523,18 @@ extern "C" int devirt_server_submit_map(devirt_server *s, uint32_t asid, uint32_
     s->submitted += 1;
     s->wake.notify_one();
     return 0;
+}
+
+extern "C" int devirt_server_submit_map(devirt_server *s, uint32_t asid, uint32_t tag, const devirt_map *maps_host,
+                                        uint32_t n, const uint64_t *pool_gpa_host, uint32_t n_pool,
+                                        devirt_result *res_host, uint64_t *ticket) {
+    return submit_map_job(s, asid, tag, false, 0, maps_host, n, pool_gpa_host, n_pool, res_host, ticket);
+}
+
+extern "C" int devirt_server_submit_ept_map(devirt_server *s, uint32_t asid, uint32_t tag, uint32_t vm,
+                                            const devirt_ept_map *maps_host, uint32_t n, const uint64_t *pool_host,
+                                            uint32_t n_pool, devirt_result *res_host, uint64_t *ticket) {
+    return submit_map_job(s, asid, tag, true, vm, maps_host, n, pool_host, n_pool, res_host, ticket);
 }
 
 extern "C" int devirt_server_poll(devirt_server *s, devirt_completion *out, uint32_t max, uint32_t *n_out) {

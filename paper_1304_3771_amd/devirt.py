@@ -134,6 +134,7 @@ _SIGS = {
     "devirt_server_start": ([vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]),
     "devirt_server_submit": ([vp, vp, u32, ctypes.POINTER(u32)]),
     "devirt_server_submit_map": ([vp, u32, u32, vp, u32, vp, u32, vp, ctypes.POINTER(u64)]),
+    "devirt_server_submit_ept_map": ([vp, u32, u32, u32, vp, u32, vp, u32, vp, ctypes.POINTER(u64)]),
     "devirt_server_poll": ([vp, vp, u32, ctypes.POINTER(u32)]),
     "devirt_server_drain": ([vp]),
     "devirt_server_stop": ([vp]),
@@ -390,6 +391,19 @@ class Server:
         _check("devirt_server_submit_map", lib().devirt_server_submit_map(
             self._h, asid, tag, m.ctypes.data if len(m) else None, len(m), pool.ctypes.data if len(pool) else None,
             len(pool), res.ctypes.data, ctypes.byref(t)))
+        return t.value, res[:len(m)]
+
+    def submit_ept_map(self, asid: int, tag: int, vm: int, maps: np.ndarray, pool) -> tuple:
+        """Queue an EPT map batch of VM vm, in guest thread (asid, tag)'s order;
+        returns its ticket and the array that receives every map's result."""
+        m = np.ascontiguousarray(maps, dtype=EPT_MAP_DTYPE)
+        pool = np.ascontiguousarray(np.asarray(pool, dtype=np.uint64).reshape(-1))
+        res = np.zeros(max(len(m), 1), RESULT_DTYPE)
+        self._held.append(res)
+        t = u64()
+        _check("devirt_server_submit_ept_map", lib().devirt_server_submit_ept_map(
+            self._h, asid, tag, vm, m.ctypes.data if len(m) else None, len(m),
+            pool.ctypes.data if len(pool) else None, len(pool), res.ctypes.data, ctypes.byref(t)))
         return t.value, res[:len(m)]
 
     def submit(self, reqs: np.ndarray) -> int:

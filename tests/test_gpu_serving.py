@@ -300,3 +300,127 @@ def test_map_batches_in_thread_order(kind):
     # the thread's operations, the map batch included, ran one after another
     mine_t = [a, t_map, c + 2, c + 3]
     assert np.all(got["t_admit_ns"][mine_t[1:]] >= got["t_done_ns"][mine_t[:-1]])
+
+
+def test_ept_map_batches_in_thread_order():
+    """Both halves of mapping a page in a VM with an EPT (section 4.2), as one
+    guest thread's operations in the serving loop: a copy into an unmapped
+    region faults in the guest's tables; a guest-table map batch points the
+    region at guest-physical pages far above guest memory; the next copy
+    faults in the EPT; an EPT map batch backs those pages with free arena
+    pages; the copies after it succeed.  Other threads' operations keep
+    arriving meanwhile.  Every result, both batches' summaries and per-map
+    results, guest memory and host bytes equal the oracle applied in
+    submission order."""
+    import torch
+    import pins
+    import paper_1304_3771_amd as dv
+    from oracle.oracle import EPT_MAP_DTYPE, MAP_DTYPE
+    sp = gen.spec("C4", n_vms=2, procs_per_vm=2, mem_bytes=256 * MiB, seed=52)
+    sp = sp.replace(ept=True, ept_np=0.02, ept_ro=0.03, ept_mis=0.01)
+    wl = gen.make_workload(sp, requests=False)
+    tr = gen.make_serving_trace(wl, 1600, 2e5, threads_per_proc=8, window=2 * MiB, classes=CLASSES,
+                                host_mode="unique", seed=53)
+    p = wl.procs[2]
+    v = wl.vms[p.vm]
+    base = 0x7E00_0000_0000
+    assert all(not (int(b) <= base < int(b) + int(s)) for b, s in p.vmas)
+    rng = np.random.default_rng(54)
+    fr = pins.usable_frames(wl, p.vm, pins.free_frames(wl, p.vm, 600, rng))
+    npg = 8
+    far = np.uint64(1 << 40) + np.uint64(4096) * np.arange(npg, dtype=np.uint64)
+    gmaps = np.zeros(npg, MAP_DTYPE)
+    gmaps["gva"] = base + 4096 * np.arange(npg, dtype=np.uint64)
+    gmaps["gpa"] = far
+    gmaps["flags"] = 1
+    gpool = [int(f) for f in fr[:200]]
+    emaps = np.zeros(npg + 1, EPT_MAP_DTYPE)
+    emaps["gpa"][:npg] = far
+    emaps["hpa"][:npg] = gen.gpa_to_arena(v.slots, fr[200:200 + npg])
+    emaps["flags"][:npg] = 7
+    emaps[npg] = (int(far[0]) + (1 << 48), int(emaps["hpa"][0]), 7, 0)   # past the EPT's reach: fails
+    epool = [int(x) for x in gen.gpa_to_arena(v.slots, fr[300:340])]
+    extra = 64 << 10
+    h0 = tr.pool_bytes
+    mine = np.zeros(4, tr.requests.dtype)
+    mine["asid"], mine["tag"] = p.asid, 999
+    mine["gva"] = base + 100
+    mine["len"] = (12000, 12000, 20000, 20000)
+    mine["dir"] = (1, 1, 1, 0)
+    mine["host"] = (h0, h0, h0, h0 + 32768)
+    n = len(tr.requests)
+    cut = [n // 5, 2 * n // 5, 3 * n // 5, 4 * n // 5]
+    hbytes = gen.fill_bytes(np.empty(tr.pool_bytes + extra, np.uint8), wl.seed, gen.POOL_KEY)
+    arenas = [wl.arena_image(k) for k in range(len(wl.vms))]
+    o = Oracle(arenas, [x.slots for x in wl.vms], [(q.vm, q.cr3, q.levels) for q in wl.procs], hbytes.copy(),
+               ept=[x.ept_root for x in wl.vms])
+    # submission order: T0 c0 T1 gmap T2 c1 T3 emap T4 c2 c3
+    R = tr.requests
+    want = [o.batch(R[:cut[0]])[0], o.batch(mine[0:1])[0], o.batch(R[cut[0]:cut[1]])[0]]
+    eg, egu = o.map_pages(p.asid, gmaps, gpool)
+    want += [o.batch(R[cut[1]:cut[2]])[0], o.batch(mine[1:2])[0], o.batch(R[cut[2]:cut[3]])[0]]
+    ee, eeu = o.ept_map_pages(p.vm, emaps, epool)
+    want += [o.batch(R[cut[3]:])[0], o.batch(mine[2:4])[0]]
+    assert want[1]["code"][0] != 0 and want[4]["code"][0] != 0 and np.all(want[7]["code"] == 0)
+    assert want[1]["code"][0] != want[4]["code"][0]          # a guest-table fault, then an EPT fault
+    assert np.all(eg["code"] == 0) and np.all(ee["code"][:npg] == 0) and ee["code"][npg] != 0 and eeu > 0
+    log("serving: guest-table and EPT maps in a thread's order")
+    ctx = new_ctx()
+    try:
+        dw = device.load(ctx, wl)
+        hb = torch.from_numpy(hbytes.copy()).cuda()
+        reqs = R.copy()
+        reqs["host"] += np.uint64(hb.data_ptr())
+        mreqs = mine.copy()
+        mreqs["host"] += np.uint64(hb.data_ptr())
+        srv = ctx.server_start(max_inflight=128, pool_bytes=4 * MiB, max_batch=32, streams=3)
+        comps = []
+        try:
+            with pytest.raises(dv.DevirtError):     # an unknown VM, refused at submission
+                srv.submit_ept_map(p.asid, 999, len(wl.vms), emaps, epool)
+            with pytest.raises(dv.DevirtError):     # a pool page outside the arena
+                srv.submit_ept_map(p.asid, 999, p.vm, emaps, [v.arena_bytes])
+            tick = {}
+            parts = [("T", reqs[:cut[0]]), ("C", mreqs[0:1]), ("T", reqs[cut[0]:cut[1]]), ("G", None),
+                     ("T", reqs[cut[1]:cut[2]]), ("C", mreqs[1:2]), ("T", reqs[cut[2]:cut[3]]), ("E", None),
+                     ("T", reqs[cut[3]:]), ("C", mreqs[2:4])]
+            for kind, part in parts:
+                if kind == "G":
+                    tick["g"], gres = srv.submit_map(p.asid, 999, gmaps, gpool)
+                elif kind == "E":
+                    tick["e"], eres = srv.submit_ept_map(p.asid, 999, p.vm, emaps, epool)
+                else:
+                    for k in range(0, len(part), 100):
+                        assert srv.submit(part[k:k + 100]) == len(part[k:k + 100])
+                        comps.append(srv.poll())
+            srv.drain()
+            comps.append(srv.poll(n + 8))
+        finally:
+            srv.stop()
+        got = np.concatenate(comps)
+        assert len(got) == n + 6 and np.array_equal(np.sort(got["ticket"]), np.arange(n + 6))
+        got = got[np.argsort(got["ticket"])]
+        garenas = device.read_arenas(ctx, dw)
+        ghost = hb.cpu().numpy()
+    finally:
+        ctx.close()
+    is_map = np.zeros(n + 6, bool)
+    is_map[[tick["g"], tick["e"]]] = True
+    w = np.concatenate(want)
+    for f in ("bytes_done", "fault_gva", "code", "level"):
+        assert np.array_equal(got[f][~is_map], w[f]), f
+    for t, er, res in ((tick["g"], eg, gres), (tick["e"], ee, eres)):
+        assert res.tobytes() == er.tobytes()
+        ok = er["code"] == 0
+        assert int(got["bytes_done"][t]) == 4096 * int(ok.sum())
+        first = np.nonzero(~ok)[0]
+        want_sum = (0, 0, 0) if not len(first) else \
+            (int(er["code"][first[0]]), int(er["level"][first[0]]), int(er["fault_gva"][first[0]]))
+        assert (int(got["code"][t]), int(got["level"][t]), int(got["fault_gva"][t])) == want_sum
+    for x, y in zip(garenas, o.arenas):
+        assert np.array_equal(x, y)
+    assert np.array_equal(ghost, o.pool)
+    mine_t = np.nonzero(np.concatenate([np.zeros(len(a), bool) if i not in (1, 4, 7) else np.ones(len(a), bool)
+                                        for i, a in enumerate(want)]))[0]
+    seq = sorted(list(np.nonzero(~is_map)[0][mine_t]) + [tick["g"], tick["e"]])
+    assert np.all(got["t_admit_ns"][seq[1:]] >= got["t_done_ns"][seq[:-1]])
