@@ -191,8 +191,29 @@ def parse_set(text: str) -> dict:
     return {k: int(v) for k, v in (kv.split("=") for kv in text.split(","))}
 
 
+SERVING_WORKLOAD = ("C4: 8 VMs x 4 GiB, 4 processes x 64 guest threads each, Poisson arrivals, "
+                    "60% 24B / 25% 4KiB / 14% 16-256KiB / 1% 4147200B")
+
+
 def serving(args):
     """C4: Poisson arrivals through the serving loop, one JSON line."""
+    out_rates = serving_rates(args, [float(x) for x in args.rates.split(",")], args.serve_plain_ops)
+    print(json.dumps({"metric": "serving p50/p99 latency and throughput, C4", "unit": "us", "n_gpus": 1,
+                      "data": "synthetic", "dtype": "u8", "config": serving_config(args), "rates": out_rates}))
+
+
+def serving_config(args):
+    return {"workload": SERVING_WORKLOAD, "max_inflight": args.max_inflight, "pool_gib": args.pool_gib,
+            "max_batch": args.max_batch, "streams": args.streams, "completion": args.completion,
+            "launch_config": args.set or "default"}
+
+
+def serving_rates(args, rates, plain_ops, seconds=None, min_ops=None):
+    """Each arrival rate's p50/p99 latency and throughput through the serving
+    loop on C4, over max(rate x seconds, min_ops) arrivals (and, for
+    plain_ops > 0, the per-request path at that rate)."""
+    seconds = args.serve_seconds if seconds is None else seconds
+    min_ops = args.serve_min_ops if min_ops is None else min_ops
     import torch
     import paper_1304_3771_amd as dv
     from workload import device, gen
@@ -205,11 +226,10 @@ def serving(args):
         ctx.set_config(**parse_set(args.set))
     dw = device.load(ctx, wl)
     log("serving: uploaded")
-    rates = [float(x) for x in args.rates.split(",")]
     out_rates = []
     pool = None
     for lam in rates:
-        n_ops = int(max(lam * args.serve_seconds, args.serve_min_ops))
+        n_ops = int(max(lam * seconds, min_ops))
         tr = gen.make_serving_trace(wl, n_ops, lam)
         if pool is None or pool.numel() < tr.pool_bytes:
             pool = torch.empty(tr.pool_bytes, dtype=torch.uint8, device="cuda")
@@ -271,7 +291,7 @@ def serving(args):
             f"{sst['ns_launch'] / 1e9:.3f} s ({sst['launches']} launches, {sst['direct_launches']} direct, "
             f"{sst['loops']} loops)")
         # the plain per-request path at the same arrival rate (bounded sample)
-        m = min(n_ops, args.serve_plain_ops)
+        m = min(n_ops, plain_ops)
         if m == 0:
             out_rates.append(rec)
             log(f"lambda {lam / 1e6:.2f} M/s: served p50 {rec['p50_us']:.0f} us p99 {rec['p99_us']:.0f} us "
@@ -300,14 +320,7 @@ def serving(args):
             f"{rec['per_request']['p50_us']:.0f} us p99 {rec['per_request']['p99_us']:.0f} us")
         out_rates.append(rec)
     ctx.close()
-    print(json.dumps({"metric": "serving p50/p99 latency and throughput, C4", "unit": "us", "n_gpus": 1,
-                      "data": "synthetic", "dtype": "u8",
-                      "config": {"workload": "C4: 8 VMs x 4 GiB, 4 processes x 64 guest threads each, Poisson "
-                                             "arrivals, 60% 24B / 25% 4KiB / 14% 16-256KiB / 1% 4147200B",
-                                 "max_inflight": args.max_inflight, "pool_gib": args.pool_gib,
-                                 "max_batch": args.max_batch, "streams": args.streams,
-                                 "completion": args.completion, "launch_config": args.set or "default"},
-                      "rates": out_rates}))
+    return out_rates
 
 
 def free_guest_frames(wl, vm):
@@ -689,6 +702,8 @@ def main():
     ap.add_argument("--profile-only", action="store_true", help="only run K timed steps (for rocprofv3)")
     ap.add_argument("--set", default="", help="launch config overrides, e.g. seg_chunks=64,nontemporal=1")
     ap.add_argument("--serving", action="store_true", help="run the C4 serving sweep instead")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave out the short C4 serving leg (1 and 5 M req/s) of the default C2 run")
     ap.add_argument("--map", action="store_true", help="time mapping pages (the guest-table writer) instead")
     ap.add_argument("--map-n", type=int, default=1 << 19, help="maps per call")
     ap.add_argument("--map-pool", type=int, default=4096, help="free guest frames handed to each call")
@@ -854,6 +869,12 @@ def main():
     for name in [x for x in extra_names.split(",") if x and x != args.workload]:
         extra[name] = extra_workload(name, args)
 
+    # ---- the serving loop on C4 at two arrival rates (the full sweep: --serving)
+    serve = None
+    if args.workload == "C2" and not args.no_serving and not args.profile_only:
+        serve = {"config": serving_config(args),
+                 "rates": serving_rates(args, [1e6, 5e6], 0, seconds=0.4, min_ops=200000)}
+
     out = {
         "metric": METRIC,
         "value": round(gbs, 2),
@@ -881,6 +902,7 @@ def main():
         "counters": counters,
         "cpu_baseline": cpu,
         "workloads": extra,
+        "serving": serve,
     }
     print(json.dumps(out))
 

@@ -66,19 +66,24 @@ struct MapJob {
     }
 };
 
+// An operation: plain data (64 bytes), copied without allocation on its way
+// from the inbox through its guest thread's FIFO into a launch.
+constexpr uint32_t kNoOp = ~0u;
 struct Op {
     uint64_t ticket;
     devirt_request r;  // a map batch: asid and tag only (len 0)
     uint64_t t_submit;
-    uint32_t th;  // index of its guest thread (set by the loop)
-    std::shared_ptr<MapJob> map;  // non-null: a map batch
+    uint32_t th;       // index of its guest thread (set by the loop)
+    uint32_t next;     // the next operation of its guest thread (op pool index)
+    MapJob *map;       // non-null: a map batch, owned by the operation until it runs
 };
 
-// A guest thread (asid, tag): its waiting operations and whether one of its
-// operations is in flight.
+// A guest thread (asid, tag): its waiting operations, a FIFO linked through
+// the op pool, and whether one of its operations is in flight.
 struct GThread {
-    std::deque<Op> q;
+    uint32_t head = kNoOp, tail = kNoOp;
     bool busy = false;
+    bool empty() const { return head == kNoOp; }
 };
 
 // A launch slot: its own stream and workspace, and pinned host buffers that
@@ -113,8 +118,9 @@ struct devirt_server {
     std::mutex mu;  // guards inbox and done
     std::condition_variable wake;  // submit or a finished batch -> sleeping loop
     std::atomic<uint32_t> done_bits{0};  // DEVIRT_SERVE_NOTIFY: slots whose batch finished
-    std::deque<Op> inbox;
-    std::deque<devirt_completion> done;
+    std::vector<Op> inbox;                // swapped out whole by the loop
+    std::vector<devirt_completion> done;  // completions [done_head, size) not yet polled
+    size_t done_head = 0;
     uint64_t next_ticket = 0;
     std::atomic<uint64_t> submitted{0}, completed{0};
 
@@ -122,6 +128,8 @@ struct devirt_server {
     // operation, at intake), indices of ready threads
     std::unordered_map<uint64_t, uint32_t> tindex;
     std::vector<GThread> threads;
+    std::vector<Op> ops;               // op pool: queued operations of every guest thread
+    std::vector<uint32_t> free_ops;    // unused op pool entries
     std::deque<uint32_t> ready;
     std::vector<devirt_completion> outbuf;
     uint64_t inflight_ops = 0, inflight_bytes = 0;
@@ -131,6 +139,33 @@ struct devirt_server {
     std::atomic<uint64_t> st_loops{0}, st_launches{0}, st_ops{0}, st_direct{0};
     std::atomic<uint64_t> ns_inbox{0}, ns_complete{0}, ns_admit{0}, ns_launch{0};
 };
+
+// The op pool (loop thread only): a guest thread's FIFO of queued operations.
+static void fifo_push(devirt_server *s, GThread &g, const Op &op) {
+    uint32_t i;
+    if (!s->free_ops.empty()) {
+        i = s->free_ops.back();
+        s->free_ops.pop_back();
+    } else {
+        i = (uint32_t)s->ops.size();
+        s->ops.emplace_back();
+    }
+    Op &o = s->ops[i];
+    o = op;
+    o.next = kNoOp;
+    if (g.tail == kNoOp)
+        g.head = i;
+    else
+        s->ops[g.tail].next = i;
+    g.tail = i;
+}
+static const Op &fifo_front(const devirt_server *s, const GThread &g) { return s->ops[g.head]; }
+static void fifo_pop(devirt_server *s, GThread &g) {
+    const uint32_t i = g.head;
+    g.head = s->ops[i].next;
+    if (g.head == kNoOp) g.tail = kNoOp;
+    s->free_ops.push_back(i);
+}
 
 static thread_local bool tl_server_thread = false;
 bool dv_in_server_thread() { return tl_server_thread; }
@@ -195,10 +230,11 @@ static int run_map(devirt_server *s) {
     const uint32_t ti = s->ready.front();
     s->ready.pop_front();
     GThread &g = s->threads[ti];
-    const Op op = g.q.front();
-    g.q.pop_front();
+    const Op op = fifo_front(s, g);
+    fifo_pop(s, g);
     const uint64_t t_admit = now_ns();
-    MapJob &j = *op.map;
+    std::unique_ptr<MapJob> owned(op.map);
+    MapJob &j = *owned;
     hipStream_t st = s->slots[0].stream;
     const uint64_t *pool = j.pool.empty() ? nullptr : j.pool.data();
     int rc = j.ept ? devirt_ept_map_pages(s->ctx, j.vm, (const devirt_ept_map *)j.maps, j.n, pool, j.pool.size(),
@@ -224,7 +260,7 @@ static int run_map(devirt_server *s) {
     c.t_submit_ns = op.t_submit;
     c.t_admit_ns = t_admit;
     c.t_done_ns = now_ns();
-    if (!g.q.empty()) s->ready.push_back(ti);
+    if (!g.empty()) s->ready.push_back(ti);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->done.push_back(c);
@@ -237,7 +273,8 @@ static int run_map(devirt_server *s) {
 static void server_loop(devirt_server *s) {
     tl_server_thread = true;
     hipSetDevice(s->ctx->device);
-    std::deque<Op> in;
+    std::vector<Op> in;
+    in.reserve(1 << 12);
     const uint32_t max_batch = s->cfg.max_batch ? s->cfg.max_batch : s->cfg.max_inflight;
     uint64_t taken = 0;  // operations moved out of the inbox so far
     for (;;) {
@@ -259,8 +296,8 @@ static void server_loop(devirt_server *s) {
             }
             op.th = it->second;
             GThread &g = s->threads[op.th];
-            if (g.q.empty() && !g.busy) s->ready.push_back(op.th);
-            g.q.push_back(op);
+            if (g.empty() && !g.busy) s->ready.push_back(op.th);
+            fifo_push(s, g, op);
             progress = true;
         }
         in.clear();
@@ -305,7 +342,7 @@ static void server_loop(devirt_server *s) {
                 out[i].dev_end_ns = d1;
                 GThread &g = s->threads[op.th];
                 g.busy = false;
-                if (!g.q.empty()) s->ready.push_back(op.th);
+                if (!g.empty()) s->ready.push_back(op.th);
                 s->inflight_ops--;
                 s->inflight_bytes -= op.r.len;
             }
@@ -330,7 +367,7 @@ static void server_loop(devirt_server *s) {
                 const uint64_t t = now_ns();
                 while (!s->ready.empty() && sl.ops.size() < max_batch && s->inflight_ops < s->cfg.max_inflight) {
                     GThread &g = s->threads[s->ready.front()];
-                    const Op &op = g.q.front();
+                    const Op &op = fifo_front(s, g);
                     if (op.map) break;  // a map batch runs alone (below)
                     if (s->inflight_ops > 0 && s->inflight_bytes + op.r.len > s->cfg.pool_bytes) break;
                     s->ready.pop_front();
@@ -339,7 +376,7 @@ static void server_loop(devirt_server *s) {
                     s->inflight_ops++;
                     s->inflight_bytes += op.r.len;
                     g.busy = true;
-                    g.q.pop_front();
+                    fifo_pop(s, g);
                 }
                 if (sl.ops.empty()) break;
                 int rc = launch_slot(s, sl);
@@ -352,7 +389,7 @@ static void server_loop(devirt_server *s) {
             }
         }
         // a map batch at the head: once nothing is on the GPU
-        if (!s->err && !s->ready.empty() && s->threads[s->ready.front()].q.front().map) {
+        if (!s->err && !s->ready.empty() && fifo_front(s, s->threads[s->ready.front()]).map) {
             bool idle = true;
             for (auto &sl : s->slots) idle = idle && !sl.busy;
             if (idle) {
@@ -406,6 +443,10 @@ static void free_server(devirt_server *s) {
         }
     }
     if (s->t_ref) hipEventDestroy(s->t_ref);
+    // map batches that never ran (the server stopped on an error)
+    for (auto &op : s->inbox) delete op.map;
+    for (auto &g : s->threads)
+        for (uint32_t i = g.head; i != kNoOp; i = s->ops[i].next) delete s->ops[i].map;
     s->ctx->server = nullptr;
     delete s;
 }
@@ -425,6 +466,8 @@ extern "C" int devirt_server_start(devirt_ctx *c, const devirt_server_cfg *cfg, 
     s->cfg = *cfg;
     s->mode = mode;
     s->device_times = (cfg->flags & DEVIRT_SERVE_DEVICE_TIMES) != 0;
+    s->inbox.reserve(1 << 12);
+    s->ops.reserve(1 << 12);
     c->server = s;
     const uint32_t max_batch = cfg->max_batch ? cfg->max_batch : cfg->max_inflight;
     s->slots.resize(cfg->streams);  // never resized again: host functions keep slot addresses
@@ -471,8 +514,11 @@ extern "C" int devirt_server_submit(devirt_server *s, const devirt_request *reqs
     const uint64_t t = now_ns();
     const size_t cap = 1u << 24;
     std::lock_guard<std::mutex> g(s->mu);
-    uint32_t k = 0;
-    for (; k < n && s->inbox.size() < cap; ++k) s->inbox.push_back(Op{s->next_ticket++, reqs[k], t, 0, nullptr});
+    const size_t base = s->inbox.size();
+    const uint32_t k = (uint32_t)std::min<size_t>(n, cap - std::min(cap, base));
+    s->inbox.resize(base + k);
+    Op *o = s->inbox.data() + base;
+    for (uint32_t i = 0; i < k; ++i) o[i] = Op{s->next_ticket++, reqs[i], t, 0, kNoOp, nullptr};
     s->submitted += k;
     if (k) s->wake.notify_one();
     if (n_queued) *n_queued = k;
@@ -498,7 +544,7 @@ static int submit_map_job(devirt_server *s, uint32_t asid, uint32_t tag, bool ep
         int rc = dv_map_pool_check(s->ctx, asid, pool_host, n_pool, hpa);
         if (rc) return rc;
     }
-    auto j = std::make_shared<MapJob>();
+    std::unique_ptr<MapJob> j(new MapJob());
     j->n = n;
     j->ept = ept;
     j->vm = vm;
@@ -519,7 +565,7 @@ static int submit_map_job(devirt_server *s, uint32_t asid, uint32_t tag, bool ep
     const uint64_t t = now_ns();
     std::lock_guard<std::mutex> g(s->mu);
     if (ticket) *ticket = s->next_ticket;
-    s->inbox.push_back(Op{s->next_ticket++, r, t, 0, j});
+    s->inbox.push_back(Op{s->next_ticket++, r, t, 0, kNoOp, j.release()});
     s->submitted += 1;
     s->wake.notify_one();
     return 0;
@@ -540,10 +586,15 @@ extern "C" int devirt_server_submit_ept_map(devirt_server *s, uint32_t asid, uin
 extern "C" int devirt_server_poll(devirt_server *s, devirt_completion *out, uint32_t max, uint32_t *n_out) {
     if (!s || !n_out || (max && !out)) return dv_fail(-EINVAL, "NULL argument");
     std::lock_guard<std::mutex> g(s->mu);
-    uint32_t k = 0;
-    while (k < max && !s->done.empty()) {
-        out[k++] = s->done.front();
-        s->done.pop_front();
+    const uint32_t k = (uint32_t)std::min<size_t>(max, s->done.size() - s->done_head);
+    if (k) memcpy(out, s->done.data() + s->done_head, (size_t)k * sizeof(devirt_completion));
+    s->done_head += k;
+    if (s->done_head == s->done.size()) {
+        s->done.clear();
+        s->done_head = 0;
+    } else if (s->done_head >= (1u << 16) && 2 * s->done_head >= s->done.size()) {
+        s->done.erase(s->done.begin(), s->done.begin() + (ptrdiff_t)s->done_head);  // keep the buffer bounded
+        s->done_head = 0;
     }
     *n_out = k;
     if (k == 0 && s->err) return dv_fail(s->err, "server failed: %s", s->err_msg.c_str());

@@ -378,7 +378,7 @@ class Context:
 class Server:
     def __init__(self, h):
         self._h = h
-        self._held = []  # result arrays of map batches, written at completion
+        self._held = {}  # ticket -> result array of a map batch, written at completion
 
     def submit_map(self, asid: int, tag: int, maps: np.ndarray, pool_gpa) -> tuple:
         """Queue a map batch for guest thread (asid, tag); returns its ticket
@@ -386,11 +386,11 @@ class Server:
         m = np.ascontiguousarray(maps, dtype=MAP_DTYPE)
         pool = np.ascontiguousarray(np.asarray(pool_gpa, dtype=np.uint64).reshape(-1))
         res = np.zeros(max(len(m), 1), RESULT_DTYPE)
-        self._held.append(res)
         t = u64()
         _check("devirt_server_submit_map", lib().devirt_server_submit_map(
             self._h, asid, tag, m.ctypes.data if len(m) else None, len(m), pool.ctypes.data if len(pool) else None,
             len(pool), res.ctypes.data, ctypes.byref(t)))
+        self._held[t.value] = res
         return t.value, res[:len(m)]
 
     def submit_ept_map(self, asid: int, tag: int, vm: int, maps: np.ndarray, pool) -> tuple:
@@ -399,11 +399,11 @@ class Server:
         m = np.ascontiguousarray(maps, dtype=EPT_MAP_DTYPE)
         pool = np.ascontiguousarray(np.asarray(pool, dtype=np.uint64).reshape(-1))
         res = np.zeros(max(len(m), 1), RESULT_DTYPE)
-        self._held.append(res)
         t = u64()
         _check("devirt_server_submit_ept_map", lib().devirt_server_submit_ept_map(
             self._h, asid, tag, vm, m.ctypes.data if len(m) else None, len(m),
             pool.ctypes.data if len(pool) else None, len(pool), res.ctypes.data, ctypes.byref(t)))
+        self._held[t.value] = res
         return t.value, res[:len(m)]
 
     def submit(self, reqs: np.ndarray) -> int:
@@ -418,7 +418,11 @@ class Server:
             out = np.empty(max_n, COMPLETION_DTYPE)
         n = u32()
         _check("devirt_server_poll", lib().devirt_server_poll(self._h, out.ctypes.data, max_n, ctypes.byref(n)))
-        return out[:n.value].copy()
+        got = out[:n.value].copy()
+        if self._held:  # a map batch's results are written by the time it completes
+            for t in got["ticket"].tolist():
+                self._held.pop(t, None)
+        return got
 
     def drain(self):
         _check("devirt_server_drain", lib().devirt_server_drain(self._h))
