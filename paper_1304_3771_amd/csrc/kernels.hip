@@ -2046,6 +2046,7 @@ constexpr uint32_t kSortTile = 1024;
 __device__ __forceinline__ uint64_t sort_count(const MapArgs &a) { return a.sc[0] < a.m ? a.sc[0] : a.m; }
 
 __global__ void __launch_bounds__(256) k_map_tile_sort(const MapArgs a, const uint64_t *src, uint64_t *dst) {
+    static_assert(kSortTile % 256 == 0, "a tile is a whole number of keys per lane");
     __shared__ uint64_t tile[kSortTile];
     const uint64_t cnt = sort_count(a);
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
@@ -2053,12 +2054,25 @@ __global__ void __launch_bounds__(256) k_map_tile_sort(const MapArgs a, const ui
     const uint32_t len = (uint32_t)std::min<uint64_t>(kSortTile, cnt - base);
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) tile[i] = src[base + i];
     __syncthreads();  // src may be dst: every read of the tile is done
-    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-        const uint64_t key = tile[i];
-        uint32_t rank = 0;
-        for (uint32_t q = 0; q < len; ++q) rank += tile[q] < key;
-        dst[base + rank] = key;
+    // each lane ranks its kSortTile / 256 keys in one sweep of the tile; a
+    // lane past the tile's end ranks the largest key, and its rank is not used
+    constexpr uint32_t K = kSortTile / 256;
+    uint64_t key[K];
+    uint32_t rank[K];
+#pragma unroll
+    for (uint32_t j = 0; j < K; ++j) {
+        key[j] = ~0ull;
+        rank[j] = 0;
+        if (threadIdx.x + 256 * j < len) key[j] = tile[threadIdx.x + 256 * j];
     }
+    for (uint32_t q = 0; q < len; ++q) {
+        const uint64_t t = tile[q];
+#pragma unroll
+        for (uint32_t j = 0; j < K; ++j) rank[j] += t < key[j];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < K; ++j)
+        if (threadIdx.x + 256 * j < len) dst[base + rank[j]] = key[j];
 }
 
 // One merge round: runs of w keys (a power of two, at least kSortTile) are
