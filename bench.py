@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -80,10 +81,16 @@ def restore_tables(ctx, wl):
 
 
 def kernel_hash():
+    """Hash of the kernel source (kernels.hip, dv_internal.h) with comments and
+    blank lines removed: it changes when the compiled kernels can change."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "dv_internal.h"):
-        with open(os.path.join(ROOT, "paper_1304_3771_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1304_3771_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            line = line.split("//", 1)[0].rstrip()
+            if line:
+                h.update(line.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -1319,12 +1319,14 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 }
 
 // Spill pass of one epoch: the groups whose runs did not all fit the queues
-// while translation ran during an earlier epoch's copies.  Launched on the
-// copy stream after the epoch's copy, so every payload byte still moves in
-// epoch order.  Each group is translated again (same results: page tables
-// change only in A/D bits, which are OR-ed) and its wavefront copies every
-// run of it; runs the copy kernel already moved are moved again with the same
-// bytes, since nothing else in the epoch touches them (batch precondition).
+// while translation ran during an earlier epoch's copies.  Launched after the
+// previous epoch's copy and this epoch's translation, and before the next
+// epoch's copy, so that it runs beside the epoch's own copy: every payload
+// byte still moves in epoch order.  Each group is translated again (same
+// results: page tables change only in A/D bits, which are OR-ed) and its
+// wavefront copies every run of it; a run the copy kernel also moves gets the
+// same bytes twice, since nothing else in the epoch touches them (batch
+// precondition).
 __global__ void __launch_bounds__(256) k_spill(DView v, DBatch b, uint64_t r0, uint64_t r1, uint32_t epoch) {
     extern __shared__ uint8_t smem[];
     const int wave = threadIdx.x >> 6;

@@ -837,11 +837,37 @@ extern "C" int devirt_copy_to_guest(devirt_ctx *c, uint32_t asid, uint64_t gva, 
 // translate(e) waits for copy(e-2), the last user of its half.  Copies stay in
 // epoch order on `s`.
 //
-// Every payload byte moves on `s`, in epoch order: a translate launch that may
-// overlap an earlier epoch's copy (overlap on, e >= 1) copies nothing itself.
-// It gets no inline copies, and a group whose runs overflow its queue part
-// goes to the epoch's spill list; the spill pass runs on `s` right after the
-// epoch's copy.
+// Payload bytes move in epoch order: a translate launch that may overlap an
+// earlier epoch's copy (overlap on, e >= 1) copies nothing itself.  It gets no
+// inline copies, and a group whose runs overflow its queue part goes to the
+// epoch's spill list.  The spill pass of epoch e runs on the side stream after
+// copy(e-1) and before translate(e+1), so it overlaps copy(e), which moves
+// bytes of the same epoch (no conflicts; a run both move is moved twice with
+// the same bytes), and copy(e+1) waits for it through translate(e+1).
+// A small epoch gets smaller groups, so that it still spreads over about 4
+// wavefronts per CU (results do not depend on the group).
+static uint32_t epoch_group(const devirt_ctx *c, uint64_t n) {
+    const uint64_t spread = (n + 4ull * c->cus - 1) / (4ull * c->cus);
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(c->cfg.group, spread));
+}
+
+// The spill pass of epoch e (overlap on, e >= 1): the groups of the epoch
+// whose runs overflowed their queue part, translated again and copied.
+static hipError_t spill_pass(devirt_ctx *c, hipStream_t st, const DView &v, const DBatch &b, const Workspace *w,
+                             uint64_t half, const std::vector<uint64_t> &epochs, size_t e) {
+    const uint64_t r0 = epochs[e - 1], r1 = epochs[e];
+    if (r1 <= r0) return hipSuccess;
+    DBatch be = b;
+    be.segs = w->segs + (e & 1) * half;
+    be.shorts = w->shorts + (e & 1) * half;
+    be.part_cap = half / kQParts;
+    be.spill_mode = 1;
+    be.inline_bytes = 0;
+    be.group = epoch_group(c, r1 - r0);
+    return launch_spill(st, grid_for(c, (r1 - r0 + be.group - 1) / be.group, c->cfg.xlat_wg, c->cfg.xlat_wgs_per_cu),
+                        (int)c->cfg.xlat_wg, v, be, r0, r1, (uint32_t)e);
+}
+
 static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStream_t s) {
     DBatch b = make_batch(c, w);
     b.reqs = a.reqs;
@@ -869,7 +895,7 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
     if (overlap) {
         if (!w->side) HIPCHK(hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking));
         side = w->side;
-        while (w->events.size() < 2 * ne + 1) {
+        while (w->events.size() < 2 * ne + 2) {
             hipEvent_t e;
             HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             w->events.push_back(e);
@@ -891,13 +917,16 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
         if (be.spill_mode) be.inline_bytes = 0;
         hipEvent_t t_done = overlap ? w->events[2 * e] : nullptr;
         hipEvent_t c_done = overlap ? w->events[2 * e + 1] : nullptr;
+        if (overlap && e >= 2) {
+            // translate(e) reuses the queue half of copy(e-2); the spill pass of
+            // epoch e-1 runs after copy(e-2) and translate(e-1), ahead of
+            // translate(e), so copy(e) waits for it
+            HIPCHK(hipStreamWaitEvent(side, w->events[2 * (e - 2) + 1], 0));
+            HIPCHK(spill_pass(c, side, v, b, w, half, a.epochs, e - 1));
+        }
         if (r1 > r0) {
-            // A small epoch gets smaller groups, so that it still spreads over
-            // about 4 wavefronts per CU (results do not depend on the group).
-            const uint64_t spread = (r1 - r0 + 4ull * c->cus - 1) / (4ull * c->cus);
-            be.group = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(c->cfg.group, spread));
+            be.group = epoch_group(c, r1 - r0);
             const uint64_t groups = (r1 - r0 + be.group - 1) / be.group;
-            if (overlap && e >= 2) HIPCHK(hipStreamWaitEvent(side, w->events[2 * (e - 2) + 1], 0));
             ProfEv *pe;
             if ((rc = prof_begin(c, side, 1, &pe))) return rc;
             HIPCHK(launch_translate_groups(side, grid_for(c, groups, c->cfg.xlat_wg, c->cfg.xlat_wgs_per_cu),
@@ -915,20 +944,30 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
                                (uint32_t)e));
             if ((rc = prof_end(c, s, pe))) return rc;
         }
-        // the spill pass uses no queue: translate(e+2) need not wait for it
         if (overlap) HIPCHK(hipEventRecord(c_done, s));
-        if (r1 > r0 && be.spill_mode)
-            HIPCHK(launch_spill(s, grid_for(c, (r1 - r0 + be.group - 1) / be.group, c->cfg.xlat_wg,
-                                            c->cfg.xlat_wgs_per_cu),
-                                (int)c->cfg.xlat_wg, v, be, r0, r1, (uint32_t)e));
         r0 = r1;
+    }
+    // the last epoch's spill pass (epochs before it ran theirs ahead of a
+    // later translate): after copy(ne-2), under copy(ne-1)
+    if (overlap && ne >= 2) {
+        HIPCHK(hipStreamWaitEvent(side, w->events[2 * (ne - 2) + 1], 0));
+        HIPCHK(spill_pass(c, side, v, b, w, half, a.epochs, ne - 1));
     }
     // every translate launch is already joined into `s` through its copy's wait
     if (a.faults || a.n_faults) {
+        // Every result is final once the last translate launch is done: the
+        // copies move bytes only, and a spill pass writes the same results
+        // again.  With overlap the fault list is therefore built on the side
+        // stream under the last copy, and `s` joins it at the end.
+        const hipStream_t fs = overlap ? side : s;
         uint64_t tiles = (a.n + kFaultTile - 1) / kFaultTile;
-        HIPCHK(launch_fault_count(s, a.res, a.n, w->tiles));
-        HIPCHK(launch_fault_scan(s, w->tiles, tiles, a.n_faults));
-        if (a.faults) HIPCHK(launch_fault_scatter(s, a.res, a.n, w->tiles, a.faults));
+        HIPCHK(launch_fault_count(fs, a.res, a.n, w->tiles));
+        HIPCHK(launch_fault_scan(fs, w->tiles, tiles, a.n_faults));
+        if (a.faults) HIPCHK(launch_fault_scatter(fs, a.res, a.n, w->tiles, a.faults));
+    }
+    if (overlap) {  // `s` joins the side stream: the last spill pass and the fault list
+        HIPCHK(hipEventRecord(w->events[2 * ne + 1], side));
+        HIPCHK(hipStreamWaitEvent(s, w->events[2 * ne + 1], 0));
     }
     return 0;
 }
