@@ -436,6 +436,44 @@ def test_overflow_across_epochs(monkeypatch, overlap):
         assert st["spilled_groups"] == 0
 
 
+def test_spill_passes_with_empty_epochs(monkeypatch):
+    """The spill pass of an epoch runs on the translate stream, beside the
+    epoch's own copy and ahead of the next epoch's translation.  Empty epochs
+    (every boundary given twice, and an empty first and last epoch) leave
+    some epochs without a translation or copy of their own.  With a
+    64-segment queue, so that groups do spill, and overlap on: results,
+    faults, every arena and pool byte equal the oracle, with completion
+    times, with device counters showing spills, and over three graph replays
+    of the batch (the oracle applies it three times)."""
+    import dataclasses
+    from oracle import Oracle
+    monkeypatch.setenv("DEVIRT_SEG_CAP", "64")
+    w = wl("epochs")
+    ends = w.epoch_end.astype(np.uint64)
+    ep = np.concatenate([[0], np.repeat(ends, 2), [ends[-1]]]).astype(np.uint64)
+    w2 = dataclasses.replace(w, epoch_end=ep)
+    assert np.sum(np.diff(np.concatenate([[0], ep.astype(np.int64)])) == 0) >= len(ends) + 1
+    exp = oracle_batch(w)
+    cfg = dict(overlap=1, group=8)
+    assert compare("empty epochs", gpu_batch(w2, cfg=cfg), exp) == []
+    got = gpu_batch(w2, cfg=cfg, t_done=True)
+    assert compare("empty epochs t_done", got, exp) == []
+    assert np.all(got[4]["t_done"] > 0)
+    ctx = new_ctx(**cfg)
+    try:
+        ctx.set_profiling(True, counters=True)
+        got = gpu_batch(w2, ctx=ctx)
+        st = got[4]["stats"]
+    finally:
+        ctx.close()
+    assert compare("empty epochs counters", got, exp) == []
+    assert st["spilled_groups"] > 0, st
+    o = Oracle.from_workload(w)
+    for _ in range(3):
+        er, ef = o.batch(w.requests)
+    assert compare("empty epochs, 3 replays", gpu_batch(w2, cfg=cfg, repeat=3), (er, ef, o.arenas, o.pool)) == []
+
+
 def test_completion_times_and_repeat():
     w = wl("multi_vm")
     got = gpu_batch(w, t_done=True)
