@@ -1,6 +1,7 @@
 """Host-side logic of the benchmark (no GPU): its refusal of several GPUs,
 the free-frame finder against a brute-force set, the map batches it times
-(every map must succeed), and its workload names."""
+(every map must succeed), its workload names, and the kernel-source hash
+that ties the committed HBM counters to the kernels they were taken on."""
 import os
 import subprocess
 import sys
@@ -65,3 +66,32 @@ def test_bench_workloads_resolve():
         sp = bench.workload_spec(name)
         assert sp.n_requests > 0 and sp.levels in (3, 4, 5)
     assert bench.workload_spec("C2-EPT").ept and bench.workload_spec("C2-PAE").levels == 3
+
+
+def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
+    """The hash that ties committed HBM counters to the kernels changes with
+    the code but not with comments or blank lines."""
+    import shutil
+    import bench
+    src = os.path.join(ROOT, "paper_1304_3771_amd", "csrc")
+    dst = tmp_path / "paper_1304_3771_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for f in ("kernels.hip", "dv_internal.h"):
+        shutil.copy(os.path.join(src, f), dst / f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_hash()
+    with open(dst / "kernels.hip", "a") as f:
+        f.write("\n// a comment\n/* and a\n   block comment */\n\n")
+    assert bench.kernel_hash() == h0
+    with open(dst / "dv_internal.h", "a") as f:
+        f.write("\nconstexpr int kUnused = 1;\n")
+    assert bench.kernel_hash() != h0
+
+
+@pytest.mark.parametrize("workload", ["C2", "C3", "C5", "C2-EPT"])
+def test_committed_counters_match_the_kernels(workload):
+    """The committed rocprofv3 HBM counters of each workload's copy kernel were
+    taken on the current kernel source (else the bench reports no traffic)."""
+    import bench
+    t = bench.measured_traffic(workload)
+    assert t is not None and t > 0, f"profiles/copy_traffic_{workload}.json is stale or missing"
