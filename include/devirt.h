@@ -357,6 +357,12 @@ typedef struct {
                                  walked by the 4 wavefronts of a workgroup
                                  together; 0 (the default) = every request by
                                  one wavefront; else >= 64                         */
+    uint32_t spill_side;      /* with overlap: 1 (the default) = the spill pass of
+                                 epoch e (groups whose runs overflowed the queue)
+                                 and the fault list run on the translate stream,
+                                 beside copy(e) and ahead of translate(e+1); 0 =
+                                 on the copy stream, right after copy(e) and at
+                                 the end                                          */
 } devirt_config;
 
 int devirt_get_config(devirt_ctx *ctx, devirt_config *cfg);

@@ -53,6 +53,7 @@ static devirt_config default_config() {
     c.overlap = 1;
     c.fifo_entries = 0;
     c.large_pages = 0;
+    c.spill_side = 1;
     return c;
 }
 
@@ -68,6 +69,7 @@ static int check_config(const devirt_config &c) {
     if (c.overlap > 1) return dv_fail(-EINVAL, "overlap must be 0 or 1");
     if (c.fifo_entries > kFifoMax) return dv_fail(-EINVAL, "fifo_entries must be <= %u", kFifoMax);
     if (c.large_pages != 0 && c.large_pages < 64) return dv_fail(-EINVAL, "large_pages must be 0 or >= 64");
+    if (c.spill_side > 1) return dv_fail(-EINVAL, "spill_side must be 0 or 1");
     return 0;
 }
 
@@ -840,10 +842,14 @@ extern "C" int devirt_copy_to_guest(devirt_ctx *c, uint32_t asid, uint64_t gva, 
 // Payload bytes move in epoch order: a translate launch that may overlap an
 // earlier epoch's copy (overlap on, e >= 1) copies nothing itself.  It gets no
 // inline copies, and a group whose runs overflow its queue part goes to the
-// epoch's spill list.  The spill pass of epoch e runs on the side stream after
-// copy(e-1) and before translate(e+1), so it overlaps copy(e), which moves
-// bytes of the same epoch (no conflicts; a run both move is moved twice with
-// the same bytes), and copy(e+1) waits for it through translate(e+1).
+// epoch's spill list.  The spill pass of epoch e then runs either on the side
+// stream after copy(e-1) and before translate(e+1) (spill_side 1), so that it
+// overlaps copy(e), which moves bytes of the same epoch (no conflicts; a run
+// both move is moved twice with the same bytes), and copy(e+1) waits for it
+// through translate(e+1); or on `s` right after copy(e) (spill_side 0).  The
+// first keeps every copy launch right behind the previous one; the second
+// lets translate(e+1) start ahead of copy(e), which on long copies leaves the
+// copy more of the GPU.  The fault list follows the spill passes.
 // A small epoch gets smaller groups, so that it still spreads over about 4
 // wavefronts per CU (results do not depend on the group).
 static uint32_t epoch_group(const devirt_ctx *c, uint64_t n) {
@@ -891,6 +897,7 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
     }
     HIPCHK(launch_reset(s, b, (uint32_t)ne));
     const bool overlap = ne > 1 && c->cfg.overlap;
+    const bool spill_side = c->cfg.spill_side != 0;
     hipStream_t side = s;
     if (overlap) {
         if (!w->side) HIPCHK(hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking));
@@ -917,12 +924,12 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
         if (be.spill_mode) be.inline_bytes = 0;
         hipEvent_t t_done = overlap ? w->events[2 * e] : nullptr;
         hipEvent_t c_done = overlap ? w->events[2 * e + 1] : nullptr;
-        if (overlap && e >= 2) {
-            // translate(e) reuses the queue half of copy(e-2); the spill pass of
-            // epoch e-1 runs after copy(e-2) and translate(e-1), ahead of
-            // translate(e), so copy(e) waits for it
+        if (overlap && e >= 2 && (spill_side || r1 > r0)) {
+            // translate(e) reuses the queue half of copy(e-2); on the side
+            // stream the spill pass of epoch e-1 runs after copy(e-2) and
+            // translate(e-1), ahead of translate(e), so copy(e) waits for it
             HIPCHK(hipStreamWaitEvent(side, w->events[2 * (e - 2) + 1], 0));
-            HIPCHK(spill_pass(c, side, v, b, w, half, a.epochs, e - 1));
+            if (spill_side) HIPCHK(spill_pass(c, side, v, b, w, half, a.epochs, e - 1));
         }
         if (r1 > r0) {
             be.group = epoch_group(c, r1 - r0);
@@ -944,12 +951,14 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
                                (uint32_t)e));
             if ((rc = prof_end(c, s, pe))) return rc;
         }
+        // the spill pass uses no queue: translate(e+2) need not wait for it
         if (overlap) HIPCHK(hipEventRecord(c_done, s));
+        if (overlap && !spill_side && e >= 1) HIPCHK(spill_pass(c, s, v, b, w, half, a.epochs, e));
         r0 = r1;
     }
     // the last epoch's spill pass (epochs before it ran theirs ahead of a
     // later translate): after copy(ne-2), under copy(ne-1)
-    if (overlap && ne >= 2) {
+    if (overlap && spill_side) {
         HIPCHK(hipStreamWaitEvent(side, w->events[2 * (ne - 2) + 1], 0));
         HIPCHK(spill_pass(c, side, v, b, w, half, a.epochs, ne - 1));
     }
@@ -959,13 +968,13 @@ static int enqueue_batch(devirt_ctx *c, Workspace *w, const BatchArgs &a, hipStr
         // copies move bytes only, and a spill pass writes the same results
         // again.  With overlap the fault list is therefore built on the side
         // stream under the last copy, and `s` joins it at the end.
-        const hipStream_t fs = overlap ? side : s;
+        const hipStream_t fs = overlap && spill_side ? side : s;
         uint64_t tiles = (a.n + kFaultTile - 1) / kFaultTile;
         HIPCHK(launch_fault_count(fs, a.res, a.n, w->tiles));
         HIPCHK(launch_fault_scan(fs, w->tiles, tiles, a.n_faults));
         if (a.faults) HIPCHK(launch_fault_scatter(fs, a.res, a.n, w->tiles, a.faults));
     }
-    if (overlap) {  // `s` joins the side stream: the last spill pass and the fault list
+    if (overlap && spill_side) {  // `s` joins the side stream: the last spill pass and the fault list
         HIPCHK(hipEventRecord(w->events[2 * ne + 1], side));
         HIPCHK(hipStreamWaitEvent(s, w->events[2 * ne + 1], 0));
     }
@@ -1153,6 +1162,7 @@ extern "C" int devirt_autotune(devirt_ctx *c, const devirt_request *reqs, uint64
         {[](devirt_config &k, uint32_t v) { k.copy_wgs_per_cu = v; }, {4, 8, 16}},
         {[](devirt_config &k, uint32_t v) { k.seg_chunks = v; }, {1, 2, 4, 16, 64}},
         {[](devirt_config &k, uint32_t v) { k.large_pages = v; }, {0, 64, 128, 256, 1024}},
+        {[](devirt_config &k, uint32_t v) { k.spill_side = v; }, {1, 0}},
     };
     for (const auto &kn : knobs) {
         if (rc) break;
@@ -1206,6 +1216,7 @@ static const CfgField kCfgFields[] = {
     {"overlap", &devirt_config::overlap},
     {"fifo_entries", &devirt_config::fifo_entries},
     {"large_pages", &devirt_config::large_pages},
+    {"spill_side", &devirt_config::spill_side},
 };
 
 static std::string device_key(devirt_ctx *c) {

@@ -53,7 +53,7 @@ SERVE_DEVICE_TIMES = 0x100
 class Config(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "group", "seg_chunks", "xlat_wg", "xlat_wgs_per_cu", "copy_wg", "copy_wgs_per_cu", "nontemporal",
-        "inline_bytes", "use_graph", "overlap", "fifo_entries", "large_pages")]
+        "inline_bytes", "use_graph", "overlap", "fifo_entries", "large_pages", "spill_side")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -396,8 +396,8 @@ def _cross_epoch_reuse(w):
     return guest, host
 
 
-@pytest.mark.parametrize("overlap", [1, 0])
-def test_overflow_across_epochs(monkeypatch, overlap):
+@pytest.mark.parametrize("overlap,spill_side", [(1, 1), (1, 0), (0, 1)])
+def test_overflow_across_epochs(monkeypatch, overlap, spill_side):
     """Many epochs that reuse guest and host bytes, a segment queue of 64
     (one segment per queue part and half), inline copies of runs up to 256 B:
     with translation overlapped (the next epoch is translated while the
@@ -412,7 +412,7 @@ def test_overflow_across_epochs(monkeypatch, overlap):
     assert len(w.epoch_end) >= 8
     g, h = _cross_epoch_reuse(w)
     assert g > 0 and h > 0, (g, h)
-    cfg = dict(inline_bytes=256, overlap=overlap, group=8)
+    cfg = dict(inline_bytes=256, overlap=overlap, group=8, spill_side=spill_side)
     exp = oracle_batch(w)
     got = gpu_batch(w, cfg=cfg)
     assert compare(f"epochs overlap={overlap}", got, exp) == []
@@ -436,9 +436,11 @@ def test_overflow_across_epochs(monkeypatch, overlap):
         assert st["spilled_groups"] == 0
 
 
-def test_spill_passes_with_empty_epochs(monkeypatch):
+@pytest.mark.parametrize("spill_side", [1, 0])
+def test_spill_passes_with_empty_epochs(monkeypatch, spill_side):
     """The spill pass of an epoch runs on the translate stream, beside the
-    epoch's own copy and ahead of the next epoch's translation.  Empty epochs
+    epoch's own copy and ahead of the next epoch's translation (spill_side 1),
+    or on the copy stream right after the epoch's copy (0).  Empty epochs
     (every boundary given twice, and an empty first and last epoch) leave
     some epochs without a translation or copy of their own.  With a
     64-segment queue, so that groups do spill, and overlap on: results,
@@ -454,7 +456,7 @@ def test_spill_passes_with_empty_epochs(monkeypatch):
     w2 = dataclasses.replace(w, epoch_end=ep)
     assert np.sum(np.diff(np.concatenate([[0], ep.astype(np.int64)])) == 0) >= len(ends) + 1
     exp = oracle_batch(w)
-    cfg = dict(overlap=1, group=8)
+    cfg = dict(overlap=1, group=8, spill_side=spill_side)
     assert compare("empty epochs", gpu_batch(w2, cfg=cfg), exp) == []
     got = gpu_batch(w2, cfg=cfg, t_done=True)
     assert compare("empty epochs t_done", got, exp) == []
