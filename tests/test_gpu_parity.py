@@ -476,6 +476,39 @@ def test_spill_passes_with_empty_epochs(monkeypatch, spill_side):
     assert compare("empty epochs, 3 replays", gpu_batch(w2, cfg=cfg, repeat=3), (er, ef, o.arenas, o.pool)) == []
 
 
+def test_maximum_length_requests():
+    """Requests of the largest length a descriptor holds (2^32 - 1 bytes) in a
+    6 GiB guest with one fully mapped 4.8 GiB region: a read and a write of
+    the whole length at unaligned guest and host addresses, and a read that
+    runs off the mapped part of the region 2 GiB in, which copies exactly up
+    to its first unmapped page; each in its own epoch.  Results, faults,
+    every arena byte and every pool byte against the oracle, with the
+    benchmark's launch configuration and with the workgroup walk of large
+    requests."""
+    import dataclasses
+    GiB = 1 << 30
+    sp = gen.spec("C2").replace(name="maxlen", mem_bytes=6 * GiB, p_np=0.0, vmas_per_proc=1, mapped_frac=0.8,
+                                n_requests=16, seed=77)
+    w = gen.make_workload(sp)
+    p = w.procs[0]
+    b, z = (int(x) for x in p.vmas[0])
+    L = (1 << 32) - 1
+    assert z >= L + 8192
+    R = np.zeros(3, gen.REQ_DTYPE)
+    R[0] = (b + 123, 0, L, p.asid, 0, (0, 0, 0), 0)                     # guest -> host
+    R[1] = (b + 4096 + 77, L + 69, L, p.asid, 1, (0, 0, 0), 0)          # host -> guest
+    R[2] = (b + z - (2 << 30) + 9, 5, L, p.asid, 0, (0, 0, 0), 0)       # off the mapped part
+    w2 = dataclasses.replace(w, requests=R, epoch_end=np.array([1, 2, 3], np.uint64), pool_bytes=2 * L + 256,
+                             req_vma=None)
+    exp = oracle_batch(w2)
+    er = exp[0]
+    assert np.all(er["bytes_done"][:2] == L) and er["code"][2] != 0 and er["bytes_done"][2] > GiB
+    log(f"max length: {L} bytes; the third request stops after {int(er['bytes_done'][2])}")
+    for cfg in (dict(group=64, seg_chunks=1, xlat_wgs_per_cu=2, copy_wg=1024, copy_wgs_per_cu=16, overlap=1),
+                dict(large_pages=256, overlap=1)):
+        assert compare(f"max length {cfg}", gpu_batch(w2, cfg=cfg), exp) == []
+
+
 def test_completion_times_and_repeat():
     w = wl("multi_vm")
     got = gpu_batch(w, t_done=True)
