@@ -1370,14 +1370,24 @@ __global__ void __launch_bounds__(64) k_plain(DView v, DBatch b, devirt_request 
 }
 
 // translate-only: one lane per address
+// The translate-only kernel's record staging area: 64 records of 24 bytes per
+// wavefront, after the walk cache and its owner slots, 16-byte aligned.
+constexpr uint32_t kXlatStage = 64 * 24;
+__host__ __device__ constexpr size_t xlat_stage_off(uint32_t block) {
+    return ((size_t)(block / 64) * kCacheWays * (sizeof(CEnt) + sizeof(uint32_t)) + 15) & ~(size_t)15;
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_xlat(DView v, uint32_t asid,
                                                                                      const uint64_t *gvas, uint64_t n,
                                                uint32_t flags, devirt_xlat *out, DCounters *counters) {
-    extern __shared__ uint8_t smem[];
+    extern __shared__ __align__(16) uint8_t smem[];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     CEnt *cache = (CEnt *)smem + wave * kCacheWays;
     uint32_t *owner = (uint32_t *)((CEnt *)smem + (blockDim.x >> 6) * kCacheWays) + wave * kCacheWays;
+    // the wavefront's 64 records are staged here and written out as
+    // contiguous 16-byte chunks (a record is 24 bytes with sub-dword fields)
+    uint32_t *stage = (uint32_t *)(smem + xlat_stage_off(blockDim.x)) + wave * (kXlatStage / 4);
     if (lane < kCacheWays) cache[lane].key = ~0ull;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1543,7 +1553,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
                 }
             }
         }
-        if (in) gp<DV_GLOBAL devirt_xlat>(out)[i] = x;
+        // every lane stages its record (an idle lane's is never written out)
+        {
+            uint32_t *r = stage + 6 * lane;
+            *(uint64_t *)r = x.gpa;
+            *(uint64_t *)(r + 2) = x.hpa;
+            r[4] = x.code;
+            r[5] = (uint32_t)x.level | ((uint32_t)x.page_shift << 8) | ((uint32_t)x.vm << 16);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        {
+            const uint32_t valid = 24u * (uint32_t)(n - b0 < 64 ? n - b0 : 64);  // bytes of this round
+            uint8_t *dst = (uint8_t *)out + 24 * b0;
+#pragma unroll
+            for (uint32_t k = 0; k < 2; ++k) {
+                const uint32_t c = (uint32_t)lane + 64u * k;  // 16-byte chunk of the round
+                if (16u * c + 16u <= valid)
+                    *gp<g_u32x4_w4>(dst + 16 * c) = *(const u32x4 *)(stage + 4 * c);
+                else if (16u * c < valid)  // the last 8 bytes of an odd count
+                    *gp<g_u64>(dst + 16 * c) = *(const uint64_t *)(stage + 4 * c);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     if (counters) {
         GroupOut st = {0, hits, misses, 0, 0, atom, 0};
@@ -1672,7 +1705,8 @@ hipError_t launch_plain(hipStream_t s, DView v, DBatch b, devirt_request req, in
 
 hipError_t launch_xlat(hipStream_t s, int grid, int block, DView v, uint32_t asid, const uint64_t *gva, uint64_t n,
                        uint32_t flags, devirt_xlat *out, DCounters *counters) {
-    hipLaunchKernelGGL(k_xlat, dim3(grid), dim3(block), wave_lds(block), s, v, asid, gva, n, flags, out, counters);
+    hipLaunchKernelGGL(k_xlat, dim3(grid), dim3(block), xlat_stage_off(block) + (size_t)(block / 64) * kXlatStage, s, v,
+                       asid, gva, n, flags, out, counters);
     return hipGetLastError();
 }
 
