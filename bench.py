@@ -193,6 +193,50 @@ def cpu_baseline(wl, seconds, name, max_vms=8):
             "single_thread": one}
 
 
+def translate_rate(ctx, wl, n, reps=3):
+    """devirt_translate on n addresses of the first process (90% in its mapped
+    leaves, 10% anywhere in the user range), READ, no A/D: addresses per
+    microsecond (M/s), the median of reps timed calls after one untimed."""
+    import torch
+    rng = np.random.default_rng(7)
+    p0 = wl.procs[0]
+    k_map = int(n * 0.9)
+    sel = rng.integers(0, len(p0.leaf_va), k_map)
+    size = np.uint64(1) << (np.uint64(12) + np.uint64(9) * (p0.leaf_level[sel].astype(np.uint64) - np.uint64(1)))
+    g = p0.leaf_va[sel] + rng.integers(0, 1 << 62, k_map, dtype=np.uint64) % size
+    user_limit = {3: 1 << 32, 4: 1 << 47, 5: 1 << 56}[p0.levels]
+    g = np.concatenate([g, rng.integers(0, user_limit, n - k_map, dtype=np.uint64)])
+    rng.shuffle(g)
+    dg = torch.from_numpy(g.view(np.int64)).cuda()
+    xo = torch.empty(n * 24, dtype=torch.uint8, device="cuda")
+    ctx.translate(p0.asid, dg, n, 0, xo)
+    ctx.sync()
+    xt = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.translate(p0.asid, dg, n, 0, xo)
+        ctx.sync()
+        xt.append(time.perf_counter() - t0)
+    return n / float(np.median(xt)) / 1e6
+
+
+def translate_only(args):
+    """Only the translate-only rate of one workload, one JSON line."""
+    import paper_1304_3771_amd as dv
+    from workload import device, gen
+    wl = gen.make_workload(workload_spec(args.workload), requests=False)
+    ctx = dv.Context(0)
+    device.load(ctx, wl)
+    mreq = translate_rate(ctx, wl, args.xlat_n, reps=args.steps)
+    ctx.close()
+    log(f"translate: {mreq:.1f} Mreq/s")
+    print(json.dumps({"metric": "Mreq/s translated", "value": round(mreq, 1), "unit": "Mreq/s", "n_gpus": 1,
+                      "steps": args.steps, "data": "synthetic", "dtype": "int64",
+                      "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+                                 "addresses": args.xlat_n}}))
+
+
 def parse_set(text: str) -> dict:
     """Launch config overrides written as key=value,key=value."""
     return {k: int(v) for k, v in (kv.split("=") for kv in text.split(","))}
@@ -709,6 +753,8 @@ def main():
     ap.add_argument("--profile-only", action="store_true", help="only run K timed steps (for rocprofv3)")
     ap.add_argument("--set", default="", help="launch config overrides, e.g. seg_chunks=64,nontemporal=1")
     ap.add_argument("--serving", action="store_true", help="run the C4 serving sweep instead")
+    ap.add_argument("--translate-only", action="store_true",
+                    help="only the translate-only rate of the workload (devirt_translate, --xlat-n addresses)")
     ap.add_argument("--no-serving", action="store_true",
                     help="leave out the short C4 serving leg (1 and 5 M req/s) of the default C2 run")
     ap.add_argument("--map", action="store_true", help="time mapping pages (the guest-table writer) instead")
@@ -743,6 +789,8 @@ def main():
         return serving(args)
     if args.map:
         return map_bench(args)
+    if args.translate_only:
+        return translate_only(args)
 
     t_gen = time.time()
     sp = workload_spec(args.workload)
@@ -834,27 +882,7 @@ def main():
     fifo = fifo_leg(ctx, wl, args)
 
     # ---- translate-only rate (Mreq/s), READ, no A/D
-    rng = np.random.default_rng(7)
-    p0 = wl.procs[0]
-    k_map = int(args.xlat_n * 0.9)
-    sel = rng.integers(0, len(p0.leaf_va), k_map)
-    size = np.uint64(1) << (np.uint64(12) + np.uint64(9) * (p0.leaf_level[sel].astype(np.uint64) - np.uint64(1)))
-    g = p0.leaf_va[sel] + rng.integers(0, 1 << 62, k_map, dtype=np.uint64) % size
-    user_limit = {3: 1 << 32, 4: 1 << 47, 5: 1 << 56}[p0.levels]
-    g = np.concatenate([g, rng.integers(0, user_limit, args.xlat_n - k_map, dtype=np.uint64)])
-    rng.shuffle(g)
-    dg = torch.from_numpy(g.view(np.int64)).cuda()
-    xo = torch.empty(args.xlat_n * 24, dtype=torch.uint8, device="cuda")
-    ctx.translate(p0.asid, dg, args.xlat_n, 0, xo)
-    ctx.sync()
-    xt = []
-    for _ in range(3):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.translate(p0.asid, dg, args.xlat_n, 0, xo)
-        ctx.sync()
-        xt.append(time.perf_counter() - t0)
-    mreq = args.xlat_n / float(np.median(xt)) / 1e6
+    mreq = translate_rate(ctx, wl, args.xlat_n)
     log(f"translate: {mreq:.1f} Mreq/s")
 
     launch = ctx.get_config()

@@ -1386,7 +1386,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     CEnt *cache = (CEnt *)smem + wave * kCacheWays;
     uint32_t *owner = (uint32_t *)((CEnt *)smem + (blockDim.x >> 6) * kCacheWays) + wave * kCacheWays;
     // the wavefront's 64 records are staged here and written out as
-    // contiguous 16-byte chunks (a record is 24 bytes with sub-dword fields)
+    // contiguous 16-byte chunks (a record is 24 bytes with sub-dword fields),
+    // with non-temporal stores: nothing on the GPU reads them back soon
     uint32_t *stage = (uint32_t *)(smem + xlat_stage_off(blockDim.x)) + wave * (kXlatStage / 4);
     if (lane < kCacheWays) cache[lane].key = ~0ull;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1403,10 +1404,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     const bool set_ad = (flags & DEVIRT_XLAT_SET_AD) != 0;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     unsigned long long hits = 0, misses = 0, atom = 0;
-    for (uint64_t b0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; b0 < n; b0 += waves * 64) {
+    // the next round's addresses are loaded at the top of this round
+    const uint64_t first = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64;
+    uint64_t gva_next = first + lane < n ? gp<const g_u64>(gvas)[first + lane] : 0;
+    for (uint64_t b0 = first; b0 < n; b0 += waves * 64) {
         const uint64_t i = b0 + lane;
         const bool in = i < n;
-        const uint64_t gva = in ? gp<const g_u64>(gvas)[i] : 0;
+        const uint64_t gva = gva_next;
+        gva_next = i + waves * 64 < n ? gp<const g_u64>(gvas)[i + waves * 64] : 0;
         devirt_xlat x;
         x.gpa = 0;
         x.hpa = 0;
@@ -1570,9 +1575,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             for (uint32_t k = 0; k < 2; ++k) {
                 const uint32_t c = (uint32_t)lane + 64u * k;  // 16-byte chunk of the round
                 if (16u * c + 16u <= valid)
-                    *gp<g_u32x4_w4>(dst + 16 * c) = *(const u32x4 *)(stage + 4 * c);
+                    __builtin_nontemporal_store(*(const u32x4 *)(stage + 4 * c), gp<g_u32x4_w4>(dst + 16 * c));
                 else if (16u * c < valid)  // the last 8 bytes of an odd count
-                    *gp<g_u64>(dst + 16 * c) = *(const uint64_t *)(stage + 4 * c);
+                    __builtin_nontemporal_store(*(const uint64_t *)(stage + 4 * c), gp<g_u64>(dst + 16 * c));
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
