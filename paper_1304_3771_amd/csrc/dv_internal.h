@@ -39,6 +39,8 @@ struct DVm {
     uint32_t index_complete;
     uint32_t lds_base;  // kernels: this VM's first slot in the workgroup's LDS copy (kLdsNone: use HBM)
     uint64_t ept_root;  // arena offset of the EPT's level-4 table; kNoEpt: memslots translate
+    uint32_t lds_idx;   // kernels: this VM's 2 MiB index in LDS, in 32-bit words (kLdsNone: none)
+    uint32_t pad;
 };
 constexpr uint32_t kLdsNone = 0xFFFFFFFFu;
 constexpr uint64_t kNoEpt = ~0ull;

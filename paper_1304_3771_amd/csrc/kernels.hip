@@ -119,16 +119,42 @@ __shared__ uint32_t g_lds_off[kLdsVms + 1];
 
 // Fills the workgroup's copy with VM `one`'s slots only (at LDS slot 0);
 // entered by every thread.  Returns (uniformly) whether they are in LDS.
-__device__ bool lds_slots_load_one(const DView &V, uint32_t one) {
+// When it fits in the rest of the area, the VM's 2 MiB index follows, one
+// 32-bit word per block: a block inside one slot as (arena_off - gpa) / 4 KiB
+// << 2 | 2 (that difference must fit 30 signed bits), a block split between
+// slots as 1, a block without a slot as 0; *idx receives its first word, or
+// kLdsNone.
+__shared__ uint32_t g_lds_idx_bad;
+__device__ bool lds_slots_load_one(const DView &V, uint32_t one, uint32_t *idx) {
+    *idx = kLdsNone;
     if (one >= V.nvm) return false;
     typedef DV_GLOBAL DVm g_vm;
     typedef DV_GLOBAL DSlot g_slot;
     const g_vm *vm = gp<const g_vm>(V.vms) + one;
     const uint32_t ns = vm->nslots;
     if (ns > kLdsSlots || one > kLdsVms) return false;
-    if (threadIdx.x == 0) g_lds_off[one] = 0;
+    if (threadIdx.x == 0) {
+        g_lds_off[one] = 0;
+        g_lds_idx_bad = 0;
+    }
     for (uint32_t t = threadIdx.x; t < ns; t += blockDim.x) g_lds_slot[t] = gp<const g_slot>(vm->slots)[t];
+    const uint32_t w0 = ns * (uint32_t)(sizeof(DSlot) / 4), nblk = vm->index_len;
+    const bool fits = vm->ept_root == kNoEpt && nblk > 0 && w0 + nblk <= kLdsSlots * (uint32_t)(sizeof(DSlot) / 4);
+    if (fits) {
+        uint32_t *words = (uint32_t *)g_lds_slot + w0;
+        for (uint32_t b = threadIdx.x; b < nblk; b += blockDim.x) {
+            const uint64_t e = gp<const g_u64>(vm->index)[b];
+            uint32_t x = (uint32_t)(e & 1u);
+            if (e & 2) {
+                const int64_t dp = (int64_t)(e & ~0xFFFull) >> 12;
+                if (dp < -(1ll << 29) || dp >= (1ll << 29)) g_lds_idx_bad = 1;
+                x = ((uint32_t)(int32_t)dp << 2) | 2u;
+            }
+            words[b] = x;
+        }
+    }
     __syncthreads();
+    if (fits && !g_lds_idx_bad) *idx = w0;
     return true;
 }
 
@@ -174,6 +200,19 @@ __device__ __forceinline__ DVm load_vm(const DView &V, uint32_t vm, bool lds) {
 // GPA -> arena offset (section 4.2: the guest-physical address is turned into
 // the host address backing it, as KVM does with its memslots).
 __device__ __forceinline__ bool slot_lookup(const DVm &v, uint64_t gpa, uint64_t &hpa) {
+    if (v.lds_idx != kLdsNone) {  // the 2 MiB index in LDS: one read unless the block is split
+        const uint64_t blk = gpa >> 21;
+        if (blk < v.index_len) {
+            const uint32_t e = ((const uint32_t *)g_lds_slot)[v.lds_idx + blk];
+            if (e & 2) {
+                hpa = gpa + ((uint64_t)(int64_t)((int32_t)e >> 2) << 12);
+                return true;
+            }
+            if (!(e & 1)) return false;
+        } else if (v.index_complete) {
+            return false;
+        }
+    }
     if (v.lds_base != kLdsNone) {  // binary search of the LDS copy
         const DSlot *sl = g_lds_slot + v.lds_base;
         uint32_t lo = 0, hi = v.nslots;
@@ -1396,9 +1435,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     DProc p = {0, 0, 4};
     DVm vmv = {};
     vmv.lds_base = kLdsNone;
+    vmv.lds_idx = kLdsNone;
     if (valid_asid) p = gp<const DV_GLOBAL DProc>(v.procs)[asid];
-    const bool lds = valid_asid && lds_slots_load_one(v, p.vm);  // one process: its VM's slots only
-    if (valid_asid) vmv = load_vm(v, p.vm, lds);
+    uint32_t lds_idx = kLdsNone;
+    const bool lds = valid_asid && lds_slots_load_one(v, p.vm, &lds_idx);  // one process: its VM's slots only
+    if (valid_asid) {
+        vmv = load_vm(v, p.vm, lds);
+        vmv.lds_idx = lds_idx;
+    }
     const uint64_t lim = user_limit(p.levels);
     const bool write = (flags & DEVIRT_XLAT_WRITE) != 0;
     const bool set_ad = (flags & DEVIRT_XLAT_SET_AD) != 0;

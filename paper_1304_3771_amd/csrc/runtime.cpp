@@ -171,6 +171,7 @@ static int upload_vms(devirt_ctx *c) {
         h[i].nslots = v.nsorted;
         h[i].index_complete = v.index_complete;
         h[i].lds_base = kLdsNone;
+        h[i].lds_idx = kLdsNone;
         h[i].ept_root = v.ept_root;
     }
     if (c->vms.size() > c->d_vms_cap) {
