@@ -887,7 +887,7 @@ def main():
 
     launch = ctx.get_config()
     ctx.close()
-    del dw, res, faults, nf, flush, B, td, xo, dg, pres
+    del dw, res, faults, nf, flush, B, td, pres
     torch.cuda.empty_cache()
 
     # ---- CPU baseline: the oracle, one thread and N threads, on a bounded sample of the same workload
