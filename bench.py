@@ -767,7 +767,7 @@ def main():
     ap.add_argument("--max-inflight", type=int, default=8192)
     ap.add_argument("--pool-gib", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=4096)
-    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--streams", type=int, default=3)
     ap.add_argument("--completion", default="poll", choices=["poll", "notify", "blocking"],
                     help="how the serving loop learns that a batch finished")
     args = ap.parse_args()
