@@ -56,7 +56,9 @@ struct DView {
     const DProc *procs;
     uint32_t nvm;
     uint32_t nproc;
-    uint32_t lds;  // kernels: the VMs' memslots are in the workgroup's LDS (set by the kernel)
+    uint32_t lds;      // kernels: the VMs' memslots are in the workgroup's LDS (set by the kernel)
+    uint32_t lds_idx;  // kernels: first LDS word of VM lds_idx_vm's 2 MiB index (kLdsNone: none)
+    uint32_t lds_idx_vm;
     uint32_t pad;
 };
 

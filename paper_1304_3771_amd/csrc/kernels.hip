@@ -117,29 +117,16 @@ constexpr uint32_t kLdsVms = 64;
 __shared__ DSlot g_lds_slot[kLdsSlots];
 __shared__ uint32_t g_lds_off[kLdsVms + 1];
 
-// Fills the workgroup's copy with VM `one`'s slots only (at LDS slot 0);
-// entered by every thread.  Returns (uniformly) whether they are in LDS.
-// When it fits in the rest of the area, the VM's 2 MiB index follows, one
-// 32-bit word per block: a block inside one slot as (arena_off - gpa) / 4 KiB
-// << 2 | 2 (that difference must fit 30 signed bits), a block split between
-// slots as 1, a block without a slot as 0; *idx receives its first word, or
-// kLdsNone.
-__shared__ uint32_t g_lds_idx_bad;
-__device__ bool lds_slots_load_one(const DView &V, uint32_t one, uint32_t *idx) {
-    *idx = kLdsNone;
-    if (one >= V.nvm) return false;
-    typedef DV_GLOBAL DVm g_vm;
-    typedef DV_GLOBAL DSlot g_slot;
-    const g_vm *vm = gp<const g_vm>(V.vms) + one;
-    const uint32_t ns = vm->nslots;
-    if (ns > kLdsSlots || one > kLdsVms) return false;
-    if (threadIdx.x == 0) {
-        g_lds_off[one] = 0;
-        g_lds_idx_bad = 0;
-    }
-    for (uint32_t t = threadIdx.x; t < ns; t += blockDim.x) g_lds_slot[t] = gp<const g_slot>(vm->slots)[t];
-    const uint32_t w0 = ns * (uint32_t)(sizeof(DSlot) / 4), nblk = vm->index_len;
+// A VM's 2 MiB index in the LDS area after the slots (from word w0), when it
+// fits: one 32-bit word per block, a block inside one slot as (arena_off -
+// gpa) / 4 KiB << 2 | 2 (that difference must fit 30 signed bits), a block
+// split between slots as 1, a block without a slot as 0.  Entered by every
+// thread; ends with a barrier.  Returns (uniformly) w0, or kLdsNone.
+typedef DV_GLOBAL DVm g_dvm;
+__device__ uint32_t lds_index_load(const g_dvm *vm, uint32_t w0) {
+    const uint32_t nblk = vm->index_len;
     const bool fits = vm->ept_root == kNoEpt && nblk > 0 && w0 + nblk <= kLdsSlots * (uint32_t)(sizeof(DSlot) / 4);
+    int bad = 0;
     if (fits) {
         uint32_t *words = (uint32_t *)g_lds_slot + w0;
         for (uint32_t b = threadIdx.x; b < nblk; b += blockDim.x) {
@@ -147,14 +134,30 @@ __device__ bool lds_slots_load_one(const DView &V, uint32_t one, uint32_t *idx) 
             uint32_t x = (uint32_t)(e & 1u);
             if (e & 2) {
                 const int64_t dp = (int64_t)(e & ~0xFFFull) >> 12;
-                if (dp < -(1ll << 29) || dp >= (1ll << 29)) g_lds_idx_bad = 1;
+                if (dp < -(1ll << 29) || dp >= (1ll << 29)) bad = 1;
                 x = ((uint32_t)(int32_t)dp << 2) | 2u;
             }
             words[b] = x;
         }
     }
-    __syncthreads();
-    if (fits && !g_lds_idx_bad) *idx = w0;
+    bad = __syncthreads_or(bad);
+    return fits && !bad ? w0 : kLdsNone;
+}
+
+// Fills the workgroup's copy with VM `one`'s slots only (at LDS slot 0),
+// followed by its 2 MiB index when that fits (V.lds_idx, V.lds_idx_vm);
+// entered by every thread.  Returns (uniformly) whether the slots are in LDS.
+__device__ bool lds_slots_load_one(DView &V, uint32_t one) {
+    V.lds_idx = kLdsNone;
+    if (one >= V.nvm) return false;
+    typedef DV_GLOBAL DSlot g_slot;
+    const g_dvm *vm = gp<const g_dvm>(V.vms) + one;
+    const uint32_t ns = vm->nslots;
+    if (ns > kLdsSlots || one > kLdsVms) return false;
+    if (threadIdx.x == 0) g_lds_off[one] = 0;
+    for (uint32_t t = threadIdx.x; t < ns; t += blockDim.x) g_lds_slot[t] = gp<const g_slot>(vm->slots)[t];
+    V.lds_idx = lds_index_load(vm, ns * (uint32_t)(sizeof(DSlot) / 4));
+    V.lds_idx_vm = one;
     return true;
 }
 
@@ -194,6 +197,7 @@ __device__ bool lds_slots_load(const DView &V) {
 __device__ __forceinline__ DVm load_vm(const DView &V, uint32_t vm, bool lds) {
     DVm v = gp<const DV_GLOBAL DVm>(V.vms)[vm];
     v.lds_base = lds ? g_lds_off[vm] : kLdsNone;
+    v.lds_idx = lds && vm == V.lds_idx_vm ? V.lds_idx : kLdsNone;
     return v;
 }
 
@@ -1437,12 +1441,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     vmv.lds_base = kLdsNone;
     vmv.lds_idx = kLdsNone;
     if (valid_asid) p = gp<const DV_GLOBAL DProc>(v.procs)[asid];
-    uint32_t lds_idx = kLdsNone;
-    const bool lds = valid_asid && lds_slots_load_one(v, p.vm, &lds_idx);  // one process: its VM's slots only
-    if (valid_asid) {
-        vmv = load_vm(v, p.vm, lds);
-        vmv.lds_idx = lds_idx;
-    }
+    const bool lds = valid_asid && lds_slots_load_one(v, p.vm);  // one process: its VM's slots only
+    if (valid_asid) vmv = load_vm(v, p.vm, lds);
     const uint64_t lim = user_limit(p.levels);
     const bool write = (flags & DEVIRT_XLAT_WRITE) != 0;
     const bool set_ad = (flags & DEVIRT_XLAT_SET_AD) != 0;

@@ -389,6 +389,8 @@ DView view_of(const devirt_ctx *c) {
     v.nvm = (uint32_t)c->vms.size();
     v.nproc = (uint32_t)c->procs.size();
     v.lds = 0;
+    v.lds_idx = kLdsNone;
+    v.lds_idx_vm = kLdsNone;
     v.pad = 0;
     return v;
 }
