@@ -528,6 +528,9 @@ extern "C" int devirt_server_submit(devirt_server *s, const devirt_request *reqs
 
 // Queues a map batch of either kind for guest thread (asid, tag).  The pool
 // is checked here, so that a bad pool is the caller's error, not the server's.
+// Both kinds of map travel in the same buffer, copied as devirt_map records.
+static_assert(sizeof(devirt_ept_map) == sizeof(devirt_map), "one record size for both kinds of map");
+
 static int submit_map_job(devirt_server *s, uint32_t asid, uint32_t tag, bool ept, uint32_t vm, const void *maps_host,
                           uint32_t n, const uint64_t *pool_host, uint32_t n_pool, devirt_result *res_host,
                           uint64_t *ticket) {
