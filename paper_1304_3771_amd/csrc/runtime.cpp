@@ -1162,7 +1162,7 @@ extern "C" int devirt_autotune(devirt_ctx *c, const devirt_request *reqs, uint64
          {0, 1, 2}},
         {[](devirt_config &k, uint32_t v) { k.group = v; }, {8, 16, 32, 64}},
         {[](devirt_config &k, uint32_t v) { k.copy_wg = v; }, {256, 512, 1024}},
-        {[](devirt_config &k, uint32_t v) { k.copy_wgs_per_cu = v; }, {4, 8, 16}},
+        {[](devirt_config &k, uint32_t v) { k.copy_wgs_per_cu = v; }, {4, 8, 16, 32, 64}},
         {[](devirt_config &k, uint32_t v) { k.seg_chunks = v; }, {1, 2, 4, 16, 64}},
         {[](devirt_config &k, uint32_t v) { k.large_pages = v; }, {0, 64, 128, 256, 1024}},
         {[](devirt_config &k, uint32_t v) { k.spill_side = v; }, {1, 0}},
